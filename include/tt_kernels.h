@@ -1,0 +1,48 @@
+/*
+ * tt_kernels.h - the update's building blocks as separate C entry points.
+ *
+ * These expose, one at a time, the device kernels that tt_stream_push_slice
+ * chains together, so that each can be checked or reused on its own.  All
+ * pointers are HIP device pointers; `hip_stream` is a hipStream_t (NULL = the
+ * default stream).  Every call is stream-ordered and returns before the work
+ * completes.  Matrices are column-major (first index fastest).  Errors:
+ * TT_ERR_INVALID_ARG for null pointers or sizes out of range, TT_ERR_DEVICE if
+ * a launch fails.  The caller owns every buffer.
+ */
+#ifndef TT_KERNELS_H
+#define TT_KERNELS_H
+
+#include "tt_stream.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Pass 1 of an update (Eq. 5 for the cores k <= k*, contracted with the right
+ * interface first): Z = X B^T for the P x J slice unfolding X (element type
+ * x_dtype), B r x J FP32, Z P x r FP64.  1 <= r <= 64.  workspace must hold
+ * tt_kernel_pass1_workspace(P, r) bytes and be zero-filled before its first
+ * use; it is left zero-filled. */
+tt_status tt_kernel_pass1(const void* X, tt_dtype x_dtype, int64_t P, int64_t J, int32_t r,
+                          const float* B, double* Z, void* workspace, int32_t* nonfinite_flag,
+                          void* hip_stream);
+size_t tt_kernel_pass1_workspace(int64_t P, int64_t J, int32_t r);
+
+/* Pass 2 of an update (Eq. 5 for the cores k > k*, contracted with the left
+ * interface first): Y = A^T X, A P x r FP32, Y r x J FP64.  1 <= r <= 64. */
+tt_status tt_kernel_pass2(const void* X, tt_dtype x_dtype, int64_t P, int64_t J, int32_t r,
+                          const float* A, double* Y, int32_t* nonfinite_flag, void* hip_stream);
+
+/* Thin QR of an m x n FP64 matrix (m >= n >= 1) as used to re-orthogonalise a
+ * core (Algorithm 1): M = Q R, Q^T Q = I, diag(R) >= 0; a column whose
+ * remaining norm is <= 64 eps ||M||_F gets the identity reflector.  M, Q
+ * column-major with leading dimension m; R n x n (may be NULL).  workspace
+ * must hold m*n doubles (only used when the matrix exceeds the LDS). */
+tt_status tt_kernel_qr(int32_t m, int32_t n, const double* M, double* Q, double* R,
+                       double* workspace, void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TT_KERNELS_H */

@@ -1,0 +1,336 @@
+"""ctypes binding of the C ABI (include/tt_stream.h, include/tt_kernels.h).
+
+Argument marshalling only: every step of an update runs in the HIP library
+lib/libttstream.so.  Device memory and streams come from PyTorch (ROCm build):
+device tensors are passed by data_ptr() and streams by their hipStream_t.
+Loading fails loudly when the library has not been built; there is no CPU
+fallback.
+
+The functions named like the C entry points (tt_stream_create, ...) map one to
+one onto them; TTStream is a small convenience wrapper over the same calls.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import (POINTER, Structure, byref, c_char_p, c_double, c_float, c_int, c_int32, c_int64, c_size_t,
+                    c_uint32, c_uint64, c_void_p)
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "lib", "libttstream.so")
+
+TT_OK, TT_ERR_INVALID_ARG, TT_ERR_SHAPE, TT_ERR_RANK, TT_ERR_OOM = 0, 1, 2, 3, 4
+TT_ERR_DEVICE, TT_ERR_NONFINITE, TT_ERR_STATE, TT_ERR_UNSUPPORTED = 5, 6, 7, 8
+STATUS_NAMES = {0: "TT_OK", 1: "TT_ERR_INVALID_ARG", 2: "TT_ERR_SHAPE", 3: "TT_ERR_RANK", 4: "TT_ERR_OOM",
+                5: "TT_ERR_DEVICE", 6: "TT_ERR_NONFINITE", 7: "TT_ERR_STATE", 8: "TT_ERR_UNSUPPORTED"}
+TT_F64, TT_F32, TT_BF16 = 0, 1, 2
+TT_FLAG_SYNC_PUSH = 0x1
+TT_FLAG_NO_ORTHO = 0x2
+
+
+class TTError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class tt_allocator(Structure):
+    _fields_ = [("alloc", c_void_p), ("free", c_void_p), ("ctx", c_void_p)]
+
+
+class tt_stream_config(Structure):
+    _fields_ = [
+        ("n_slice_modes", c_int32),
+        ("mode_sizes", POINTER(c_int64)),
+        ("ranks", POINTER(c_int64)),
+        ("compute", c_int),
+        ("seed", c_uint64),
+        ("init_cores", POINTER(c_double)),
+        ("allocator", POINTER(tt_allocator)),
+        ("hip_stream", c_void_p),
+        ("keep_history", c_int32),
+        ("history_capacity", c_int64),
+        ("split_point", c_int32),
+        ("flags", c_uint32),
+    ]
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libttstream.so (raises if it is missing: build it first)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"HIP library not built: {path} (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    sv = c_void_p
+    proto = {
+        "tt_stream_create": (c_int, [POINTER(tt_stream_config), POINTER(c_void_p)]),
+        "tt_stream_push_slice": (c_int, [sv, sv, c_int, c_int]),
+        "tt_stream_reconstruct": (c_int, [sv, sv, c_int, c_int]),
+        "tt_stream_destroy": (c_int, [sv]),
+        "tt_stream_synchronize": (c_int, [sv]),
+        "tt_stream_time": (c_int, [sv, POINTER(c_int64)]),
+        "tt_stream_info": (c_int, [sv, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32), POINTER(c_int64)]),
+        "tt_stream_get_state": (c_int, [sv, POINTER(c_double), POINTER(c_double), POINTER(c_int64)]),
+        "tt_stream_set_state": (c_int, [sv, POINTER(c_double), POINTER(c_double), c_int64]),
+        "tt_stream_get_history": (c_int, [sv, POINTER(c_double), c_int64, POINTER(c_int64)]),
+        "tt_clamp_ranks": (c_int, [c_int32, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64)]),
+        "tt_stream_last_push_ms": (c_int, [sv, POINTER(c_float)]),
+        "tt_last_error_string": (c_char_p, []),
+        "tt_version": (c_char_p, []),
+        "tt_kernel_pass1": (c_int, [sv, c_int, c_int64, c_int64, c_int32, sv, sv, sv, sv, sv]),
+        "tt_kernel_pass1_workspace": (c_size_t, [c_int64, c_int64, c_int32]),
+        "tt_kernel_pass2": (c_int, [sv, c_int, c_int64, c_int64, c_int32, sv, sv, sv, sv]),
+        "tt_kernel_qr": (c_int, [c_int32, c_int32, sv, sv, sv, sv, sv]),
+    }
+    for name, (res, args) in proto.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != TT_OK:
+        raise TTError(status, where, load_library().tt_last_error_string().decode())
+
+
+def _i64(values: Sequence[int]):
+    arr = (c_int64 * len(values))(*[int(v) for v in values])
+    return arr
+
+
+# ------------------------------------------------------------- C-named calls
+def tt_clamp_ranks(modes: Sequence[int], ranks: Sequence[int]):
+    lib = load_library()
+    m = len(modes)
+    out = (c_int64 * m)()
+    _check(lib.tt_clamp_ranks(m, _i64(modes), _i64(ranks), out), "tt_clamp_ranks")
+    return [int(v) for v in out]
+
+
+def tt_stream_create(modes, ranks, *, init_cores: Optional[np.ndarray] = None, seed: int = 0,
+                     hip_stream: int = 0, keep_history: bool = False, history_capacity: int = 0,
+                     split_point: int = 0, flags: int = 0, compute: int = TT_F32):
+    lib = load_library()
+    m = len(modes)
+    cfg = tt_stream_config()
+    cfg.n_slice_modes = m
+    modes_a, ranks_a = _i64(modes), _i64(ranks)
+    cfg.mode_sizes = ctypes.cast(modes_a, POINTER(c_int64))
+    cfg.ranks = ctypes.cast(ranks_a, POINTER(c_int64))
+    cfg.compute = compute
+    cfg.seed = seed
+    init = None
+    if init_cores is not None:
+        init = np.ascontiguousarray(init_cores, dtype=np.float64)
+        cfg.init_cores = init.ctypes.data_as(POINTER(c_double))
+    cfg.hip_stream = hip_stream or None
+    cfg.keep_history = 1 if keep_history else 0
+    cfg.history_capacity = history_capacity
+    cfg.split_point = split_point
+    cfg.flags = flags
+    h = c_void_p()
+    _check(lib.tt_stream_create(byref(cfg), byref(h)), "tt_stream_create")
+    return h
+
+
+def tt_stream_push_slice(h, ptr: int, dtype: int, on_device: bool) -> int:
+    return load_library().tt_stream_push_slice(h, c_void_p(ptr), dtype, 1 if on_device else 0)
+
+
+def tt_stream_reconstruct(h, ptr: int, dtype: int, on_device: bool) -> int:
+    return load_library().tt_stream_reconstruct(h, c_void_p(ptr), dtype, 1 if on_device else 0)
+
+
+def tt_stream_destroy(h) -> int:
+    return load_library().tt_stream_destroy(h)
+
+
+def tt_stream_synchronize(h) -> int:
+    return load_library().tt_stream_synchronize(h)
+
+
+# ------------------------------------------------------------- wrapper
+_TORCH_DT = {}
+
+
+def _dtype_code_torch(t) -> int:
+    import torch
+    if not _TORCH_DT:
+        _TORCH_DT.update({torch.float64: TT_F64, torch.float32: TT_F32, torch.bfloat16: TT_BF16})
+    return _TORCH_DT[t.dtype]
+
+
+def _dtype_code_np(a: np.ndarray) -> int:
+    if a.dtype == np.float64:
+        return TT_F64
+    if a.dtype == np.float32:
+        return TT_F32
+    raise TypeError("host slices must be float64 or float32")
+
+
+class TTStream:
+    """One streaming TT decomposition on the current GPU.
+
+    modes: slice mode sizes I_1..I_m; ranks: feasible TT-ranks r_1..r_m.
+    init: optional (cores, g) in FP64 (cores[k] of shape (r_{k-1}, I_k, r_k)).
+    stream: torch.cuda.Stream (default: the current stream).
+    """
+
+    def __init__(self, modes, ranks, init=None, *, seed: int = 0, stream=None, keep_history: bool = False,
+                 history_capacity: int = 0, split_point: int = 0, sync_push: bool = False):
+        self.modes = tuple(int(v) for v in modes)
+        self.ranks = tuple(int(v) for v in ranks)
+        self.n = int(np.prod(self.modes))
+        flat = None
+        if init is not None:
+            cores, g = init
+            parts = [np.asarray(c, dtype=np.float64).reshape(-1, order="F") for c in cores]
+            parts.append(np.asarray(g, dtype=np.float64).reshape(-1))
+            flat = np.concatenate(parts)
+        self._stream = stream
+        sp = int(stream.cuda_stream) if stream is not None else self._current_stream_handle()
+        self._h = tt_stream_create(self.modes, self.ranks, init_cores=flat, seed=seed, hip_stream=sp,
+                                   keep_history=keep_history, history_capacity=history_capacity,
+                                   split_point=split_point, flags=TT_FLAG_SYNC_PUSH if sync_push else 0)
+        self._lib = load_library()
+
+    @staticmethod
+    def _current_stream_handle() -> int:
+        import torch
+        return int(torch.cuda.current_stream().cuda_stream)
+
+    # -- updates
+    def push(self, x) -> None:
+        """Push one slice: a torch CUDA tensor (any shape, numel = N, contiguous,
+        memory with i_1 fastest) or a numpy array (shape `modes`, or flat
+        with i_1 fastest)."""
+        if isinstance(x, np.ndarray):
+            flat = np.ascontiguousarray(x.reshape(-1, order="F") if x.ndim > 1 else x)
+            if flat.size != self.n:
+                raise ValueError("slice size mismatch")
+            st = tt_stream_push_slice(self._h, flat.ctypes.data, _dtype_code_np(flat), False)
+        else:
+            if not x.is_cuda or not x.is_contiguous() or x.numel() != self.n:
+                raise ValueError("device slice must be a contiguous CUDA tensor with N elements")
+            st = tt_stream_push_slice(self._h, x.data_ptr(), _dtype_code_torch(x), True)
+        _check(st, "tt_stream_push_slice")
+
+    def push_ptr(self, ptr: int, dtype: int) -> int:
+        """Push a device slice by raw pointer; returns the status code."""
+        return tt_stream_push_slice(self._h, ptr, dtype, True)
+
+    def synchronize(self) -> None:
+        _check(tt_stream_synchronize(self._h), "tt_stream_synchronize")
+
+    def synchronize_status(self) -> int:
+        return tt_stream_synchronize(self._h)
+
+    def time(self) -> int:
+        t = c_int64()
+        _check(self._lib.tt_stream_time(self._h, byref(t)), "tt_stream_time")
+        return int(t.value)
+
+    def info(self):
+        cl, rl, sp, db = c_int64(), c_int64(), c_int32(), c_int64()
+        _check(self._lib.tt_stream_info(self._h, byref(cl), byref(rl), byref(sp), byref(db)), "tt_stream_info")
+        return {"cores_len": cl.value, "r_last": rl.value, "split_point": sp.value, "device_bytes": db.value}
+
+    # -- outputs
+    def reconstruct(self, out=None, dtype: str = "float64"):
+        """Reconstruction M_t of the latest slice.  With out=None returns a
+        host numpy array of shape `modes`; with a CUDA tensor writes into it."""
+        if out is None:
+            arr = np.empty(self.n, dtype=np.float64 if dtype == "float64" else np.float32)
+            code = TT_F64 if arr.dtype == np.float64 else TT_F32
+            _check(tt_stream_reconstruct(self._h, arr.ctypes.data, code, False), "tt_stream_reconstruct")
+            return arr.reshape(self.modes, order="F")
+        _check(tt_stream_reconstruct(self._h, out.data_ptr(), _dtype_code_torch(out), True), "tt_stream_reconstruct")
+        return out
+
+    def get_state(self):
+        info = self.info()
+        cores = np.empty(info["cores_len"], dtype=np.float64)
+        g = np.empty(info["r_last"], dtype=np.float64)
+        t = c_int64()
+        _check(self._lib.tt_stream_get_state(self._h, cores.ctypes.data_as(POINTER(c_double)),
+                                             g.ctypes.data_as(POINTER(c_double)), byref(t)), "tt_stream_get_state")
+        r = (1,) + self.ranks
+        out, off = [], 0
+        for k, n in enumerate(self.modes):
+            sz = r[k] * n * r[k + 1]
+            out.append(cores[off:off + sz].reshape((r[k], n, r[k + 1]), order="F"))
+            off += sz
+        return out, g, int(t.value)
+
+    def set_state(self, cores, g, t: int = 0) -> None:
+        flat = np.concatenate([np.asarray(c, dtype=np.float64).reshape(-1, order="F") for c in cores])
+        gg = np.ascontiguousarray(g, dtype=np.float64)
+        _check(self._lib.tt_stream_set_state(self._h, flat.ctypes.data_as(POINTER(c_double)),
+                                             gg.ctypes.data_as(POINTER(c_double)), int(t)), "tt_stream_set_state")
+
+    def history(self, rows: int = 1 << 30) -> np.ndarray:
+        rl = self.info()["r_last"]
+        cap = min(rows, max(self.time(), 0))
+        out = np.empty((max(cap, 1), rl), dtype=np.float64)
+        got = c_int64()
+        _check(self._lib.tt_stream_get_history(self._h, out.ctypes.data_as(POINTER(c_double)), cap, byref(got)),
+               "tt_stream_get_history")
+        return out[: got.value]
+
+    def last_push_ms(self) -> float:
+        v = c_float()
+        _check(self._lib.tt_stream_last_push_ms(self._h, byref(v)), "tt_stream_last_push_ms")
+        return float(v.value)
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            _check(tt_stream_destroy(self._h), "tt_stream_destroy")
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------- kernel calls
+def tt_kernel_pass1(X, P: int, J: int, r: int, B, Z, workspace, flag, hip_stream: int = 0) -> int:
+    return load_library().tt_kernel_pass1(c_void_p(X.data_ptr()), _dtype_code_torch(X), P, J, r,
+                                          c_void_p(B.data_ptr()), c_void_p(Z.data_ptr()),
+                                          c_void_p(workspace.data_ptr()), c_void_p(flag.data_ptr()),
+                                          c_void_p(hip_stream or None))
+
+
+def tt_kernel_pass1_workspace(P: int, J: int, r: int) -> int:
+    return int(load_library().tt_kernel_pass1_workspace(P, J, r))
+
+
+def tt_kernel_pass2(X, P: int, J: int, r: int, A, Y, flag, hip_stream: int = 0) -> int:
+    return load_library().tt_kernel_pass2(c_void_p(X.data_ptr()), _dtype_code_torch(X), P, J, r,
+                                          c_void_p(A.data_ptr()), c_void_p(Y.data_ptr()),
+                                          c_void_p(flag.data_ptr()), c_void_p(hip_stream or None))
+
+
+def tt_kernel_qr(M, Q, R, workspace, hip_stream: int = 0) -> int:
+    m, n = M.shape[1], M.shape[0]   # M given as a (n, m) C-contiguous tensor = m x n column-major
+    return load_library().tt_kernel_qr(m, n, c_void_p(M.data_ptr()), c_void_p(Q.data_ptr()),
+                                       c_void_p(R.data_ptr()) if R is not None else None,
+                                       c_void_p(workspace.data_ptr()), c_void_p(hip_stream or None))

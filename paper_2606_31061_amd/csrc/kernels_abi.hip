@@ -1,0 +1,83 @@
+// C entry points of the individual update kernels (include/tt_kernels.h).
+#include "tt_internal.h"
+#include "tt_kernels.h"
+
+#include <string>
+
+namespace ttk {
+hipError_t qr64_setup(size_t lds_limit);
+hipError_t pass_setup();
+}  // namespace ttk
+
+
+namespace {
+
+tt_status kfail(tt_status st, const char* what, hipError_t e = hipSuccess) {
+  std::string msg = std::string("tt_kernel: ") + what;
+  if (e != hipSuccess) msg += std::string(": ") + hipGetErrorString(e);
+  return ttk::set_error(st, msg.c_str());
+}
+
+int pass1_chunks_for(int64_t P, int64_t J) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  const int tiles = ttk::pass1_tiles(P);
+  const int64_t pairs = (J + 1) / 2;
+  int64_t chunks = (cus + tiles - 1) / tiles;
+  if (chunks > pairs / 8) chunks = pairs / 8;
+  if (chunks < 1) chunks = 1;
+  return (int)chunks;
+}
+
+size_t lds_limit() {
+  int dev = 0, lds = 65536;
+  if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+  return (size_t)lds;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t tt_kernel_pass1_workspace(int64_t P, int64_t J, int32_t r) {
+  if (P < 1 || J < 1 || r < 1 || r > 64) return 0;
+  const int chunks = pass1_chunks_for(P, J);
+  const size_t ws = ttk::pass1_ws_floats(P, r, chunks) * sizeof(float);
+  return ((ws + 255) & ~size_t(255)) + sizeof(int) * (ttk::pass1_tiles(P) + 1);
+}
+
+tt_status tt_kernel_pass1(const void* X, tt_dtype x_dtype, int64_t P, int64_t J, int32_t r, const float* B, double* Z,
+                          void* workspace, int32_t* nonfinite_flag, void* hip_stream) {
+  if (!X || !B || !Z || !workspace || !nonfinite_flag) return kfail(TT_ERR_INVALID_ARG, "null");
+  if (P < 1 || J < 1 || r < 1 || r > 64) return kfail(TT_ERR_INVALID_ARG, "size");
+  if (ttk::pass_setup() != hipSuccess) return kfail(TT_ERR_DEVICE, "setup");
+  const int chunks = pass1_chunks_for(P, J);
+  const size_t ws = ttk::pass1_ws_floats(P, r, chunks) * sizeof(float);
+  float* wsp = static_cast<float*>(workspace);
+  int* cnt = reinterpret_cast<int*>(static_cast<char*>(workspace) + ((ws + 255) & ~size_t(255)));
+  hipError_t e = ttk::pass1(static_cast<hipStream_t>(hip_stream), X, x_dtype, P, J, r, B, Z, wsp, cnt,
+                            nonfinite_flag, chunks, 8);
+  return e == hipSuccess ? TT_OK : kfail(TT_ERR_DEVICE, "pass1", e);
+}
+
+tt_status tt_kernel_pass2(const void* X, tt_dtype x_dtype, int64_t P, int64_t J, int32_t r, const float* A, double* Y,
+                          int32_t* nonfinite_flag, void* hip_stream) {
+  if (!X || !A || !Y || !nonfinite_flag) return kfail(TT_ERR_INVALID_ARG, "null");
+  if (P < 1 || J < 1 || r < 1 || r > 64) return kfail(TT_ERR_INVALID_ARG, "size");
+  if (ttk::pass_setup() != hipSuccess) return kfail(TT_ERR_DEVICE, "setup");
+  hipError_t e = ttk::pass2(static_cast<hipStream_t>(hip_stream), X, x_dtype, P, J, r, A, Y, nonfinite_flag);
+  return e == hipSuccess ? TT_OK : kfail(TT_ERR_DEVICE, "pass2", e);
+}
+
+tt_status tt_kernel_qr(int32_t m, int32_t n, const double* M, double* Q, double* R, double* workspace,
+                       void* hip_stream) {
+  if (!M || !Q || !workspace) return kfail(TT_ERR_INVALID_ARG, "null");
+  if (n < 1 || m < n) return kfail(TT_ERR_INVALID_ARG, "size");
+  const size_t lds = lds_limit();
+  if (ttk::qr64_setup(lds) != hipSuccess) return kfail(TT_ERR_DEVICE, "setup");
+  hipError_t e = ttk::qr64(static_cast<hipStream_t>(hip_stream), m, n, M, 1, m, Q, 1, m, R,
+                           64.0 * 2.220446049250313e-16, workspace, lds);
+  return e == hipSuccess ? TT_OK : kfail(TT_ERR_DEVICE, "qr", e);
+}
+
+}  // extern "C"

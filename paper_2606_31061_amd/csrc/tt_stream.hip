@@ -1,0 +1,634 @@
+// Host runtime of the C ABI declared in include/tt_stream.h.
+//
+// One handle holds one stream's state on one GPU: the committed FP64 cores
+// G_1..G_m and temporal vector g (the "master" state), plus the workspace of
+// one update.  A push launches the update as a fixed sequence of kernels on
+// the handle's HIP stream:
+//   right-orthogonalisation   normalise g, LQ sweep k = m..2 (Section 3.4.1)
+//   right interfaces          B_k = G_{k+1} x_3 B_{k+1}, k = m-1..k*
+//   pass 1                    Z = X^<k*> B_{k*}^T          (slice stream)
+//   head                      Z_k for k < k*; for k = 1..k*: G~_k = A_k^T Z_k,
+//                             thin QR, A_{k+1} = A_k x G_k  (Eq. 5 reassociated)
+//   pass 2                    Y = A_{k*+1}^T X^<k*>          (slice stream)
+//   tail                      for k = k*+1..m: G~_k = Y_k B_k^T, thin QR,
+//                             Y_{k+1} = G_k^T Y_k; g = Y_{m+1}
+//   commit                    if the slice was finite, new state -> master
+// Nothing is read back to the host during a push.
+#include "tt_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+namespace ttk {
+hipError_t qr64_setup(size_t lds_limit);
+hipError_t pass_setup();
+hipError_t to_f32(hipStream_t st, const double* src, float* dst, int64_t n);
+}  // namespace ttk
+
+namespace {
+
+constexpr uint64_t kMagic = 0x54545354524d3031ULL;  // "TTSTRM01"
+constexpr uint64_t kDead = 0xdeadbeefdeadbeefULL;
+constexpr double kQrTol = 64.0 * 2.220446049250313e-16;
+
+thread_local std::string g_last_error = "no error";
+
+tt_status fail(tt_status st, const std::string& msg) {
+  g_last_error = msg;
+  return st;
+}
+
+#define TT_HIP(call)                                                                            \
+  do {                                                                                          \
+    hipError_t e_ = (call);                                                                     \
+    if (e_ != hipSuccess)                                                                       \
+      return fail(TT_ERR_DEVICE, std::string(#call) + " failed: " + hipGetErrorString(e_));     \
+  } while (0)
+
+size_t dtype_size(tt_dtype d) { return d == TT_F64 ? 8 : d == TT_F32 ? 4 : 2; }
+
+bool mul_ok(int64_t a, int64_t b, int64_t* out) {
+  if (a <= 0 || b <= 0) return false;
+  if (a > INT64_MAX / b) return false;
+  *out = a * b;
+  return true;
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014) and the Box-Muller transform give the
+// optional seeded N(0,1) initial cores.
+uint64_t splitmix64(uint64_t& s) {
+  uint64_t z = (s += 0x9e3779b97f4a7c15ULL);
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+void normal_fill(std::vector<double>& v, uint64_t seed) {
+  uint64_t s = seed;
+  const double two_pi = 6.283185307179586476925286766559;
+  for (size_t i = 0; i < v.size(); i += 2) {
+    double u1 = ((splitmix64(s) >> 11) + 1.0) * (1.0 / 9007199254740993.0);  // (0,1]
+    double u2 = (splitmix64(s) >> 11) * (1.0 / 9007199254740992.0);
+    double rad = std::sqrt(-2.0 * std::log(u1));
+    v[i] = rad * std::cos(two_pi * u2);
+    if (i + 1 < v.size()) v[i + 1] = rad * std::sin(two_pi * u2);
+  }
+}
+
+}  // namespace
+
+tt_status ttk::set_error(tt_status st, const char* msg) { return fail(st, msg); }
+
+struct tt_stream {
+  uint64_t magic = kMagic;
+  int m = 0;
+  std::vector<int64_t> I;    // I[1..m] (I[0] unused)
+  std::vector<int64_t> r;    // r[0..m], r[0] = 1
+  std::vector<int64_t> Pk;   // Pk[k] = I_1..I_k, Pk[0] = 1
+  std::vector<int64_t> Jk;   // Jk[k] = I_{k+1}..I_m, Jk[m] = 1
+  std::vector<int64_t> coff; // offset of G_k in a state buffer; coff[m+1] = offset of g
+  int64_t N = 0, cores_len = 0, state_len = 0;
+  int kstar = 1;
+  tt_dtype compute = TT_F32;
+  uint32_t flags = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  tt_allocator alloc{};
+  bool has_alloc = false;
+  size_t lds_limit = 65536;
+  size_t device_bytes = 0;
+  std::vector<void*> owned;
+
+  double* master = nullptr;
+  double* work = nullptr;
+  double* fresh = nullptr;
+  double* Rbuf = nullptr;
+  std::vector<double*> B;    // B[k] for k = kstar..m-1
+  float* B32 = nullptr;
+  double* Z = nullptr;
+  std::vector<double*> Zk;   // Zk[k] for k = 1..kstar-1
+  std::vector<double*> A;    // A[k] for k = 3..kstar+1
+  float* A32 = nullptr;
+  double* Gt = nullptr;
+  double* Y[2] = {nullptr, nullptr};
+  double* qrwork = nullptr;
+  float* ws = nullptr;
+  int* cnt = nullptr;
+  int* flag = nullptr;
+  int* rejected = nullptr;
+  int64_t* tdev = nullptr;
+  double* hist = nullptr;
+  int64_t hist_cap = 0;
+  double* recon[2] = {nullptr, nullptr};
+  void* stage = nullptr;
+  size_t stage_bytes = 0;
+  int p1_chunks = 1, p1_waves = 8;
+  int rejected_seen = 0;
+  int64_t pushes = 0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr, evcopy = nullptr;
+  bool timed = false;
+
+  double* g_of(double* st) const { return st + coff[m + 1]; }
+  double* G_of(double* st, int k) const { return st + coff[k]; }
+};
+
+namespace {
+
+bool valid(const tt_stream* s) { return s != nullptr && s->magic == kMagic; }
+
+void* dev_alloc(tt_stream* s, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  bytes = (bytes + 255) & ~size_t(255);
+  void* p = nullptr;
+  if (s->has_alloc) {
+    p = s->alloc.alloc(bytes, s->alloc.ctx);
+  } else {
+    if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+  }
+  if (p) {
+    s->owned.push_back(p);
+    s->device_bytes += bytes;
+  }
+  return p;
+}
+
+void release(tt_stream* s) {
+  for (void* p : s->owned) {
+    if (s->has_alloc) s->alloc.free(p, s->alloc.ctx);
+    else (void)hipFree(p);
+  }
+  s->owned.clear();
+  if (s->ev0) (void)hipEventDestroy(s->ev0);
+  if (s->ev1) (void)hipEventDestroy(s->ev1);
+  if (s->evcopy) (void)hipEventDestroy(s->evcopy);
+}
+
+tt_status check_shape(int32_t m, const int64_t* modes, const int64_t* ranks) {
+  if (m < 1) return fail(TT_ERR_SHAPE, "n_slice_modes must be >= 1");
+  int64_t N = 1;
+  for (int k = 0; k < m; ++k) {
+    if (modes[k] < 1) return fail(TT_ERR_SHAPE, "mode sizes must be >= 1");
+    if (!mul_ok(N, modes[k], &N) || N > (int64_t(1) << 40)) return fail(TT_ERR_SHAPE, "slice size overflows");
+    if (ranks && ranks[k] < 1) return fail(TT_ERR_SHAPE, "ranks must be >= 1");
+  }
+  return TT_OK;
+}
+
+void clamp(int32_t m, const int64_t* modes, const int64_t* in, int64_t* out) {
+  std::vector<int64_t> r(m + 1);
+  r[0] = 1;
+  for (int k = 1; k <= m; ++k) r[k] = in[k - 1];
+  for (int k = 1; k <= m; ++k) {
+    int64_t cap;
+    if (!mul_ok(r[k - 1], modes[k - 1], &cap)) cap = INT64_MAX;
+    if (r[k] > cap) r[k] = cap;
+  }
+  for (int k = m; k >= 2; --k) {
+    int64_t cap;
+    if (!mul_ok(modes[k - 1], r[k], &cap)) cap = INT64_MAX;
+    if (r[k - 1] > cap) r[k - 1] = cap;
+  }
+  for (int k = 1; k <= m; ++k) out[k - 1] = r[k];
+}
+
+// Split point: the k in [1, m] that minimises the size of the two pass
+// outputs, P_k r_k + J_k r_k (pass 1 writes P_k x r_k, pass 2 writes
+// r_k x J_k, and the chain work on each side scales with them).
+int choose_split(const tt_stream* s) {
+  int best = 1;
+  double bestc = 1e300;
+  for (int k = 1; k <= s->m; ++k) {
+    if (s->r[k] > 64) continue;
+    const double c = (double)s->Pk[k] * s->r[k] + (double)s->Jk[k] * s->r[k];
+    if (c < bestc) {
+      bestc = c;
+      best = k;
+    }
+  }
+  return best;
+}
+
+tt_status launch_update(tt_stream* s, const void* X, tt_dtype xdt) {
+  hipStream_t st = s->stream;
+  const int m = s->m, ks = s->kstar;
+  const auto& I = s->I;
+  const auto& r = s->r;
+  const auto& Pk = s->Pk;
+  const auto& Jk = s->Jk;
+  const size_t lds = s->lds_limit;
+
+  // right-orthogonalisation: normalise g into the work state, then LQ sweep
+  TT_HIP(ttk::normalize_g(st, s->g_of(s->master), s->g_of(s->work), (int)r[m], s->G_of(s->master, m),
+                          s->G_of(s->work, m), r[m - 1] * I[m] * r[m]));
+  for (int k = m; k >= 2; --k) {
+    const int64_t rows = I[k] * r[k];
+    const int n = (int)r[k - 1];
+    double* Gk = s->G_of(s->work, k);
+    // LQ of the r_{k-1} x (I_k r_k) unfolding = QR of its transpose
+    TT_HIP(ttk::qr64(st, (int)rows, n, Gk, n, 1, Gk, n, 1, s->Rbuf, kQrTol, s->qrwork, lds));
+    // G_{k-1} <- G_{k-1} x_3 L with L = R^T
+    const int64_t rows2 = r[k - 2] * I[k - 1];
+    TT_HIP(ttk::gemm64(st, rows2, n, n, s->G_of(s->master, k - 1), 1, rows2, s->Rbuf, n, 1,
+                       s->G_of(s->work, k - 1), 1, rows2, nullptr));
+  }
+
+  // right interfaces B_k for k = m-1 .. kstar (B_m = g)
+  auto Bk = [&](int k) -> const double* { return k == m ? s->g_of(s->work) : s->B[k]; };
+  for (int k = m - 1; k >= ks; --k) {
+    const int64_t rows = r[k] * I[k + 1];
+    TT_HIP(ttk::gemm64(st, rows, Jk[k + 1], r[k + 1], s->G_of(s->work, k + 1), 1, rows, Bk(k + 1), 1, r[k + 1],
+                       s->B[k], 1, rows, k == ks ? s->B32 : nullptr));
+  }
+  if (ks == m) TT_HIP(ttk::to_f32(st, s->g_of(s->work), s->B32, r[m]));
+
+  // pass 1
+  TT_HIP(ttk::pass1(st, X, xdt, Pk[ks], Jk[ks], (int)r[ks], s->B32, s->Z, s->ws, s->cnt, s->flag, s->p1_chunks,
+                    s->p1_waves));
+
+  // head: Z_k for k < kstar from the pre-sweep cores
+  auto Zof = [&](int k) -> double* { return k == ks ? s->Z : s->Zk[k]; };
+  for (int k = ks - 1; k >= 1; --k) {
+    const int64_t Kd = I[k + 1] * r[k + 1];
+    TT_HIP(ttk::gemm64(st, Pk[k], r[k], Kd, Zof(k + 1), 1, Pk[k], s->G_of(s->work, k + 1), r[k], 1, Zof(k), 1,
+                       Pk[k], nullptr));
+  }
+  // forward sweep k = 1..kstar
+  for (int k = 1; k <= ks; ++k) {
+    const int64_t rows = r[k - 1] * I[k];
+    const int n = (int)r[k];
+    const double* Gt;
+    if (k == 1) {
+      Gt = Zof(1);
+    } else {
+      const double* Ak = (k == 2) ? s->G_of(s->fresh, 1) : s->A[k];
+      TT_HIP(ttk::gemm64(st, r[k - 1], I[k] * r[k], Pk[k - 1], Ak, Pk[k - 1], 1, Zof(k), 1, Pk[k - 1], s->Gt, 1,
+                         r[k - 1], nullptr));
+      Gt = s->Gt;
+    }
+    double* Gnew = s->G_of(s->fresh, k);
+    TT_HIP(ttk::qr64(st, (int)rows, n, Gt, 1, rows, Gnew, 1, rows, nullptr, kQrTol, s->qrwork, lds));
+    if (k >= 2) {
+      const double* Ak = (k == 2) ? s->G_of(s->fresh, 1) : s->A[k];
+      TT_HIP(ttk::gemm64(st, Pk[k - 1], I[k] * r[k], r[k - 1], Ak, 1, Pk[k - 1], Gnew, 1, r[k - 1], s->A[k + 1], 1,
+                         Pk[k - 1], k == ks ? s->A32 : nullptr));
+    } else if (ks == 1) {
+      TT_HIP(ttk::to_f32(st, Gnew, s->A32, Pk[1] * r[1]));
+    }
+  }
+
+  // pass 2
+  TT_HIP(ttk::pass2(st, X, xdt, Pk[ks], Jk[ks], (int)r[ks], s->A32, s->Y[0], s->flag));
+
+  // tail k = kstar+1 .. m
+  int cur = 0;
+  for (int k = ks + 1; k <= m; ++k) {
+    const int64_t rows = r[k - 1] * I[k];
+    const int n = (int)r[k];
+    TT_HIP(ttk::gemm64(st, rows, n, Jk[k], s->Y[cur], 1, rows, Bk(k), r[k], 1, s->Gt, 1, rows, nullptr));
+    double* Gnew = s->G_of(s->fresh, k);
+    TT_HIP(ttk::qr64(st, (int)rows, n, s->Gt, 1, rows, Gnew, 1, rows, nullptr, kQrTol, s->qrwork, lds));
+    double* dst = (k == m) ? s->g_of(s->fresh) : s->Y[cur ^ 1];
+    TT_HIP(ttk::gemm64(st, n, Jk[k], rows, Gnew, rows, 1, s->Y[cur], 1, rows, dst, 1, n, nullptr));
+    cur ^= 1;
+  }
+  if (ks == m) TT_HIP(ttk::copy64(st, s->g_of(s->fresh), s->Y[0], r[m]));
+
+  TT_HIP(ttk::commit(st, s->flag, s->fresh, s->master, s->state_len, s->g_of(s->fresh), (int)r[m], s->hist,
+                     s->hist_cap, s->tdev, s->rejected));
+  return TT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* tt_last_error_string(void) { return g_last_error.c_str(); }
+
+const char* tt_version(void) { return "tt_stream 0.1 (gfx950)"; }
+
+tt_status tt_clamp_ranks(int32_t m, const int64_t* modes, const int64_t* ranks_in, int64_t* ranks_out) {
+  if (!modes || !ranks_in || !ranks_out) return fail(TT_ERR_INVALID_ARG, "null pointer");
+  tt_status st = check_shape(m, modes, ranks_in);
+  if (st != TT_OK) return st;
+  clamp(m, modes, ranks_in, ranks_out);
+  return TT_OK;
+}
+
+tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
+  if (!cfg || !out) return fail(TT_ERR_INVALID_ARG, "null cfg or out");
+  *out = nullptr;
+  if (!cfg->mode_sizes || !cfg->ranks) return fail(TT_ERR_INVALID_ARG, "null mode_sizes or ranks");
+  const int m = cfg->n_slice_modes;
+  tt_status st = check_shape(m, cfg->mode_sizes, cfg->ranks);
+  if (st != TT_OK) return st;
+  {
+    std::vector<int64_t> cl(m);
+    clamp(m, cfg->mode_sizes, cfg->ranks, cl.data());
+    for (int k = 0; k < m; ++k)
+      if (cl[k] != cfg->ranks[k])
+        return fail(TT_ERR_RANK, "infeasible TT-ranks: need r_k <= r_{k-1} I_k and r_{k-1} <= I_k r_k");
+  }
+  if (cfg->compute != TT_F32 && cfg->compute != TT_BF16) return fail(TT_ERR_INVALID_ARG, "compute must be F32/BF16");
+  if (cfg->compute == TT_BF16) return fail(TT_ERR_UNSUPPORTED, "BF16 contractions are not built in this version");
+  if (cfg->flags & ~(TT_FLAG_SYNC_PUSH)) return fail(TT_ERR_UNSUPPORTED, "unsupported flags");
+  if (cfg->split_point < 0 || cfg->split_point > m) return fail(TT_ERR_INVALID_ARG, "split_point out of range");
+
+  tt_stream* s = new (std::nothrow) tt_stream();
+  if (!s) return fail(TT_ERR_OOM, "host allocation failed");
+  s->m = m;
+  s->compute = cfg->compute;
+  s->flags = cfg->flags;
+  s->stream = static_cast<hipStream_t>(cfg->hip_stream);
+  if (cfg->allocator) {
+    if (!cfg->allocator->alloc || !cfg->allocator->free) {
+      delete s;
+      return fail(TT_ERR_INVALID_ARG, "allocator needs alloc and free");
+    }
+    s->alloc = *cfg->allocator;
+    s->has_alloc = true;
+  }
+  s->I.assign(m + 1, 1);
+  s->r.assign(m + 1, 1);
+  for (int k = 1; k <= m; ++k) {
+    s->I[k] = cfg->mode_sizes[k - 1];
+    s->r[k] = cfg->ranks[k - 1];
+  }
+  s->Pk.assign(m + 1, 1);
+  s->Jk.assign(m + 1, 1);
+  for (int k = 1; k <= m; ++k) s->Pk[k] = s->Pk[k - 1] * s->I[k];
+  for (int k = m - 1; k >= 0; --k) s->Jk[k] = s->Jk[k + 1] * s->I[k + 1];
+  s->N = s->Pk[m];
+  s->coff.assign(m + 2, 0);
+  for (int k = 1; k <= m; ++k) s->coff[k + 1] = s->coff[k] + s->r[k - 1] * s->I[k] * s->r[k];
+  s->cores_len = s->coff[m + 1];
+  s->state_len = s->cores_len + s->r[m];
+
+  s->kstar = cfg->split_point > 0 ? cfg->split_point : choose_split(s);
+  if (s->r[s->kstar] > 64) {
+    delete s;
+    return fail(TT_ERR_UNSUPPORTED, "rank at the split point must be <= 64");
+  }
+
+  auto bail = [&](tt_status code, const std::string& msg) {
+    release(s);
+    delete s;
+    return fail(code, msg);
+  };
+  if (hipGetDevice(&s->device) != hipSuccess) return bail(TT_ERR_DEVICE, "hipGetDevice failed");
+  int lds = 65536;
+  if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device) != hipSuccess)
+    return bail(TT_ERR_DEVICE, "cannot query LDS size");
+  s->lds_limit = (size_t)lds;
+  if (ttk::qr64_setup(s->lds_limit) != hipSuccess || ttk::pass_setup() != hipSuccess)
+    return bail(TT_ERR_DEVICE, "kernel attribute setup failed");
+
+  const int m_ = m;
+  const auto& I = s->I;
+  const auto& r = s->r;
+  const int ks = s->kstar;
+  int64_t rmax = 1, qrmax = 1, gtmax = 1, ymax = 1;
+  for (int k = 1; k <= m_; ++k) {
+    rmax = std::max(rmax, r[k]);
+    qrmax = std::max(qrmax, r[k - 1] * I[k] * r[k]);
+    gtmax = std::max(gtmax, r[k - 1] * I[k] * r[k]);
+  }
+  for (int k = ks; k <= m_; ++k) ymax = std::max(ymax, r[k] * s->Jk[k]);
+
+  // chunks of pass 1: enough blocks to cover every CU about once
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
+  const int tiles = ttk::pass1_tiles(s->Pk[ks]);
+  const int64_t pairs = (s->Jk[ks] + 1) / 2;
+  int64_t chunks = (cus + tiles - 1) / tiles;
+  if (chunks > pairs / 8) chunks = pairs / 8;
+  if (chunks < 1) chunks = 1;
+  s->p1_chunks = (int)chunks;
+  s->p1_waves = 8;
+
+  bool ok = true;
+  auto D = [&](size_t n) -> double* {
+    double* p = static_cast<double*>(dev_alloc(s, n * sizeof(double)));
+    ok = ok && p;
+    return p;
+  };
+  auto F = [&](size_t n) -> float* {
+    float* p = static_cast<float*>(dev_alloc(s, n * sizeof(float)));
+    ok = ok && p;
+    return p;
+  };
+  s->master = D(s->state_len);
+  s->work = D(s->state_len);
+  s->fresh = D(s->state_len);
+  s->Rbuf = D(rmax * rmax);
+  s->B.assign(m_ + 1, nullptr);
+  for (int k = ks; k <= m_ - 1; ++k) s->B[k] = D(r[k] * s->Jk[k]);
+  s->B32 = F(r[ks] * s->Jk[ks]);
+  s->Z = D(s->Pk[ks] * r[ks]);
+  s->Zk.assign(m_ + 1, nullptr);
+  for (int k = 1; k < ks; ++k) s->Zk[k] = D(s->Pk[k] * r[k]);
+  s->A.assign(m_ + 2, nullptr);
+  for (int k = 3; k <= ks + 1; ++k) s->A[k] = D(s->Pk[k - 1] * r[k - 1]);
+  s->A32 = F(s->Pk[ks] * r[ks]);
+  s->Gt = D(gtmax);
+  s->Y[0] = D(ymax);
+  s->Y[1] = D(ymax);
+  s->qrwork = D(qrmax);
+  s->ws = F(ttk::pass1_ws_floats(s->Pk[ks], (int)r[ks], s->p1_chunks));
+  s->cnt = static_cast<int*>(dev_alloc(s, sizeof(int) * (tiles + 1)));
+  s->flag = static_cast<int*>(dev_alloc(s, sizeof(int) * 2));
+  s->rejected = s->flag + 1;
+  s->tdev = static_cast<int64_t*>(dev_alloc(s, sizeof(int64_t)));
+  if (cfg->keep_history) {
+    s->hist_cap = cfg->history_capacity > 0 ? cfg->history_capacity : 1024;
+    s->hist = D((size_t)s->hist_cap * r[m_]);
+  }
+  if (!ok || !s->cnt || !s->flag || !s->tdev) return bail(TT_ERR_OOM, "device allocation failed");
+
+#define TT_HIP_BAIL(call)                                                                   \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess) return bail(TT_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+  TT_HIP_BAIL(hipMemsetAsync(s->cnt, 0, sizeof(int) * (tiles + 1), s->stream));
+  TT_HIP_BAIL(hipMemsetAsync(s->flag, 0, sizeof(int) * 2, s->stream));
+  TT_HIP_BAIL(hipMemsetAsync(s->tdev, 0, sizeof(int64_t), s->stream));
+  TT_HIP_BAIL(hipEventCreate(&s->ev0));
+  TT_HIP_BAIL(hipEventCreate(&s->ev1));
+  TT_HIP_BAIL(hipEventCreateWithFlags(&s->evcopy, hipEventDisableTiming));
+
+  std::vector<double> init(s->state_len);
+  if (cfg->init_cores) std::memcpy(init.data(), cfg->init_cores, sizeof(double) * s->state_len);
+  else normal_fill(init, cfg->seed);
+  for (double v : init)
+    if (!std::isfinite(v)) return bail(TT_ERR_NONFINITE, "initial cores contain NaN/Inf");
+  TT_HIP_BAIL(hipMemcpyAsync(s->master, init.data(), sizeof(double) * s->state_len, hipMemcpyHostToDevice, s->stream));
+  TT_HIP_BAIL(hipStreamSynchronize(s->stream));
+#undef TT_HIP_BAIL
+  *out = s;
+  return TT_OK;
+}
+
+tt_status tt_stream_push_slice(tt_stream* s, const void* slice, tt_dtype dtype, int on_device) {
+  if (!valid(s)) return fail(TT_ERR_INVALID_ARG, "invalid handle");
+  if (!slice) return fail(TT_ERR_INVALID_ARG, "null slice");
+  if (dtype != TT_F64 && dtype != TT_F32 && dtype != TT_BF16) return fail(TT_ERR_INVALID_ARG, "bad dtype");
+  const void* X = slice;
+  if (!on_device) {
+    const size_t bytes = (size_t)s->N * dtype_size(dtype);
+    if (s->stage_bytes < bytes) {
+      void* p = dev_alloc(s, bytes);
+      if (!p) return fail(TT_ERR_OOM, "staging allocation failed");
+      s->stage = p;
+      s->stage_bytes = bytes;
+    }
+    TT_HIP(hipMemcpyAsync(s->stage, slice, bytes, hipMemcpyHostToDevice, s->stream));
+    TT_HIP(hipEventRecord(s->evcopy, s->stream));
+    X = s->stage;
+  }
+  TT_HIP(hipEventRecord(s->ev0, s->stream));
+  tt_status st = launch_update(s, X, dtype);
+  if (st != TT_OK) return st;
+  TT_HIP(hipEventRecord(s->ev1, s->stream));
+  s->timed = true;
+  s->pushes++;
+  if (!on_device) TT_HIP(hipEventSynchronize(s->evcopy));
+  if (s->flags & TT_FLAG_SYNC_PUSH) return tt_stream_synchronize(s);
+  return TT_OK;
+}
+
+tt_status tt_stream_synchronize(tt_stream* s) {
+  if (!valid(s)) return fail(TT_ERR_INVALID_ARG, "invalid handle");
+  TT_HIP(hipStreamSynchronize(s->stream));
+  int rej = 0;
+  TT_HIP(hipMemcpy(&rej, s->rejected, sizeof(int), hipMemcpyDeviceToHost));
+  if (rej > s->rejected_seen) {
+    s->rejected_seen = rej;
+    return fail(TT_ERR_NONFINITE, "a slice contained NaN/Inf; its update was discarded");
+  }
+  return TT_OK;
+}
+
+tt_status tt_stream_time(tt_stream* s, int64_t* t_out) {
+  if (!valid(s) || !t_out) return fail(TT_ERR_INVALID_ARG, "invalid handle or null output");
+  TT_HIP(hipStreamSynchronize(s->stream));
+  TT_HIP(hipMemcpy(t_out, s->tdev, sizeof(int64_t), hipMemcpyDeviceToHost));
+  return TT_OK;
+}
+
+tt_status tt_stream_info(const tt_stream* s, int64_t* cores_len, int64_t* r_last, int32_t* split_point,
+                         int64_t* device_bytes) {
+  if (!valid(s)) return fail(TT_ERR_INVALID_ARG, "invalid handle");
+  if (cores_len) *cores_len = s->cores_len;
+  if (r_last) *r_last = s->r[s->m];
+  if (split_point) *split_point = s->kstar;
+  if (device_bytes) *device_bytes = (int64_t)s->device_bytes;
+  return TT_OK;
+}
+
+tt_status tt_stream_get_state(tt_stream* s, double* cores, double* g, int64_t* t_out) {
+  if (!valid(s)) return fail(TT_ERR_INVALID_ARG, "invalid handle");
+  TT_HIP(hipStreamSynchronize(s->stream));
+  if (cores) TT_HIP(hipMemcpy(cores, s->master, sizeof(double) * s->cores_len, hipMemcpyDeviceToHost));
+  if (g) TT_HIP(hipMemcpy(g, s->g_of(s->master), sizeof(double) * s->r[s->m], hipMemcpyDeviceToHost));
+  if (t_out) TT_HIP(hipMemcpy(t_out, s->tdev, sizeof(int64_t), hipMemcpyDeviceToHost));
+  return TT_OK;
+}
+
+tt_status tt_stream_set_state(tt_stream* s, const double* cores, const double* g, int64_t t) {
+  if (!valid(s) || !cores || !g) return fail(TT_ERR_INVALID_ARG, "invalid handle or null input");
+  if (t < 0) return fail(TT_ERR_INVALID_ARG, "t must be >= 0");
+  for (int64_t i = 0; i < s->cores_len; ++i)
+    if (!std::isfinite(cores[i])) return fail(TT_ERR_NONFINITE, "cores contain NaN/Inf");
+  for (int64_t i = 0; i < s->r[s->m]; ++i)
+    if (!std::isfinite(g[i])) return fail(TT_ERR_NONFINITE, "g contains NaN/Inf");
+  TT_HIP(hipStreamSynchronize(s->stream));
+  TT_HIP(hipMemcpy(s->master, cores, sizeof(double) * s->cores_len, hipMemcpyHostToDevice));
+  TT_HIP(hipMemcpy(s->g_of(s->master), g, sizeof(double) * s->r[s->m], hipMemcpyHostToDevice));
+  TT_HIP(hipMemcpy(s->tdev, &t, sizeof(int64_t), hipMemcpyHostToDevice));
+  return TT_OK;
+}
+
+tt_status tt_stream_get_history(tt_stream* s, double* out, int64_t rows, int64_t* rows_out) {
+  if (!valid(s) || !out || !rows_out) return fail(TT_ERR_INVALID_ARG, "invalid handle or null output");
+  if (!s->hist) return fail(TT_ERR_STATE, "history was not enabled");
+  int64_t t = 0;
+  TT_HIP(hipStreamSynchronize(s->stream));
+  TT_HIP(hipMemcpy(&t, s->tdev, sizeof(int64_t), hipMemcpyDeviceToHost));
+  const int64_t have = std::min(t, s->hist_cap);
+  const int64_t n = std::min(have, rows);
+  const int64_t rm = s->r[s->m];
+  std::vector<double> ring((size_t)s->hist_cap * rm);
+  TT_HIP(hipMemcpy(ring.data(), s->hist, sizeof(double) * ring.size(), hipMemcpyDeviceToHost));
+  const int64_t first = t - have;  // oldest kept update index
+  for (int64_t i = 0; i < n; ++i) {
+    const int64_t row = (first + i) % s->hist_cap;
+    std::memcpy(out + i * rm, ring.data() + row * rm, sizeof(double) * rm);
+  }
+  *rows_out = n;
+  return TT_OK;
+}
+
+tt_status tt_stream_reconstruct(tt_stream* s, void* out, tt_dtype dtype, int on_device) {
+  if (!valid(s) || !out) return fail(TT_ERR_INVALID_ARG, "invalid handle or null output");
+  if (dtype != TT_F64 && dtype != TT_F32) return fail(TT_ERR_INVALID_ARG, "reconstruct dtype must be F64/F32");
+  int64_t t = 0;
+  TT_HIP(hipStreamSynchronize(s->stream));
+  TT_HIP(hipMemcpy(&t, s->tdev, sizeof(int64_t), hipMemcpyDeviceToHost));
+  if (t == 0) return fail(TT_ERR_STATE, "no slice has been pushed");
+  if (!s->recon[0]) {
+    s->recon[0] = static_cast<double*>(dev_alloc(s, sizeof(double) * s->N));
+    s->recon[1] = static_cast<double*>(dev_alloc(s, sizeof(double) * s->N));
+    if (!s->recon[0] || !s->recon[1]) return fail(TT_ERR_OOM, "reconstruction buffers");
+  }
+  hipStream_t st = s->stream;
+  // V_{m+1} = g; V_k = G_k^L V_{k+1}, viewed as r_{k-1} x (I_k .. I_m)
+  const double* V = s->g_of(s->master);
+  int64_t cols = 1;
+  int cur = 0;
+  for (int k = s->m; k >= 1; --k) {
+    const int64_t rows = s->r[k - 1] * s->I[k];
+    double* dst = s->recon[cur];
+    TT_HIP(ttk::gemm64(st, rows, cols, s->r[k], s->G_of(s->master, k), 1, rows, V, 1, s->r[k], dst, 1, rows,
+                       nullptr));
+    V = dst;
+    cols *= s->I[k];
+    cur ^= 1;
+  }
+  if (on_device) {
+    TT_HIP(ttk::convert_out(st, V, out, dtype, s->N));
+  } else {
+    if (dtype == TT_F64) {
+      TT_HIP(hipMemcpyAsync(out, V, sizeof(double) * s->N, hipMemcpyDeviceToHost, st));
+    } else {
+      double* tmp = s->recon[cur];
+      TT_HIP(ttk::convert_out(st, V, tmp, TT_F32, s->N));
+      TT_HIP(hipMemcpyAsync(out, tmp, sizeof(float) * s->N, hipMemcpyDeviceToHost, st));
+    }
+    TT_HIP(hipStreamSynchronize(st));
+  }
+  return TT_OK;
+}
+
+tt_status tt_stream_last_push_ms(tt_stream* s, float* ms) {
+  if (!valid(s) || !ms) return fail(TT_ERR_INVALID_ARG, "invalid handle or null output");
+  if (!s->timed) return fail(TT_ERR_STATE, "no push yet");
+  TT_HIP(hipEventSynchronize(s->ev1));
+  TT_HIP(hipEventElapsedTime(ms, s->ev0, s->ev1));
+  return TT_OK;
+}
+
+tt_status tt_stream_destroy(tt_stream* s) {
+  if (!valid(s)) return fail(TT_ERR_INVALID_ARG, "invalid handle");
+  (void)hipStreamSynchronize(s->stream);
+  release(s);
+  s->magic = kDead;
+  delete s;
+  return TT_OK;
+}
+
+}  // extern "C"

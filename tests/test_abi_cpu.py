@@ -1,0 +1,103 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+that include/*.h declares, and its host-side validation (rank feasibility,
+shapes, null arguments) behaves as documented."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import ttals
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2606_31061_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.fail("libttstream.so is not built; run __graft_entry__.build() first")
+    return binding, binding.load_library()
+
+
+def _declared_functions():
+    names = []
+    for h in ("tt_stream.h", "tt_kernels.h"):
+        text = open(os.path.join(ROOT, "include", h)).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names += re.findall(r"\b(tt_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    binding, lib = _lib()
+    names = _declared_functions()
+    assert len(names) >= 18
+    handle = ctypes.CDLL(binding.LIB_PATH)
+    for n in names:
+        assert hasattr(handle, n), f"missing export {n}"
+
+
+def test_version_and_error_string():
+    _, lib = _lib()
+    assert b"gfx950" in lib.tt_version()
+    assert isinstance(lib.tt_last_error_string(), bytes)
+
+
+@pytest.mark.parametrize("modes,ranks", [
+    ((8, 9, 15, 8, 16, 15, 3, 1, 1), [32] * 9),
+    ((32, 32), (4, 4)),
+    ((240, 320, 3), (16, 16, 16)),
+    ((2, 2, 2), (8, 8, 8)),
+    ((3, 1, 1), (5, 5, 2)),
+    ((5,), (9,)),
+])
+def test_clamp_ranks_matches_oracle(modes, ranks):
+    binding, _ = _lib()
+    assert binding.tt_clamp_ranks(modes, ranks) == ttals.clamp_ranks(modes, ranks)
+
+
+def test_clamp_ranks_rejects_bad_shapes():
+    binding, _ = _lib()
+    with pytest.raises(binding.TTError) as e:
+        binding.tt_clamp_ranks((4, 0), (2, 2))
+    assert e.value.status == binding.TT_ERR_SHAPE
+
+
+def test_create_validates_before_touching_the_device():
+    binding, _ = _lib()
+    # infeasible ranks
+    with pytest.raises(binding.TTError) as e:
+        binding.tt_stream_create((2, 2), (4, 4))
+    assert e.value.status == binding.TT_ERR_RANK
+    # non-positive mode size
+    with pytest.raises(binding.TTError) as e:
+        binding.tt_stream_create((4, 0), (1, 1))
+    assert e.value.status == binding.TT_ERR_SHAPE
+    # no modes
+    with pytest.raises(binding.TTError) as e:
+        binding.tt_stream_create((), ())
+    assert e.value.status == binding.TT_ERR_SHAPE
+    # unknown flags
+    with pytest.raises(binding.TTError) as e:
+        binding.tt_stream_create((4, 4), (2, 2), flags=0x100)
+    assert e.value.status == binding.TT_ERR_UNSUPPORTED
+
+
+def test_null_handles_are_rejected():
+    binding, lib = _lib()
+    assert lib.tt_stream_push_slice(None, None, 1, 1) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_stream_reconstruct(None, None, 0, 0) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_stream_destroy(None) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_stream_synchronize(None) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_stream_create(None, None) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_kernel_pass1_workspace(0, 1, 1) == 0
+
+
+def test_product_path_does_not_import_the_oracle():
+    for dirpath, _, files in os.walk(os.path.join(ROOT, "paper_2606_31061_amd")):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in text and "from oracle" not in text, f

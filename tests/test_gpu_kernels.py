@@ -1,0 +1,139 @@
+"""Kernel-level parity of the update's building blocks, called through the C
+ABI (include/tt_kernels.h): pass 1 and pass 2 against a float64 NumPy
+contraction of the same FP32-rounded operands, and the FP64 Householder QR
+against the oracle's QR and its defining properties."""
+
+import numpy as np
+import pytest
+
+from oracle.householder import householder_qr
+from tests.gpu_util import say, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _rng(s):
+    return np.random.Generator(np.random.PCG64(s))
+
+
+CASES = [(32, 32, 4), (240, 960, 16), (1080, 5760, 32), (100, 77, 5), (33, 1, 8), (200, 300, 48),
+         (8, 777, 8), (4, 3, 1)]
+
+
+def _ref_round(X, dt):
+    import torch
+    if dt == torch.bfloat16:
+        return torch.from_numpy(X).to(torch.bfloat16).to(torch.float64).numpy()
+    return X.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("P,J,r", CASES)
+@pytest.mark.parametrize("xdt", ["f32", "f64", "bf16"])
+def test_pass1_matches_numpy(P, J, r, xdt):
+    torch = torch_cuda()
+    from paper_2606_31061_amd import binding
+    say(f"pass1 P={P} J={J} r={r} {xdt}")
+    rng = _rng(P * 7 + J + r)
+    X = rng.standard_normal((P, J))
+    B = rng.standard_normal((r, J)).astype(np.float32)
+    tdt = {"f32": torch.float32, "f64": torch.float64, "bf16": torch.bfloat16}[xdt]
+    Xd = torch.from_numpy(np.asfortranarray(X).reshape(-1, order="F").copy()).cuda().to(tdt)
+    Bd = torch.from_numpy(np.asfortranarray(B).reshape(-1, order="F").copy()).cuda()
+    Zd = torch.full((P * r,), float("nan"), dtype=torch.float64, device="cuda")
+    ws = torch.zeros(binding.tt_kernel_pass1_workspace(P, J, r), dtype=torch.uint8, device="cuda")
+    flag = torch.zeros(1, dtype=torch.int32, device="cuda")
+    for rep in range(2):  # second call checks the workspace counters were left at zero
+        assert binding.tt_kernel_pass1(Xd, P, J, r, Bd, Zd, ws, flag) == 0
+        torch.cuda.synchronize()
+        Z = Zd.cpu().numpy().reshape(P, r, order="F")
+        Xr = _ref_round(X, tdt)
+        ref = Xr @ B.astype(np.float64).T
+        bound = np.abs(Xr) @ np.abs(B.astype(np.float64)).T
+        assert np.all(np.abs(Z - ref) <= 2e-6 * bound + 1e-30), rep
+    assert int(flag.item()) == 0
+    assert int(ws[-4 * ((P + 31) // 32 + 1):].sum().item()) == 0
+
+
+@pytest.mark.parametrize("P,J,r", CASES)
+@pytest.mark.parametrize("xdt", ["f32", "f64", "bf16"])
+def test_pass2_matches_numpy(P, J, r, xdt):
+    torch = torch_cuda()
+    from paper_2606_31061_amd import binding
+    say(f"pass2 P={P} J={J} r={r} {xdt}")
+    rng = _rng(P * 5 + J + r)
+    X = rng.standard_normal((P, J))
+    A = rng.standard_normal((P, r)).astype(np.float32)
+    tdt = {"f32": torch.float32, "f64": torch.float64, "bf16": torch.bfloat16}[xdt]
+    Xd = torch.from_numpy(np.asfortranarray(X).reshape(-1, order="F").copy()).cuda().to(tdt)
+    Ad = torch.from_numpy(np.asfortranarray(A).reshape(-1, order="F").copy()).cuda()
+    Yd = torch.full((r * J,), float("nan"), dtype=torch.float64, device="cuda")
+    flag = torch.zeros(1, dtype=torch.int32, device="cuda")
+    assert binding.tt_kernel_pass2(Xd, P, J, r, Ad, Yd, flag) == 0
+    torch.cuda.synchronize()
+    Y = Yd.cpu().numpy().reshape(r, J, order="F")
+    Xr = _ref_round(X, tdt)
+    ref = A.astype(np.float64).T @ Xr
+    bound = np.abs(A.astype(np.float64)).T @ np.abs(Xr)
+    assert np.all(np.abs(Y - ref) <= 2e-6 * bound + 1e-30)
+    assert int(flag.item()) == 0
+
+
+def test_passes_flag_nonfinite_slices():
+    torch = torch_cuda()
+    from paper_2606_31061_amd import binding
+    say("pass flags nonfinite")
+    P, J, r = 240, 960, 16
+    X = np.ones((P, J))
+    X[17, 300] = np.nan
+    Xd = torch.from_numpy(X.reshape(-1, order="F").copy()).cuda().float()
+    Bd = torch.ones(r * J, dtype=torch.float32, device="cuda")
+    Ad = torch.ones(P * r, dtype=torch.float32, device="cuda")
+    Zd = torch.zeros(P * r, dtype=torch.float64, device="cuda")
+    Yd = torch.zeros(r * J, dtype=torch.float64, device="cuda")
+    ws = torch.zeros(binding.tt_kernel_pass1_workspace(P, J, r), dtype=torch.uint8, device="cuda")
+    f1 = torch.zeros(1, dtype=torch.int32, device="cuda")
+    f2 = torch.zeros(1, dtype=torch.int32, device="cuda")
+    assert binding.tt_kernel_pass1(Xd, P, J, r, Bd, Zd, ws, f1) == 0
+    assert binding.tt_kernel_pass2(Xd, P, J, r, Ad, Yd, f2) == 0
+    torch.cuda.synchronize()
+    assert int(f1.item()) == 1 and int(f2.item()) == 1
+
+
+QR_CASES = [(8, 8, None), (72, 32, None), (480, 32, None), (512, 32, None), (96, 32, 1), (480, 32, 3),
+            (32, 32, 1), (5120, 16, None), (5120, 16, 3), (1, 1, None), (300, 7, None), (16, 16, 0)]
+
+
+@pytest.mark.parametrize("m,n,rank", QR_CASES)
+def test_qr_matches_oracle(m, n, rank):
+    torch = torch_cuda()
+    from paper_2606_31061_amd import binding
+    say(f"qr m={m} n={n} rank={rank}")
+    rng = _rng(m * 31 + n)
+    if rank is None:
+        M = rng.standard_normal((m, n))
+    elif rank == 0:
+        M = np.zeros((m, n))
+    else:
+        M = rng.standard_normal((m, rank)) @ rng.standard_normal((rank, n))
+    Md = torch.from_numpy(M.T.copy()).cuda()      # (n, m) C-contiguous = m x n column-major
+    Qd = torch.empty_like(Md)
+    Rd = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    wk = torch.empty(m * n, dtype=torch.float64, device="cuda")
+    assert binding.tt_kernel_qr(Md, Qd, Rd, wk) == 0
+    torch.cuda.synchronize()
+    Q = Qd.cpu().numpy().T
+    R = Rd.cpu().numpy().T
+    nrm = max(np.linalg.norm(M), 1e-300)
+    assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= 1e-12
+    assert np.linalg.norm(Q @ R - M) <= 1e-12 * nrm
+    assert np.allclose(R, np.triu(R), atol=0) and np.all(np.diag(R) >= 0)
+    Qo, Ro = householder_qr(M)
+    if rank is None:
+        # full rank: the thin QR with diag(R) > 0 is unique
+        assert np.max(np.abs(Q - Qo)) <= 1e-11
+        assert np.max(np.abs(R - Ro)) <= 1e-11 * np.max(np.abs(Ro))
+    else:
+        # rank-deficient: the data columns agree; completions may differ
+        k = max(rank, 0)
+        if k:
+            assert np.linalg.norm(Q[:, :k] @ Q[:, :k].T @ M - M) <= 1e-11 * nrm

@@ -1,0 +1,284 @@
+"""Parity of the HIP update (through the C ABI) with the FP64 oracle.
+
+The cores are unique only up to an orthogonal gauge per bond and the
+completion columns of rank-deficient QRs, so parity is on gauge-invariant
+outputs: the reconstruction M_t of every slice, the per-slice error E_t and
+the stream RE (Section 5.1), ||g|| = ||M_t||, and the orthogonality of the
+GPU's FP64 cores.  Tolerances (FP32 slice contractions, FP64 chain):
+  max_t ||M_t^gpu - M_t^oracle|| / ||X_t|| <= 1e-5
+  |RE_gpu - RE_oracle| <= 1e-5 RE_oracle   (the FP32 bound for configs 1-2)
+"""
+
+import numpy as np
+import pytest
+
+from oracle import ttals
+from tests.gpu_util import rel, run_gpu_stream, say, to_device_slice, torch_cuda
+from ttgen import config_c1, config_c2, config_c3, exact_tt_stream
+
+pytestmark = pytest.mark.gpu
+
+M_TOL = 1e-5
+RE_TOL = 1e-5
+
+
+def _compare_stream(modes, ranks, init, slices, **kw):
+    torch = torch_cuda()
+    Ms, s = run_gpu_stream(torch, modes, ranks, init, slices, **kw)
+    ref = ttals.run_stream(slices, init[0], init[1], keep_M=True)
+    E_gpu = np.array([np.linalg.norm(np.asarray(X, np.float64) - M) for X, M in zip(slices, Ms)])
+    worst = max(rel(M, i.M, np.linalg.norm(X)) for M, i, X in zip(Ms, ref.infos, slices))
+    re_gpu = float(np.sqrt(np.sum(E_gpu ** 2) / np.sum(ref.Xnorm ** 2)))
+    return s, ref, worst, re_gpu, E_gpu
+
+
+def _orth_errors(cores):
+    out = []
+    for G in cores:
+        L = ttals.left_unfold(G)
+        out.append(np.linalg.norm(L.T @ L - np.eye(L.shape[1])))
+    return out
+
+
+def test_c1_order3_stream_parity():
+    st = config_c1()
+    init = st.init()
+    slices = list(st.frames(1, st.T))
+    say("c1 order-3 32x32 r=(4,4), 200 slices")
+    s, ref, worst, re_gpu, _ = _compare_stream(st.modes, st.ranks, init, slices)
+    assert worst <= M_TOL, worst
+    assert abs(re_gpu - ref.re) <= RE_TOL * ref.re, (re_gpu, ref.re)
+    cores, g, t = s.get_state()
+    assert t == st.T
+    assert max(_orth_errors(cores)) <= 1e-12
+    # temporal rows kept on the device: ||g_t|| = ||M_t||
+    hist = s.history()
+    assert hist.shape == (st.T, st.ranks[-1])
+    s.close()
+
+
+def test_c1_exact_recovery_on_gpu():
+    st = config_c1(sigma=0.0, T=20)
+    init = st.init()
+    slices = list(st.frames(1, st.T))
+    say("c1 noise-free exact recovery")
+    torch = torch_cuda()
+    Ms, s = run_gpu_stream(torch, st.modes, st.ranks, init, slices)
+    for X, M in zip(slices, Ms):
+        assert rel(M, X, np.linalg.norm(X)) <= 1e-6
+    s.close()
+
+
+def test_c2_video_stream_parity_prefix():
+    st = config_c2(T=1000)
+    init = st.init()
+    slices = list(st.frames(1, 40))
+    say("c2 240x320x3 r=16, 40 frames")
+    s, ref, worst, re_gpu, _ = _compare_stream(st.modes, st.ranks, init, slices)
+    assert worst <= M_TOL, worst
+    assert abs(re_gpu - ref.re) <= RE_TOL * ref.re, (re_gpu, ref.re)
+    cores, g, t = s.get_state()
+    assert max(_orth_errors(cores)) <= 1e-12
+    s.close()
+
+
+def test_c3_full_size_parity_first_slices():
+    st = config_c3(T=500)
+    init = st.init()
+    slices = list(st.frames(1, 3))
+    say("c3 order-9 6.2M-element slices, 3 frames")
+    torch = torch_cuda()
+    from paper_2606_31061_amd import TTStream
+    s = TTStream(st.modes, st.ranks, init=init)
+    assert s.info()["split_point"] == 3
+    c, g = init
+    for t, X in enumerate(slices, start=1):
+        s.push(to_device_slice(torch, X))
+        M = s.reconstruct()
+        c, g, info = ttals.online_step(c, g, X)
+        xn = np.linalg.norm(X.astype(np.float64))
+        e = rel(M, info.M, xn)
+        E = np.linalg.norm(X.astype(np.float64) - M)
+        say(f"c3 t={t} |dM|/|X|={e:.3e} E_gpu={E:.6e} E_or={info.E:.6e}")
+        assert e <= M_TOL, (t, e)
+        assert abs(E - info.E) <= 1e-4 * info.E
+    cores, _, _ = s.get_state()
+    assert max(_orth_errors(cores)) <= 1e-12
+    s.close()
+
+
+SHAPES = [
+    ((12, 10, 3), (4, 4, 3)),
+    ((6, 5, 4, 3), (3, 4, 4, 2)),
+    ((5, 1, 4, 1), (3, 3, 4, 4)),
+    ((7, 6), (5, 1)),
+    ((9,), (4,)),
+    ((64, 2, 33), (40, 33, 33)),
+]
+
+
+@pytest.mark.parametrize("modes,ranks", SHAPES)
+def test_small_shapes_parity(modes, ranks):
+    st = exact_tt_stream(modes, ranks, ranks, 12, 5, 6, sigma=1e-2)
+    init = st.init()
+    slices = list(st.frames(1, st.T))
+    say(f"shape {modes} ranks {ranks}")
+    s, ref, worst, re_gpu, _ = _compare_stream(modes, ranks, init, slices)
+    assert worst <= M_TOL, worst
+    assert abs(re_gpu - ref.re) <= RE_TOL * ref.re + 1e-7
+    s.close()
+
+
+@pytest.mark.parametrize("split", [1, 2, 3])
+def test_every_split_point_gives_the_same_update(split):
+    modes, ranks = (6, 5, 4, 3), (3, 4, 4, 2)
+    st = exact_tt_stream(modes, ranks, ranks, 10, 8, 9, sigma=1e-2)
+    init = st.init()
+    slices = list(st.frames(1, st.T))
+    say(f"split point {split}")
+    s, ref, worst, re_gpu, _ = _compare_stream(modes, ranks, init, slices, split_point=split)
+    assert s.info()["split_point"] == split
+    assert worst <= M_TOL, worst
+    s.close()
+
+
+def test_one_step_from_injected_oracle_state():
+    torch = torch_cuda()
+    from paper_2606_31061_amd import TTStream
+    st = config_c2(T=1000)
+    init = st.init()
+    slices = list(st.frames(1, 6))
+    ref = ttals.run_stream(slices[:5], init[0], init[1])
+    say("one step from injected state (c2)")
+    s = TTStream(st.modes, st.ranks, init=init)
+    s.set_state(ref.cores, ref.g, t=5)
+    s.push(to_device_slice(torch, slices[5]))
+    M = s.reconstruct()
+    c, g, info = ttals.online_step(ref.cores, ref.g, slices[5])
+    assert s.time() == 6
+    assert rel(M, info.M, np.linalg.norm(slices[5])) <= M_TOL
+    _, gg, _ = s.get_state()
+    assert abs(np.linalg.norm(gg) - np.linalg.norm(g)) <= 1e-5 * np.linalg.norm(g)
+    s.close()
+
+
+def test_nonfinite_slice_leaves_state_unchanged():
+    torch = torch_cuda()
+    from paper_2606_31061_amd import TTStream, binding
+    st = config_c1(T=5)
+    init = st.init()
+    slices = list(st.frames(1, 5))
+    say("nonfinite slice rejected")
+    s = TTStream(st.modes, st.ranks, init=init)
+    s.push(to_device_slice(torch, slices[0]))
+    s.synchronize()
+    before = s.get_state()
+    bad = slices[1].copy()
+    bad[3, 7] = np.inf
+    s.push(to_device_slice(torch, bad))
+    assert s.synchronize_status() == binding.TT_ERR_NONFINITE
+    after = s.get_state()
+    assert after[2] == before[2] == 1
+    for a, b in zip(after[0], before[0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(after[1], before[1])
+    bad[3, 7] = np.nan
+    s.push(to_device_slice(torch, bad))
+    assert s.synchronize_status() == binding.TT_ERR_NONFINITE
+    # the stream continues normally afterwards
+    s.push(to_device_slice(torch, slices[1]))
+    s.synchronize()
+    assert s.time() == 2
+    s.close()
+    # synchronous mode reports it from the push itself
+    s2 = TTStream(st.modes, st.ranks, init=init, sync_push=True)
+    with pytest.raises(binding.TTError) as e:
+        s2.push(to_device_slice(torch, bad))
+    assert e.value.status == binding.TT_ERR_NONFINITE
+    s2.close()
+
+
+def test_zero_slice_then_recovery():
+    torch = torch_cuda()
+    st = exact_tt_stream((12, 10, 3), (4, 4, 3), (4, 4, 3), 6, 3, 4, sigma=1e-2)
+    init = st.init()
+    slices = list(st.frames(1, 6))
+    slices[2] = np.zeros_like(slices[2])
+    say("zero slice")
+    s, ref, worst, re_gpu, E = _compare_stream(st.modes, st.ranks, init, slices)
+    assert E[2] == 0.0
+    assert worst <= M_TOL
+    s.close()
+
+
+def test_determinism_bitwise():
+    torch = torch_cuda()
+    from paper_2606_31061_amd import TTStream
+    st = config_c2(T=1000)
+    init = st.init()
+    xs = [to_device_slice(torch, X) for X in st.frames(1, 5)]
+    say("determinism")
+    states = []
+    for _ in range(2):
+        s = TTStream(st.modes, st.ranks, init=init)
+        for x in xs:
+            s.push(x)
+        states.append(s.get_state())
+        s.close()
+    for a, b in zip(states[0][0], states[1][0]):
+        assert np.array_equal(a, b)
+    assert np.array_equal(states[0][1], states[1][1])
+
+
+def test_host_and_device_inputs_and_dtypes_agree():
+    torch = torch_cuda()
+    from paper_2606_31061_amd import TTStream
+    st = config_c1(T=6)
+    init = st.init()
+    slices = list(st.frames(1, 6))
+    say("host/device inputs, f64/f32")
+    outs = []
+    for mode in ("host64", "dev64", "dev32", "host32"):
+        s = TTStream(st.modes, st.ranks, init=init)
+        for X in slices:
+            if mode == "host64":
+                s.push(np.asarray(X, dtype=np.float64))
+            elif mode == "host32":
+                s.push(np.asarray(X, dtype=np.float32))
+            elif mode == "dev64":
+                s.push(to_device_slice(torch, X))
+            else:
+                s.push(to_device_slice(torch, X, torch.float32))
+        outs.append(s.reconstruct())
+        s.close()
+    assert np.array_equal(outs[0], outs[1])          # same bytes, same path
+    assert np.array_equal(outs[2], outs[3])
+    assert rel(outs[0], outs[2], np.linalg.norm(outs[0])) <= 1e-5
+
+
+def test_reconstruct_before_push_is_a_state_error():
+    torch_cuda()
+    from paper_2606_31061_amd import TTStream, binding
+    say("reconstruct before push")
+    s = TTStream((8, 8), (2, 2), seed=3)
+    with pytest.raises(binding.TTError) as e:
+        s.reconstruct()
+    assert e.value.status == binding.TT_ERR_STATE
+    s.close()
+
+
+def test_reconstruct_into_device_tensor_f32():
+    torch = torch_cuda()
+    from paper_2606_31061_amd import TTStream
+    st = config_c1(T=3)
+    init = st.init()
+    say("reconstruct to device f32")
+    s = TTStream(st.modes, st.ranks, init=init)
+    for X in st.frames(1, 3):
+        s.push(to_device_slice(torch, X))
+    host = s.reconstruct()
+    dev = torch.empty(32 * 32, dtype=torch.float32, device="cuda")
+    s.reconstruct(out=dev)
+    torch.cuda.synchronize()
+    assert np.allclose(dev.cpu().numpy(), host.reshape(-1, order="F").astype(np.float32), rtol=1e-6, atol=1e-6)
+    s.close()
