@@ -213,20 +213,24 @@ __global__ void __launch_bounds__(256) k_normalize_g(const double* g_in, double*
   }
 }
 
-__global__ void __launch_bounds__(256) k_commit(int* flag, const double* new_state, double* master, int64_t len,
-                                                const double* g_new, int rm, double* history, int64_t hist_cap,
-                                                int64_t* t_dev, int* rejected) {
-  const int ok = (*flag == 0);
-  if (ok) {
-    for (int64_t e = threadIdx.x; e < len; e += 256) master[e] = new_state[e];
-    if (history && hist_cap > 0) {
-      const int64_t row = (*t_dev) % hist_cap;
-      for (int i = threadIdx.x; i < rm; i += 256) history[row * rm + i] = g_new[i];
-    }
+// Commit, part 1: every block copies its share of the new state (and the
+// temporal row) when the update saw a finite slice.
+__global__ void __launch_bounds__(256) k_commit_copy(const int* flag, const double* new_state, double* master,
+                                                     int64_t len, const double* g_new, int rm, double* history,
+                                                     int64_t hist_cap, const int64_t* t_dev) {
+  if (*flag != 0) return;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < len; e += (int64_t)gridDim.x * blockDim.x)
+    master[e] = new_state[e];
+  if (blockIdx.x == 0 && history && hist_cap > 0) {
+    const int64_t row = (*t_dev) % hist_cap;
+    for (int i = threadIdx.x; i < rm; i += blockDim.x) history[row * rm + i] = g_new[i];
   }
-  __syncthreads();
+}
+
+// Commit, part 2: advance t (or count the rejected slice) and clear the flag.
+__global__ void k_commit_final(int* flag, int64_t* t_dev, int* rejected) {
   if (threadIdx.x == 0) {
-    if (ok) *t_dev += 1;
+    if (*flag == 0) *t_dev += 1;
     else *rejected += 1;
     *flag = 0;
   }
@@ -268,10 +272,16 @@ hipError_t gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K,
   return hipGetLastError();
 }
 
+bool qr_reg_fits(int m, int n, size_t lds_limit);
+hipError_t qr_reg(hipStream_t st, int m, int n, const double* M, int64_t mrs, int64_t mcs, double* Q, int64_t qrs,
+                  int64_t qcs, double* R, double tol);
+hipError_t qr_reg_setup(size_t lds);
+
 hipError_t qr64(hipStream_t st, int m, int n, const double* M, int64_t mrs, int64_t mcs,
                 double* Q, int64_t qrs, int64_t qcs, double* R, double tol,
                 double* gwork, size_t lds_limit) {
   if (m < n || n < 1) return hipErrorInvalidValue;
+  if (qr_reg_fits(m, n, lds_limit)) return qr_reg(st, m, n, M, mrs, mcs, Q, qrs, qcs, R, tol);
   const size_t small = (size_t)(2 * n + 32) * sizeof(double);
   const size_t need = small + (size_t)m * n * sizeof(double);
   if (need <= lds_limit) {
@@ -299,8 +309,9 @@ hipError_t normalize_g(hipStream_t st, const double* g_in, double* g_out, int rm
 hipError_t commit(hipStream_t st, int* flag, const double* new_state, double* master, int64_t len,
                   const double* g_new, int rm, double* history, int64_t hist_cap,
                   int64_t* t_dev, int* rejected) {
-  hipLaunchKernelGGL(k_commit, dim3(1), dim3(256), 0, st, flag, new_state, master, len, g_new, rm, history,
-                     hist_cap, t_dev, rejected);
+  hipLaunchKernelGGL(k_commit_copy, dim3(grid_for(len, 256, 256)), dim3(256), 0, st, flag, new_state, master, len,
+                     g_new, rm, history, hist_cap, t_dev);
+  hipLaunchKernelGGL(k_commit_final, dim3(1), dim3(64), 0, st, flag, t_dev, rejected);
   return hipGetLastError();
 }
 
@@ -321,7 +332,8 @@ hipError_t to_f32(hipStream_t st, const double* src, float* dst, int64_t n) {
 hipError_t qr64_setup(size_t lds_limit) {
   hipError_t e = hipFuncSetAttribute((const void*)k_qr64_lds<kQrThreads>,
                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_limit);
-  return e;
+  if (e != hipSuccess) return e;
+  return qr_reg_setup(lds_limit);
 }
 
 }  // namespace ttk
