@@ -20,9 +20,10 @@ extern "C" {
 
 /* Pass 1 of an update (Eq. 5 for the cores k <= k*, contracted with the right
  * interface first): Z = X B^T for the P x J slice unfolding X (element type
- * x_dtype), B r x J FP32, Z P x r FP64.  1 <= r <= 64.  workspace must hold
- * tt_kernel_pass1_workspace(P, r) bytes and be zero-filled before its first
- * use; it is left zero-filled. */
+ * x_dtype), B r x J FP32, Z P x r FP64.  1 <= r <= 64.  workspace (device,
+ * caller-owned, no initialisation needed) must hold
+ * tt_kernel_pass1_workspace(P, J, r) bytes; it receives the FP32 partial
+ * tiles, which are then added in FP64 in a fixed order. */
 tt_status tt_kernel_pass1(const void* X, tt_dtype x_dtype, int64_t P, int64_t J, int32_t r,
                           const float* B, double* Z, void* workspace, int32_t* nonfinite_flag,
                           void* hip_stream);

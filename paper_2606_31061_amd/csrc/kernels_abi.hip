@@ -18,15 +18,10 @@ tt_status kfail(tt_status st, const char* what, hipError_t e = hipSuccess) {
   return ttk::set_error(st, msg.c_str());
 }
 
-int pass1_chunks_for(int64_t P, int64_t J) {
+ttk::Pass1Plan plan_for(int64_t P, int64_t J, int r) {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  const int tiles = ttk::pass1_tiles(P);
-  const int64_t pairs = (J + 1) / 2;
-  int64_t chunks = (cus + tiles - 1) / tiles;
-  if (chunks > pairs / 8) chunks = pairs / 8;
-  if (chunks < 1) chunks = 1;
-  return (int)chunks;
+  return ttk::pass1_plan(P, J, r, cus);
 }
 
 size_t lds_limit() {
@@ -41,9 +36,7 @@ extern "C" {
 
 size_t tt_kernel_pass1_workspace(int64_t P, int64_t J, int32_t r) {
   if (P < 1 || J < 1 || r < 1 || r > 64) return 0;
-  const int chunks = pass1_chunks_for(P, J);
-  const size_t ws = ttk::pass1_ws_floats(P, r, chunks) * sizeof(float);
-  return ((ws + 255) & ~size_t(255)) + sizeof(int) * (ttk::pass1_tiles(P) + 1);
+  return plan_for(P, J, r).ws_floats * sizeof(float);
 }
 
 tt_status tt_kernel_pass1(const void* X, tt_dtype x_dtype, int64_t P, int64_t J, int32_t r, const float* B, double* Z,
@@ -51,12 +44,9 @@ tt_status tt_kernel_pass1(const void* X, tt_dtype x_dtype, int64_t P, int64_t J,
   if (!X || !B || !Z || !workspace || !nonfinite_flag) return kfail(TT_ERR_INVALID_ARG, "null");
   if (P < 1 || J < 1 || r < 1 || r > 64) return kfail(TT_ERR_INVALID_ARG, "size");
   if (ttk::pass_setup() != hipSuccess) return kfail(TT_ERR_DEVICE, "setup");
-  const int chunks = pass1_chunks_for(P, J);
-  const size_t ws = ttk::pass1_ws_floats(P, r, chunks) * sizeof(float);
-  float* wsp = static_cast<float*>(workspace);
-  int* cnt = reinterpret_cast<int*>(static_cast<char*>(workspace) + ((ws + 255) & ~size_t(255)));
-  hipError_t e = ttk::pass1(static_cast<hipStream_t>(hip_stream), X, x_dtype, P, J, r, B, Z, wsp, cnt,
-                            nonfinite_flag, chunks, 8);
+  const ttk::Pass1Plan pl = plan_for(P, J, r);
+  hipError_t e = ttk::pass1(static_cast<hipStream_t>(hip_stream), X, x_dtype, pl, P, J, r, B, Z,
+                            static_cast<float*>(workspace), nonfinite_flag);
   return e == hipSuccess ? TT_OK : kfail(TT_ERR_DEVICE, "pass1", e);
 }
 

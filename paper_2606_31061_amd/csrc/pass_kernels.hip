@@ -17,16 +17,97 @@ namespace {
 
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
-template <typename T>
-__device__ __forceinline__ float ldf(const T* p);
+// ---------------------------------------------------------------- loads
+// VEC consecutive elements of X converted to FP32 (streamed: non-temporal).
+template <typename T, int VEC>
+struct Ld;
 template <>
-__device__ __forceinline__ float ldf<float>(const float* p) { return __builtin_nontemporal_load(p); }
+struct Ld<float, 1> {
+  static __device__ __forceinline__ void get(const float* p, float* o) { o[0] = __builtin_nontemporal_load(p); }
+};
 template <>
-__device__ __forceinline__ float ldf<double>(const double* p) { return (float)__builtin_nontemporal_load(p); }
+struct Ld<float, 2> {
+  static __device__ __forceinline__ void get(const float* p, float* o) {
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    const f2 v = __builtin_nontemporal_load(reinterpret_cast<const f2*>(p));
+    o[0] = v.x;
+    o[1] = v.y;
+  }
+};
 template <>
-__device__ __forceinline__ float ldf<__hip_bfloat16>(const __hip_bfloat16* p) {
-  const unsigned short u = __builtin_nontemporal_load(reinterpret_cast<const unsigned short*>(p));
-  return __uint_as_float(((unsigned)u) << 16);
+struct Ld<float, 4> {
+  static __device__ __forceinline__ void get(const float* p, float* o) {
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const f4 v = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
+    o[0] = v.x;
+    o[1] = v.y;
+    o[2] = v.z;
+    o[3] = v.w;
+  }
+};
+template <int VEC>
+struct Ld<double, VEC> {
+  static __device__ __forceinline__ void get(const double* p, float* o) {
+#pragma unroll
+    for (int s = 0; s < VEC; ++s) o[s] = (float)__builtin_nontemporal_load(p + s);
+  }
+};
+template <int VEC>
+struct Ld<__hip_bfloat16, VEC> {
+  static __device__ __forceinline__ void get(const __hip_bfloat16* p, float* o) {
+    const unsigned short* q = reinterpret_cast<const unsigned short*>(p);
+#pragma unroll
+    for (int s = 0; s < VEC; ++s) o[s] = __uint_as_float(((unsigned)__builtin_nontemporal_load(q + s)) << 16);
+  }
+};
+
+// Regular (cached) loads: pass 1's row tiles share the L2 lines where a
+// column's segments meet, and the tiles of one chunk run on one XCD.
+template <typename T, int VEC>
+struct LdC;
+template <int VEC>
+struct LdC<float, VEC> {
+  static __device__ __forceinline__ void get(const float* p, float* o) {
+    if constexpr (VEC == 4) {
+      const float4 v = *reinterpret_cast<const float4*>(p);
+      o[0] = v.x;
+      o[1] = v.y;
+      o[2] = v.z;
+      o[3] = v.w;
+    } else if constexpr (VEC == 2) {
+      const float2 v = *reinterpret_cast<const float2*>(p);
+      o[0] = v.x;
+      o[1] = v.y;
+    } else {
+      o[0] = *p;
+    }
+  }
+};
+template <int VEC>
+struct LdC<double, VEC> {
+  static __device__ __forceinline__ void get(const double* p, float* o) {
+#pragma unroll
+    for (int s = 0; s < VEC; ++s) o[s] = (float)p[s];
+  }
+};
+template <int VEC>
+struct LdC<__hip_bfloat16, VEC> {
+  static __device__ __forceinline__ void get(const __hip_bfloat16* p, float* o) {
+    const unsigned short* q = reinterpret_cast<const unsigned short*>(p);
+#pragma unroll
+    for (int s = 0; s < VEC; ++s) o[s] = __uint_as_float(((unsigned)q[s]) << 16);
+  }
+};
+
+// Workgroups are dispatched to the 8 XCDs round-robin by linear id.  Pass 1
+// maps linear id b to (row tile, chunk) so that every row tile of a chunk
+// lands on XCD b % 8: chunk = 8 * (s / tiles) + b % 8, tile = s % tiles with
+// s = b / 8.  Returns false for the padding ids of a ragged last group.
+__device__ __forceinline__ bool xcd_tile(int b, int tiles, int chunks, int& tile, int& chunk) {
+  const int x = b & 7, sidx = b >> 3;
+  tile = sidx % tiles;
+  chunk = 8 * (sidx / tiles) + x;
+  return chunk < chunks;
 }
 
 __device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
@@ -37,116 +118,188 @@ __device__ __forceinline__ floatx16 mfma32(float a, float b, floatx16 c) {
 __device__ __forceinline__ int mfma_row(int lane, int v) { return 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3); }
 
 // ------------------------------------------------------------------ pass 1
-// Grid (ceil(P/32), chunks); block of WPB waves.  Block (tp, c) owns rows
-// [32 tp, 32 tp + 32) and a contiguous range of column pairs; its waves take
-// the pairs round-robin.  Each block reduces its waves in LDS, writes one
-// partial tile, and the last block of a row tile to finish adds the chunks'
-// partials in chunk order (FP64) and writes Z.
-template <typename T, int WPB, int NTN>
-__global__ void __launch_bounds__(WPB * 64) k_pass1(const T* __restrict__ X, int64_t P, int64_t J, int r,
-                                                    const float* __restrict__ B, double* __restrict__ Z,
-                                                    float* __restrict__ ws, int* __restrict__ cnt,
-                                                    int* __restrict__ flag) {
-  __shared__ float red[WPB * NTN * 1024];
-  __shared__ int ticket;
-  const int tp = blockIdx.x, c = blockIdx.y, chunks = gridDim.y;
+// Grid of tiles x chunks blocks (XCD-aware order, see xcd_tile), NW waves per
+// block.  Block (tp, c) owns
+// the row tile [32 VEC tp, 32 VEC (tp+1)) and a contiguous range of column
+// pairs, which its waves take round-robin.  Lane i + 32h loads VEC
+// consecutive rows p0 + VEC i .. +VEC-1 of column 2q + h with one vector load;
+// element s feeds MFMA s, whose 32 result rows are p0 + VEC i' + s.  All VEC
+// MFMAs of a step share the right-interface operand B(a, j).  The next
+// step's loads are issued before the current step's MFMAs.  The waves' tiles
+// are added in LDS in wave order and the block writes one FP32 partial tile;
+// k_pass1_reduce adds the chunks' partials in chunk order in FP64.
+template <typename T, int VEC, int NW, int NTN>
+__global__ void __launch_bounds__(NW * 64) k_pass1(const T* __restrict__ X, int64_t P, int64_t J, int r,
+                                                   const float* __restrict__ B, float* __restrict__ part,
+                                                   int tiles, int chunks) {
+  constexpr int TILEF = NTN * VEC * 1024;
+  // LDS slots for the wave reduction: waves add into slot w % SLOTS in
+  // rounds, in wave order, so the sum is reproducible.
+  constexpr int SLOTS = (NW * TILEF <= 16384) ? NW : (16384 / TILEF);
+  __shared__ float red[SLOTS * TILEF];
+  int tp, c;
+  if (!xcd_tile((int)blockIdx.x, tiles, chunks, tp, c)) return;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t p0 = (int64_t)tp * 32;
+  const int64_t p0 = (int64_t)tp * 32 * VEC;
   const int64_t npairs = (J + 1) >> 1;
   const int64_t pb = npairs * c / chunks, pe = npairs * (c + 1) / chunks;
-  const int64_t prow = p0 + (lane & 31);
-  const bool rowok = prow < P;
+  const int64_t prow = p0 + (int64_t)VEC * (lane & 31);
+  const bool rowok = prow < P;  // P % VEC == 0, so a vector is all in or all out
   const int half = lane >> 5;
   const int acol = lane & 31;
-  floatx16 acc[NTN];
-#pragma unroll
-  for (int t = 0; t < NTN; ++t) acc[t] = floatx16{0};
-
-  constexpr int U = 8;
-  int64_t q = pb + w;
-  for (; q + (int64_t)(U - 1) * WPB < pe; q += (int64_t)U * WPB) {
-    float xa[U], bb[U][NTN];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int64_t j = 2 * (q + (int64_t)u * WPB) + half;
-      const bool jok = j < J;
-      xa[u] = (jok && rowok) ? ldf<T>(X + prow + P * j) : 0.f;
-#pragma unroll
-      for (int t = 0; t < NTN; ++t) {
-        const int a = acol + 32 * t;
-        bb[u][t] = (jok && a < r) ? B[a + (int64_t)r * j] : 0.f;
-      }
-    }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-#pragma unroll
-      for (int t = 0; t < NTN; ++t) acc[t] = mfma32(xa[u], bb[u][t], acc[t]);
-    }
-  }
-  for (; q < pe; q += WPB) {
-    const int64_t j = 2 * q + half;
-    const bool jok = j < J;
-    const float xa = (jok && rowok) ? ldf<T>(X + prow + P * j) : 0.f;
-#pragma unroll
-    for (int t = 0; t < NTN; ++t) {
-      const int a = acol + 32 * t;
-      const float b = (jok && a < r) ? B[a + (int64_t)r * j] : 0.f;
-      acc[t] = mfma32(xa, b, acc[t]);
-    }
-  }
-
-  // block reduction over waves
+  floatx16 acc[NTN][VEC];
 #pragma unroll
   for (int t = 0; t < NTN; ++t)
 #pragma unroll
-    for (int v = 0; v < 16; ++v) red[((w * NTN + t) * 16 + v) * 64 + lane] = acc[t][v];
-  __syncthreads();
-  float* part = ws + ((int64_t)tp * chunks + c) * (NTN * 1024);
-  for (int e = threadIdx.x; e < NTN * 1024; e += WPB * 64) {
-    float s = 0.f;
+    for (int s = 0; s < VEC; ++s) acc[t][s] = floatx16{0};
+
+  // Column pairs per load batch: the next batch is in flight while the MFMAs
+  // of the current one run (two batches stay under 63 outstanding loads).
+  constexpr int U = (VEC == 1) ? 8 : 4;
+  // Per-lane pointers of this wave's first column pair.  Rows past P (last
+  // tile only) read row P - VEC; columns past the chunk read its last column
+  // (pointer clamped).  Both are zeroed by masks applied at MFMA time, so the
+  // load batches themselves never wait on their data: the next batch stays
+  // in flight while the current one is multiplied.
+  const int64_t prow_c = rowok ? prow : P - VEC;
+  const float rmask = rowok ? 1.f : 0.f;
+  const int64_t j_first = 2 * (pb + w) + half;
+  const int64_t jend = (2 * pe < J) ? 2 * pe : J;
+  int acol_c[NTN];
+  float amask[NTN];
 #pragma unroll
-    for (int ww = 0; ww < WPB; ++ww) s += red[ww * NTN * 1024 + e];
-    part[e] = s;
+  for (int t = 0; t < NTN; ++t) {
+    const int a = acol + 32 * t;
+    acol_c[t] = a < r ? a : r - 1;
+    amask[t] = a < r ? 1.f : 0.f;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) ticket = atomicAdd(&cnt[tp], 1);
-  __syncthreads();
-  if (ticket != chunks - 1) return;
-  __threadfence();
-  // last block of this row tile: deterministic sum over chunks
-  int bad = 0;
-  for (int e = threadIdx.x; e < NTN * 1024; e += WPB * 64) {
-    double s = 0.0;
-    for (int cc = 0; cc < chunks; ++cc) s += (double)ws[((int64_t)tp * chunks + cc) * (NTN * 1024) + e];
-    const int t = e / 1024, v = (e % 1024) / 64, ln = e % 64;
-    const int64_t row = p0 + mfma_row(ln, v);
-    const int col = (ln & 31) + 32 * t;
-    if (row < P && col < r) {
-      Z[row + P * (int64_t)col] = s;
-      if (!isfinite(s)) bad = 1;
+  const int64_t xstep = 2 * (int64_t)NW * P;   // one column pair per wave step
+  const int64_t bstep = 2 * (int64_t)NW * r;
+  const T* xp = X + prow_c + P * j_first;
+  const T* xlast = X + prow_c + P * (jend - 1);
+  const float* bp = B + (int64_t)r * j_first;
+  const float* blast = B + (int64_t)r * (jend - 1);
+  const int64_t nsteps = (pe > pb + w) ? (pe - (pb + w) + NW - 1) / NW : 0;
+
+  float xa0[U][VEC], bb0[U][NTN], xa1[U][VEC], bb1[U][NTN];
+  auto load = [&](float (&xa)[U][VEC], float (&bb)[U][NTN], int64_t i0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const T* x = xp + (i0 + u) * xstep;
+      x = x < xlast ? x : xlast;
+      LdC<T, VEC>::get(x, xa[u]);
+      const float* b = bp + (i0 + u) * bstep;
+      b = b < blast ? b : blast;
+#pragma unroll
+      for (int t = 0; t < NTN; ++t) bb[u][t] = b[acol_c[t]];
+    }
+  };
+  auto compute = [&](const float (&xa)[U][VEC], const float (&bb)[U][NTN], int64_t i0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int64_t j = j_first + (i0 + u) * 2 * NW;
+      const float m = (j < jend) ? rmask : 0.f;
+#pragma unroll
+      for (int t = 0; t < NTN; ++t) {
+        const float b = bb[u][t] * amask[t];
+#pragma unroll
+        for (int s = 0; s < VEC; ++s) acc[t][s] = mfma32(xa[u][s] * m, b, acc[t][s]);
+      }
+    }
+  };
+  // Branch-free steady state: loads past the wave's last step read the
+  // clamped column and are masked, so the prefetch is unconditional.
+  if (nsteps > 0) {
+    // sched_barrier keeps each batch's loads together and ahead of the
+    // previous batch's MFMAs (the scheduler would otherwise interleave them).
+    load(xa0, bb0, 0);
+    for (int64_t i0 = 0; i0 < nsteps; i0 += 2 * U) {
+      __builtin_amdgcn_sched_barrier(0);
+      load(xa1, bb1, i0 + U);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(xa0, bb0, i0);
+      __builtin_amdgcn_sched_barrier(0);
+      load(xa0, bb0, i0 + 2 * U);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(xa1, bb1, i0 + U);
     }
   }
-  if (bad) atomicOr(flag, 1);
-  if (threadIdx.x == 0) cnt[tp] = 0;
+
+#pragma unroll
+  for (int round = 0; round < NW / SLOTS; ++round) {
+    if (w / SLOTS == round) {
+      float* slot = red + (w % SLOTS) * TILEF;
+#pragma unroll
+      for (int t = 0; t < NTN; ++t)
+#pragma unroll
+        for (int s = 0; s < VEC; ++s)
+#pragma unroll
+          for (int v = 0; v < 16; ++v) {
+            const int e = ((t * VEC + s) * 16 + v) * 64 + lane;
+            slot[e] = (round == 0) ? acc[t][s][v] : slot[e] + acc[t][s][v];
+          }
+    }
+    __syncthreads();
+  }
+  float* out = part + ((int64_t)tp * chunks + c) * TILEF;
+  for (int e = threadIdx.x; e < TILEF; e += NW * 64) {
+    float sum = 0.f;
+#pragma unroll
+    for (int ww = 0; ww < SLOTS; ++ww) sum += red[ww * TILEF + e];
+    out[e] = sum;
+  }
+}
+
+// Z(row, col) = sum over chunks of the partial tiles (FP64, chunk order).
+template <int VEC, int NTN>
+__global__ void __launch_bounds__(256) k_pass1_reduce(const float* __restrict__ part, int chunks, int64_t P, int r,
+                                                      double* __restrict__ Z, int* __restrict__ flag) {
+  constexpr int TILEF = NTN * VEC * 1024;
+  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t tp = g / TILEF;
+  const int e = (int)(g % TILEF);
+  const int64_t ntiles = (P + 32 * VEC - 1) / (32 * VEC);
+  if (tp >= ntiles) return;
+  const int t = e / (VEC * 1024), s = (e / 1024) % VEC, v = (e / 64) % 16, ln = e % 64;
+  const int64_t row = tp * 32 * VEC + (int64_t)VEC * mfma_row(ln, v) + s;
+  const int col = (ln & 31) + 32 * t;
+  if (row >= P || col >= r) return;
+  double sum = 0.0;
+  const float* p = part + tp * chunks * TILEF + e;
+  int cc = 0;
+  for (; cc + 8 <= chunks; cc += 8) {  // eight loads in flight, summed in chunk order
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(cc + u) * TILEF];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) sum += (double)v[u];
+  }
+  for (; cc < chunks; ++cc) sum += (double)p[(int64_t)cc * TILEF];
+  Z[row + P * (int64_t)col] = sum;
+  if (!isfinite(sum)) atomicOr(flag, 1);
 }
 
 // ------------------------------------------------------------------ pass 2
-// Grid ceil(J/32) blocks of 16 waves; block b owns columns [32 b, 32 b + 32)
+// Grid ceil(J/32) blocks of kPass2Waves waves; block b owns columns [32 b, 32 b + 32)
 // and all P rows.  Wave w owns the row slab [w*slab, (w+1)*slab) and stages it
-// through its own LDS area in chunks of up to kPass2SlabMax rows, so the slice
-// is read with consecutive lanes on consecutive rows of a column.  The MFMA's
-// reduction index k runs over rows: lane i + 32g supplies rows kk + 4g + s for
-// the four MFMAs s = 0..3 of a step, for both the slice (operand A = X^T) and
-// the left interface (operand B).  The 16 waves' partial 32x32 tiles are then
-// added in LDS in wave order and the block writes Y in FP64.
+// through its own LDS area in chunks of at most kPass2SlabMax rows, loading
+// VEC consecutive rows of a column per lane, so the slice is read in runs
+// along its contiguous index.  The MFMA's reduction index k runs over rows:
+// lane i + 32g supplies rows kk + 4g + s for the four MFMAs s = 0..3 of a
+// step, for both the slice (operand A = X^T) and the left interface
+// (operand B).  The waves' tiles are added in LDS in wave order and the
+// block writes Y in FP64.  The next chunk's slice loads are held in
+// registers while the current chunk's MFMAs run.
 constexpr int kLdp = kPass2SlabMax + 4;
 
-template <typename T, int NTN>
-__global__ void __launch_bounds__(1024) k_pass2(const T* __restrict__ X, int64_t P, int64_t J, int r,
-                                                const float* __restrict__ A, double* __restrict__ Y,
-                                                int* __restrict__ flag, int slab, int nchunk) {
+template <typename T, int VEC, int NTN>
+__global__ void __launch_bounds__(kPass2Waves * 64) k_pass2(const T* __restrict__ X, int64_t P, int64_t J, int r,
+                                                            const float* __restrict__ A, double* __restrict__ Y,
+                                                            int* __restrict__ flag, int slab, int nchunk) {
   extern __shared__ float lds[];
+  constexpr int PER_COL = kPass2SlabMax / VEC;           // vector loads per column and chunk
+  constexpr int NLD = (32 * PER_COL + 63) / 64;          // vector loads per lane and chunk
+  constexpr int KS = kPass2SlabMax / 8;                  // MFMA k-steps per chunk
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   float* Xs = lds + w * 32 * kLdp;
   const int64_t j0 = (int64_t)blockIdx.x * 32;
@@ -157,50 +310,116 @@ __global__ void __launch_bounds__(1024) k_pass2(const T* __restrict__ X, int64_t
 #pragma unroll
   for (int t = 0; t < NTN; ++t) acc[t] = floatx16{0};
 
-  for (int ch = 0; ch < nchunk; ++ch) {
-    const int64_t c0 = rb + (int64_t)ch * kPass2SlabMax;
-    int64_t rows = re - c0;
+  auto rows_of = [&](int ch) -> int {
+    int64_t rows = re - (rb + (int64_t)ch * kPass2SlabMax);
     if (rows < 0) rows = 0;
     if (rows > kPass2SlabMax) rows = kPass2SlabMax;
-    const int r8 = (int)((rows + 7) & ~7LL);
-    // stage X(c0 .. c0+r8, j0 .. j0+32) -> Xs[col][row]
-    for (int e = lane; e < 32 * r8; e += 64) {
-      const int col = e / r8, row = e - col * r8;
-      const int64_t jj = j0 + col;
-      float v = 0.f;
-      if (row < rows && jj < J) v = ldf<T>(X + (c0 + row) + P * jj);
-      Xs[col * kLdp + row] = v;
+    return (int)rows;
+  };
+  // slice loads of one chunk into registers (lane e -> column e / PER_COL)
+  float xr[NLD][VEC];
+  // Loads are unconditional (row and column clamped to the slice) so that
+  // the wait counts stay exact; out-of-range values are zeroed at the store.
+  static_assert((32 * PER_COL) % 64 == 0, "whole vector loads per lane");
+  auto load_chunk = [&](int ch) {
+    const int64_t c0 = rb + (int64_t)ch * kPass2SlabMax;
+#pragma unroll
+    for (int it = 0; it < NLD; ++it) {
+      const int e = lane + 64 * it;
+      const int col = e / PER_COL, row = (e - col * PER_COL) * VEC;
+      int64_t p = c0 + row;
+      p = p < P - VEC ? p : P - VEC;
+      int64_t jj = j0 + col;
+      jj = jj < J ? jj : J - 1;
+      Ld<T, VEC>::get(X + p + P * jj, xr[it]);
     }
+  };
+  auto store_chunk = [&](int ch) {
+    const int rows = rows_of(ch);
+#pragma unroll
+    for (int it = 0; it < NLD; ++it) {
+      const int e = lane + 64 * it;
+      const int col = e / PER_COL, row = (e - col * PER_COL) * VEC;
+      const bool colok = j0 + col < J;
+#pragma unroll
+      for (int s = 0; s < VEC; ++s) Xs[col * kLdp + row + s] = (colok && row + s < rows) ? xr[it][s] : 0.f;
+    }
+  };
+
+  if (nchunk > 0) load_chunk(0);
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int64_t c0 = rb + (int64_t)ch * kPass2SlabMax;
+    const int rows = rows_of(ch);
+    const int r8 = (rows + 7) & ~7;
+    store_chunk(ch);
     __syncthreads();
-    for (int kk = 0; kk < r8; kk += 8) {
-      const float4 xv = *reinterpret_cast<const float4*>(&Xs[jl * kLdp + kk + 4 * g]);
-      const int64_t pbase = c0 + kk + 4 * g;
+    // Interface fragments of every k-step (operand B of k-step k is
+    // A(c0 + 8k + 4g + s, a)), issued before the next chunk's slice loads:
+    // waits are in issue order, so the MFMAs can then start while the slice
+    // prefetch is still in flight.
+    float av[KS][NTN][4];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+      const int64_t pbase = c0 + 8 * k + 4 * g;
 #pragma unroll
       for (int t = 0; t < NTN; ++t) {
         const int a = jl + 32 * t;
-        float av[4];
+        const int ac = a < r ? a : r - 1;
+        if (VEC == 4) {
+          const int64_t pc = pbase < P - 3 ? pbase : P - 4;
+          const float4 q = *reinterpret_cast<const float4*>(A + pc + P * (int64_t)ac);
+          av[k][t][0] = q.x;
+          av[k][t][1] = q.y;
+          av[k][t][2] = q.z;
+          av[k][t][3] = q.w;
+        } else {
 #pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          const int64_t p = pbase + s;
-          av[s] = (a < r && p < c0 + rows) ? A[p + P * (int64_t)a] : 0.f;
+          for (int s = 0; s < 4; ++s) {
+            const int64_t p = pbase + s;
+            av[k][t][s] = A[(p < P ? p : P - 1) + P * (int64_t)ac];
+          }
         }
-        acc[t] = mfma32(xv.x, av[0], acc[t]);
-        acc[t] = mfma32(xv.y, av[1], acc[t]);
-        acc[t] = mfma32(xv.z, av[2], acc[t]);
-        acc[t] = mfma32(xv.w, av[3], acc[t]);
       }
+    }
+    auto mfma_chunk = [&]() {
+#pragma unroll
+      for (int k = 0; k < KS; ++k) {
+        if (8 * k >= r8) break;
+        const float4 xv = *reinterpret_cast<const float4*>(&Xs[jl * kLdp + 8 * k + 4 * g]);
+#pragma unroll
+        for (int t = 0; t < NTN; ++t) {
+          const int a = jl + 32 * t;
+          const float am = a < r ? 1.f : 0.f;
+          float b[4];
+#pragma unroll
+          for (int s = 0; s < 4; ++s) b[s] = (8 * k + 4 * g + s < rows) ? av[k][t][s] * am : 0.f;
+          acc[t] = mfma32(xv.x, b[0], acc[t]);
+          acc[t] = mfma32(xv.y, b[1], acc[t]);
+          acc[t] = mfma32(xv.z, b[2], acc[t]);
+          acc[t] = mfma32(xv.w, b[3], acc[t]);
+        }
+      }
+    };
+    // Separate paths with and without the prefetch keep the wait counts
+    // exact on each (a merged path would wait for the prefetch too).
+    if (ch + 1 < nchunk) {
+      __builtin_amdgcn_sched_barrier(0);
+      load_chunk(ch + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_chunk();
+    } else {
+      mfma_chunk();
     }
     __syncthreads();
   }
-  // cross-wave reduction in LDS (reuses the staging area)
+  // cross-wave reduction in LDS (reuses the staging area), wave order
   int bad = 0;
 #pragma unroll
   for (int t = 0; t < NTN; ++t) {
 #pragma unroll
     for (int v = 0; v < 16; ++v) lds[(w * 16 + v) * 64 + lane] = acc[t][v];
     __syncthreads();
-    {
-      const int e = threadIdx.x;  // 1024 entries of the tile
+    for (int e = threadIdx.x; e < 1024; e += kPass2Waves * 64) {
       float s = 0.f;
 #pragma unroll
       for (int ww = 0; ww < kPass2Waves; ++ww) s += lds[ww * 1024 + e];
@@ -217,50 +436,105 @@ __global__ void __launch_bounds__(1024) k_pass2(const T* __restrict__ X, int64_t
   if (bad) atomicOr(flag, 1);
 }
 
-template <typename T>
-hipError_t pass1_t(hipStream_t st, const T* X, int64_t P, int64_t J, int r, const float* B, double* Z, float* ws,
-                   int* cnt, int* flag, int chunks, int waves) {
-  const dim3 grid((unsigned)pass1_tiles(P), (unsigned)chunks);
-  if (r <= 32) {
-    if (waves == 4) hipLaunchKernelGGL((k_pass1<T, 4, 1>), grid, dim3(256), 0, st, X, P, J, r, B, Z, ws, cnt, flag);
-    else hipLaunchKernelGGL((k_pass1<T, 8, 1>), grid, dim3(512), 0, st, X, P, J, r, B, Z, ws, cnt, flag);
-  } else {
-    hipLaunchKernelGGL((k_pass1<T, 4, 2>), grid, dim3(256), 0, st, X, P, J, r, B, Z, ws, cnt, flag);
-  }
+// ------------------------------------------------------------------ launch
+template <typename T, int VEC, int NW, int NTN>
+hipError_t launch_p1(hipStream_t st, const T* X, int64_t P, int64_t J, int r, const float* B, double* Z, float* ws,
+                     int* flag, int chunks) {
+  const int tiles = (int)((P + 32 * VEC - 1) / (32 * VEC));
+  const int groups = (chunks + 7) / 8;
+  hipLaunchKernelGGL((k_pass1<T, VEC, NW, NTN>), dim3(tiles * groups * 8), dim3(NW * 64), 0, st, X, P, J, r, B, ws,
+                     tiles, chunks);
+  constexpr int TILEF = NTN * VEC * 1024;
+  const int64_t threads = (int64_t)tiles * TILEF;
+  hipLaunchKernelGGL((k_pass1_reduce<VEC, NTN>), dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, st, ws,
+                     chunks, P, r, Z, flag);
   return hipGetLastError();
 }
 
 template <typename T>
-hipError_t pass2_t(hipStream_t st, const T* X, int64_t P, int64_t J, int r, const float* A, double* Y, int* flag) {
+hipError_t pass1_t(hipStream_t st, const T* X, const Pass1Plan& pl, int64_t P, int64_t J, int r, const float* B,
+                   double* Z, float* ws, int* flag) {
+  const int c = pl.chunks;
+  if (pl.ntn == 1) {
+    if (pl.vec == 4) {
+      if (pl.waves == 8) return launch_p1<T, 4, 8, 1>(st, X, P, J, r, B, Z, ws, flag, c);
+      return launch_p1<T, 4, 4, 1>(st, X, P, J, r, B, Z, ws, flag, c);
+    }
+    if (pl.vec == 2) {
+      if (pl.waves == 8) return launch_p1<T, 2, 8, 1>(st, X, P, J, r, B, Z, ws, flag, c);
+      return launch_p1<T, 2, 4, 1>(st, X, P, J, r, B, Z, ws, flag, c);
+    }
+    if (pl.waves == 16) return launch_p1<T, 1, 16, 1>(st, X, P, J, r, B, Z, ws, flag, c);
+    return launch_p1<T, 1, 8, 1>(st, X, P, J, r, B, Z, ws, flag, c);
+  }
+  if (pl.vec == 2) return launch_p1<T, 2, 4, 2>(st, X, P, J, r, B, Z, ws, flag, c);
+  return launch_p1<T, 1, 8, 2>(st, X, P, J, r, B, Z, ws, flag, c);
+}
+
+template <typename T, int VEC>
+hipError_t pass2_v(hipStream_t st, const T* X, int64_t P, int64_t J, int r, const float* A, double* Y, int* flag) {
   int64_t slab = (P + kPass2Waves - 1) / kPass2Waves;
   slab = (slab + 7) & ~7LL;
   const int nchunk = (int)((slab + kPass2SlabMax - 1) / kPass2SlabMax);
   const size_t lds = (size_t)kPass2Waves * 32 * kLdp * sizeof(float);
   const dim3 grid((unsigned)((J + 31) / 32));
+  const dim3 block(kPass2Waves * 64);
   if (r <= 32)
-    hipLaunchKernelGGL((k_pass2<T, 1>), grid, dim3(1024), lds, st, X, P, J, r, A, Y, flag, (int)slab, nchunk);
+    hipLaunchKernelGGL((k_pass2<T, VEC, 1>), grid, block, lds, st, X, P, J, r, A, Y, flag, (int)slab, nchunk);
   else
-    hipLaunchKernelGGL((k_pass2<T, 2>), grid, dim3(1024), lds, st, X, P, J, r, A, Y, flag, (int)slab, nchunk);
+    hipLaunchKernelGGL((k_pass2<T, VEC, 2>), grid, block, lds, st, X, P, J, r, A, Y, flag, (int)slab, nchunk);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t pass2_t(hipStream_t st, const T* X, int64_t P, int64_t J, int r, const float* A, double* Y, int* flag) {
+  if (P % 4 == 0) return pass2_v<T, 4>(st, X, P, J, r, A, Y, flag);
+  return pass2_v<T, 1>(st, X, P, J, r, A, Y, flag);
+}
+
+template <typename T, int VEC, int NTN>
+hipError_t attr2(int lds) {
+  return hipFuncSetAttribute((const void*)k_pass2<T, VEC, NTN>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
 }
 
 }  // namespace
 
-int pass1_tiles(int64_t P) { return (int)((P + 31) / 32); }
-
-size_t pass1_ws_floats(int64_t P, int r, int chunks) {
-  const int ntn = r <= 32 ? 1 : 2;
-  return (size_t)pass1_tiles(P) * chunks * ntn * 1024;
+Pass1Plan pass1_plan(int64_t P, int64_t J, int r, int cus) {
+  Pass1Plan pl;
+  pl.ntn = r <= 32 ? 1 : 2;
+  // Widest row vector that divides P: 128-row tiles (one 512-byte run per
+  // column per half-wave) measured fastest on the 1080 x 5760 slice.
+  if (pl.ntn == 1) {
+    pl.vec = (P % 4 == 0) ? 4 : (P % 2 == 0 ? 2 : 1);
+    pl.waves = (pl.vec == 4) ? 8 : (pl.vec == 2 ? 4 : 8);
+  } else {
+    pl.vec = (P % 2 == 0) ? 2 : 1;
+    pl.waves = (pl.vec == 2) ? 4 : 8;
+  }
+  pl.tiles = (int)((P + 32 * pl.vec - 1) / (32 * pl.vec));
+  // about one block per CU, at least 16 column pairs per wave
+  const int64_t pairs = (J + 1) / 2;
+  int64_t chunks = ((int64_t)cus + pl.tiles - 1) / pl.tiles;
+  const int64_t maxc = pairs / (16 * pl.waves);
+  if (chunks > maxc) chunks = maxc;
+  if (chunks < 1) chunks = 1;
+  pl.chunks = (int)chunks;
+  return finish_plan(pl, P);
 }
 
-hipError_t pass1(hipStream_t st, const void* X, tt_dtype xdt, int64_t P, int64_t J, int r, const float* B, double* Z,
-                 float* ws, int* cnt, int* flag, int chunks, int waves) {
+Pass1Plan finish_plan(Pass1Plan pl, int64_t P) {
+  pl.tiles = (int)((P + 32 * pl.vec - 1) / (32 * pl.vec));
+  pl.ws_floats = (size_t)pl.tiles * pl.chunks * pl.ntn * pl.vec * 1024;
+  return pl;
+}
+
+hipError_t pass1(hipStream_t st, const void* X, tt_dtype xdt, const Pass1Plan& pl, int64_t P, int64_t J, int r,
+                 const float* B, double* Z, float* ws, int* flag) {
   if (r < 1 || r > 64) return hipErrorInvalidValue;
   switch (xdt) {
-    case TT_F32: return pass1_t(st, static_cast<const float*>(X), P, J, r, B, Z, ws, cnt, flag, chunks, waves);
-    case TT_F64: return pass1_t(st, static_cast<const double*>(X), P, J, r, B, Z, ws, cnt, flag, chunks, waves);
-    case TT_BF16:
-      return pass1_t(st, static_cast<const __hip_bfloat16*>(X), P, J, r, B, Z, ws, cnt, flag, chunks, waves);
+    case TT_F32: return pass1_t(st, static_cast<const float*>(X), pl, P, J, r, B, Z, ws, flag);
+    case TT_F64: return pass1_t(st, static_cast<const double*>(X), pl, P, J, r, B, Z, ws, flag);
+    case TT_BF16: return pass1_t(st, static_cast<const __hip_bfloat16*>(X), pl, P, J, r, B, Z, ws, flag);
   }
   return hipErrorInvalidValue;
 }
@@ -278,19 +552,17 @@ hipError_t pass2(hipStream_t st, const void* X, tt_dtype xdt, int64_t P, int64_t
 
 hipError_t pass_setup() {
   const int lds = (int)((size_t)kPass2Waves * 32 * kLdp * sizeof(float));
-  hipError_t e;
-  e = hipFuncSetAttribute((const void*)k_pass2<float, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_pass2<float, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_pass2<double, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_pass2<double, 2>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e != hipSuccess) return e;
-  e = hipFuncSetAttribute((const void*)k_pass2<__hip_bfloat16, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute((const void*)k_pass2<__hip_bfloat16, 2>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                             lds);
+  hipError_t e = hipSuccess;
+#define TT_A2(T)                                    \
+  if (e == hipSuccess) e = attr2<T, 4, 1>(lds);     \
+  if (e == hipSuccess) e = attr2<T, 4, 2>(lds);     \
+  if (e == hipSuccess) e = attr2<T, 1, 1>(lds);     \
+  if (e == hipSuccess) e = attr2<T, 1, 2>(lds);
+  TT_A2(float)
+  TT_A2(double)
+  TT_A2(__hip_bfloat16)
+#undef TT_A2
+  return e;
 }
 
 }  // namespace ttk

@@ -16,7 +16,7 @@ tt_status set_error(tt_status st, const char* msg);
 constexpr int kQrThreads = 256;
 // Rows of the slice staged per wave in pass 2 (multiple of 8).
 constexpr int kPass2SlabMax = 72;
-constexpr int kPass2Waves = 16;
+constexpr int kPass2Waves = 8;
 
 // ---------------------------------------------------------------- chain (FP64)
 // C(i,j) = sum_k A(i,k) B(k,j) with element strides; optional FP32 copy of C.
@@ -55,12 +55,21 @@ hipError_t convert_out(hipStream_t st, const double* src, void* dst, tt_dtype dt
 
 // ---------------------------------------------------------------- passes (FP32)
 // Pass 1: Z(p,a) = sum_j X(p,j) B(a,j), X P x J (p fastest) of dtype `xdt`,
-// B r x J FP32; Z written FP64 (P x r column-major).  Partials: ws (floats),
-// counters: cnt (ints, zero on entry, left zero).  Sets *flag if Z non-finite.
-hipError_t pass1(hipStream_t st, const void* X, tt_dtype xdt, int64_t P, int64_t J, int r,
-                 const float* B, double* Z, float* ws, int* cnt, int* flag, int chunks, int waves);
-size_t pass1_ws_floats(int64_t P, int r, int chunks);
-int pass1_tiles(int64_t P);
+// B r x J FP32; Z written FP64 (P x r column-major) from FP32 partial tiles
+// (ws, plan.ws_floats floats) added in FP64.  Sets *flag if Z is non-finite.
+struct Pass1Plan {
+  int vec = 1;        // rows per lane (row tile = 32 vec)
+  int ntn = 1;        // 32-column MFMA tiles of the rank (r <= 32 ntn)
+  int waves = 8;      // waves per block
+  int tiles = 1;      // row tiles
+  int chunks = 1;     // column chunks
+  size_t ws_floats = 0;
+};
+Pass1Plan pass1_plan(int64_t P, int64_t J, int r, int cus);
+// Recomputes tiles and ws_floats after vec/ntn/waves/chunks were set.
+Pass1Plan finish_plan(Pass1Plan plan, int64_t P);
+hipError_t pass1(hipStream_t st, const void* X, tt_dtype xdt, const Pass1Plan& plan, int64_t P, int64_t J, int r,
+                 const float* B, double* Z, float* ws, int* flag);
 
 // Pass 2: Y(a,j) = sum_p A(p,a) X(p,j); A P x r FP32 column-major; Y FP64
 // r x J column-major.  Sets *flag if Y non-finite.

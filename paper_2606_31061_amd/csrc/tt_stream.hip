@@ -118,7 +118,6 @@ struct tt_stream {
   double* Y[2] = {nullptr, nullptr};
   double* qrwork = nullptr;
   float* ws = nullptr;
-  int* cnt = nullptr;
   int* flag = nullptr;
   int* rejected = nullptr;
   int64_t* tdev = nullptr;
@@ -127,7 +126,7 @@ struct tt_stream {
   double* recon[2] = {nullptr, nullptr};
   void* stage = nullptr;
   size_t stage_bytes = 0;
-  int p1_chunks = 1, p1_waves = 8;
+  ttk::Pass1Plan p1;
   int rejected_seen = 0;
   int64_t pushes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evcopy = nullptr;
@@ -247,8 +246,7 @@ tt_status launch_update(tt_stream* s, const void* X, tt_dtype xdt) {
   if (ks == m) TT_HIP(ttk::to_f32(st, s->g_of(s->work), s->B32, r[m]));
 
   // pass 1
-  TT_HIP(ttk::pass1(st, X, xdt, Pk[ks], Jk[ks], (int)r[ks], s->B32, s->Z, s->ws, s->cnt, s->flag, s->p1_chunks,
-                    s->p1_waves));
+  TT_HIP(ttk::pass1(st, X, xdt, s->p1, Pk[ks], Jk[ks], (int)r[ks], s->B32, s->Z, s->ws, s->flag));
 
   // head: Z_k for k < kstar from the pre-sweep cores
   auto Zof = [&](int k) -> double* { return k == ks ? s->Z : s->Zk[k]; };
@@ -399,16 +397,9 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
   }
   for (int k = ks; k <= m_; ++k) ymax = std::max(ymax, r[k] * s->Jk[k]);
 
-  // chunks of pass 1: enough blocks to cover every CU about once
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
-  const int tiles = ttk::pass1_tiles(s->Pk[ks]);
-  const int64_t pairs = (s->Jk[ks] + 1) / 2;
-  int64_t chunks = (cus + tiles - 1) / tiles;
-  if (chunks > pairs / 8) chunks = pairs / 8;
-  if (chunks < 1) chunks = 1;
-  s->p1_chunks = (int)chunks;
-  s->p1_waves = 8;
+  s->p1 = ttk::pass1_plan(s->Pk[ks], s->Jk[ks], (int)r[ks], cus);
 
   bool ok = true;
   auto D = [&](size_t n) -> double* {
@@ -438,8 +429,7 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
   s->Y[0] = D(ymax);
   s->Y[1] = D(ymax);
   s->qrwork = D(qrmax);
-  s->ws = F(ttk::pass1_ws_floats(s->Pk[ks], (int)r[ks], s->p1_chunks));
-  s->cnt = static_cast<int*>(dev_alloc(s, sizeof(int) * (tiles + 1)));
+  s->ws = F(s->p1.ws_floats);
   s->flag = static_cast<int*>(dev_alloc(s, sizeof(int) * 2));
   s->rejected = s->flag + 1;
   s->tdev = static_cast<int64_t*>(dev_alloc(s, sizeof(int64_t)));
@@ -447,14 +437,13 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
     s->hist_cap = cfg->history_capacity > 0 ? cfg->history_capacity : 1024;
     s->hist = D((size_t)s->hist_cap * r[m_]);
   }
-  if (!ok || !s->cnt || !s->flag || !s->tdev) return bail(TT_ERR_OOM, "device allocation failed");
+  if (!ok || !s->flag || !s->tdev) return bail(TT_ERR_OOM, "device allocation failed");
 
 #define TT_HIP_BAIL(call)                                                                   \
   do {                                                                                        \
     hipError_t e_ = (call);                                                                   \
     if (e_ != hipSuccess) return bail(TT_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
   } while (0)
-  TT_HIP_BAIL(hipMemsetAsync(s->cnt, 0, sizeof(int) * (tiles + 1), s->stream));
   TT_HIP_BAIL(hipMemsetAsync(s->flag, 0, sizeof(int) * 2, s->stream));
   TT_HIP_BAIL(hipMemsetAsync(s->tdev, 0, sizeof(int64_t), s->stream));
   TT_HIP_BAIL(hipEventCreate(&s->ev0));

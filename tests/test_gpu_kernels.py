@@ -40,9 +40,9 @@ def test_pass1_matches_numpy(P, J, r, xdt):
     Xd = torch.from_numpy(np.asfortranarray(X).reshape(-1, order="F").copy()).cuda().to(tdt)
     Bd = torch.from_numpy(np.asfortranarray(B).reshape(-1, order="F").copy()).cuda()
     Zd = torch.full((P * r,), float("nan"), dtype=torch.float64, device="cuda")
-    ws = torch.zeros(binding.tt_kernel_pass1_workspace(P, J, r), dtype=torch.uint8, device="cuda")
+    ws = torch.full((binding.tt_kernel_pass1_workspace(P, J, r),), 255, dtype=torch.uint8, device="cuda")
     flag = torch.zeros(1, dtype=torch.int32, device="cuda")
-    for rep in range(2):  # second call checks the workspace counters were left at zero
+    for rep in range(2):  # the workspace needs no initialisation and can be reused
         assert binding.tt_kernel_pass1(Xd, P, J, r, Bd, Zd, ws, flag) == 0
         torch.cuda.synchronize()
         Z = Zd.cpu().numpy().reshape(P, r, order="F")
@@ -51,7 +51,6 @@ def test_pass1_matches_numpy(P, J, r, xdt):
         bound = np.abs(Xr) @ np.abs(B.astype(np.float64)).T
         assert np.all(np.abs(Z - ref) <= 2e-6 * bound + 1e-30), rep
     assert int(flag.item()) == 0
-    assert int(ws[-4 * ((P + 31) // 32 + 1):].sum().item()) == 0
 
 
 @pytest.mark.parametrize("P,J,r", CASES)
