@@ -116,6 +116,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--profile-ops", action="store_true",
+                    help="also print the per-operation times of the update's chain (stderr)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: every stream's update runs on a single device and this build "
@@ -168,6 +170,17 @@ def main():
     dev_ms = s.last_push_ms()
     s.close()
     log(f"latency p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
+
+    if args.profile_ops:
+        sp = TTStream(spec.modes, spec.ranks, init=(cores, g), profile_ops=True)
+        for i in range(4):
+            sp.push(pool[i % pool_n])
+        prof = sp.op_profile()
+        sp.close()
+        tot = sum(p[2] for p in prof)
+        log(f"chain operations of one update: {len(prof)} ops, {tot:.1f} us on the chain workgroup")
+        for i, (kind, dims, us) in enumerate(prof):
+            log(f"  op {i:3d} {kind:6s} m={dims[0]:6d} n={dims[1]:6d} k={dims[2]:6d} {us:9.2f} us")
 
     kt = time_pass_kernels(torch, pool, P, J, r, args.kernel_reps)
     b1, b2 = pass_bytes(P, J, r)

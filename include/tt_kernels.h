@@ -34,11 +34,14 @@ size_t tt_kernel_pass1_workspace(int64_t P, int64_t J, int32_t r);
 tt_status tt_kernel_pass2(const void* X, tt_dtype x_dtype, int64_t P, int64_t J, int32_t r,
                           const float* A, double* Y, int32_t* nonfinite_flag, void* hip_stream);
 
-/* Thin QR of an m x n FP64 matrix (m >= n >= 1) as used to re-orthogonalise a
- * core (Algorithm 1): M = Q R, Q^T Q = I, diag(R) >= 0; a column whose
- * remaining norm is <= 64 eps ||M||_F gets the identity reflector.  M, Q
- * column-major with leading dimension m; R n x n (may be NULL).  workspace
- * must hold m*n doubles (only used when the matrix exceeds the LDS). */
+/* Thin QR of an m x n FP64 matrix (m >= n >= 1, n <= 256) as used to
+ * re-orthogonalise a core (Algorithm 1; Section 3.4.2): M = Q R, Q^T Q = I,
+ * diag(R) >= 0.  Well-conditioned matrices with n <= 32 take CholeskyQR2
+ * (two Gram/Cholesky passes); otherwise, or when a Cholesky pivot falls below
+ * (1e-6 ||M||_F)^2, Householder, where a column whose remaining norm is
+ * <= 64 eps ||M||_F gets the identity reflector (R_jj = 0).  M, Q column-major
+ * with leading dimension m (Q may alias M); R n x n (may be NULL).
+ * workspace must hold m*n doubles.  TT_ERR_UNSUPPORTED for n > 256. */
 tt_status tt_kernel_qr(int32_t m, int32_t n, const double* M, double* Q, double* R,
                        double* workspace, void* hip_stream);
 

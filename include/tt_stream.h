@@ -91,6 +91,7 @@ typedef struct {
 /* Flags. */
 #define TT_FLAG_SYNC_PUSH 0x1u   /* push waits for its update and reports NONFINITE */
 #define TT_FLAG_NO_ORTHO 0x2u    /* ablation: skip the LQ sweep and the QR steps    */
+#define TT_FLAG_PROFILE_OPS 0x4u /* time every chain operation (tt_stream_op_profile) */
 
 /* Create a stream.  The initial cores are the paper's random initialisation
  * (Algorithm 1, first line): taken from init_cores, else i.i.d. N(0,1) from a
@@ -157,6 +158,18 @@ tt_status tt_clamp_ranks(int32_t m, const int64_t* modes, const int64_t* ranks_i
 /* Device time of the last completed push in milliseconds (HIP events around
  * the update on the handle's stream).  Waits for the handle's work. */
 tt_status tt_stream_last_push_ms(tt_stream* s, float* ms);
+
+/* Per-operation device times of the last push, for a stream created with
+ * TT_FLAG_PROFILE_OPS.  The update's small dense steps run as a list of
+ * operations on one workgroup; each gets a start and end stamp from the
+ * device wall clock.  For op i < min(count, cap): kinds[i] = 1 GEMM, 2 QR,
+ * 3 g normalisation, 4 copy, 5 commit; dims[3i..3i+2] = (m, n, k) (GEMM:
+ * rows, columns, depth; QR: rows, columns, reflector cap); us[i] = duration
+ * in microseconds.  Operations launched over the whole GPU and the slice
+ * passes are not listed (a kernel trace times them).  Waits for the handle's
+ * work.  Errors: INVALID_ARG (null), STATE (flag not set or no push yet). */
+tt_status tt_stream_op_profile(tt_stream* s, int64_t cap, int32_t* kinds, int64_t* dims, double* us,
+                               int64_t* count);
 
 /* Description of the calling thread's last error (never NULL). */
 const char* tt_last_error_string(void);

@@ -30,6 +30,7 @@ STATUS_NAMES = {0: "TT_OK", 1: "TT_ERR_INVALID_ARG", 2: "TT_ERR_SHAPE", 3: "TT_E
 TT_F64, TT_F32, TT_BF16 = 0, 1, 2
 TT_FLAG_SYNC_PUSH = 0x1
 TT_FLAG_NO_ORTHO = 0x2
+TT_FLAG_PROFILE_OPS = 0x4
 
 
 class TTError(RuntimeError):
@@ -84,6 +85,8 @@ def load_library(path: str = LIB_PATH):
         "tt_stream_get_history": (c_int, [sv, POINTER(c_double), c_int64, POINTER(c_int64)]),
         "tt_clamp_ranks": (c_int, [c_int32, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64)]),
         "tt_stream_last_push_ms": (c_int, [sv, POINTER(c_float)]),
+        "tt_stream_op_profile": (c_int, [sv, c_int64, POINTER(c_int32), POINTER(c_int64), POINTER(c_double),
+                                         POINTER(c_int64)]),
         "tt_last_error_string": (c_char_p, []),
         "tt_version": (c_char_p, []),
         "tt_kernel_pass1": (c_int, [sv, c_int, c_int64, c_int64, c_int32, sv, sv, sv, sv, sv]),
@@ -188,7 +191,8 @@ class TTStream:
     """
 
     def __init__(self, modes, ranks, init=None, *, seed: int = 0, stream=None, keep_history: bool = False,
-                 history_capacity: int = 0, split_point: int = 0, sync_push: bool = False):
+                 history_capacity: int = 0, split_point: int = 0, sync_push: bool = False,
+                 profile_ops: bool = False):
         self.modes = tuple(int(v) for v in modes)
         self.ranks = tuple(int(v) for v in ranks)
         self.n = int(np.prod(self.modes))
@@ -202,7 +206,9 @@ class TTStream:
         sp = int(stream.cuda_stream) if stream is not None else self._current_stream_handle()
         self._h = tt_stream_create(self.modes, self.ranks, init_cores=flat, seed=seed, hip_stream=sp,
                                    keep_history=keep_history, history_capacity=history_capacity,
-                                   split_point=split_point, flags=TT_FLAG_SYNC_PUSH if sync_push else 0)
+                                   split_point=split_point,
+                                   flags=(TT_FLAG_SYNC_PUSH if sync_push else 0)
+                                   | (TT_FLAG_PROFILE_OPS if profile_ops else 0))
         self._lib = load_library()
 
     @staticmethod
@@ -292,6 +298,19 @@ class TTStream:
         v = c_float()
         _check(self._lib.tt_stream_last_push_ms(self._h, byref(v)), "tt_stream_last_push_ms")
         return float(v.value)
+
+    def op_profile(self):
+        """Per-operation device times (us) of the last push as a list of
+        (kind, (m, n, k), us); needs flags including TT_FLAG_PROFILE_OPS."""
+        cnt = c_int64()
+        _check(self._lib.tt_stream_op_profile(self._h, 0, None, None, None, byref(cnt)), "tt_stream_op_profile")
+        n = cnt.value
+        kinds = (c_int32 * max(n, 1))()
+        dims = (c_int64 * max(3 * n, 1))()
+        us = (c_double * max(n, 1))()
+        _check(self._lib.tt_stream_op_profile(self._h, n, kinds, dims, us, byref(cnt)), "tt_stream_op_profile")
+        names = {1: "gemm", 2: "qr", 3: "normg", 4: "copy", 5: "commit"}
+        return [(names.get(kinds[i], "?"), (dims[3 * i], dims[3 * i + 1], dims[3 * i + 2]), us[i]) for i in range(n)]
 
     def close(self) -> None:
         if self._h is not None and self._h.value:

@@ -1,0 +1,983 @@
+// The update's small FP64 chain, run as lists of operations by one workgroup.
+//
+// Between the two slice passes the update is a sequential chain of small
+// dense steps (Algorithm 1): the LQ sweep of the right-orthogonalisation
+// (Section 3.4.1), the right interfaces, and for every core the local solve of
+// Eq. 5 followed by a thin QR (Section 3.4.2).  Each step is at most a few
+// hundred KB, so a step is latency-bound and a kernel launch per step would
+// cost more than the step.  Here a host-built list of ChainOp records is
+// executed by ONE workgroup of 16 waves (k_chain): consecutive operations are
+// separated by a workgroup barrier only.  Contractions large enough to need
+// the whole GPU are launched separately by the runtime.
+//
+// Every operation first copies its operands from global memory into LDS with
+// many loads in flight, then computes from LDS:
+//   GEMM    C = A B (FP64 v_mfma_f64_16x16x4) with element strides, optional
+//           FP32 copy of C.  Operands are staged in k-chunks; each wave keeps
+//           at least four independent accumulators so the matrix pipe stays
+//           busy.
+//   QR      thin QR M = Q R, diag(R) >= 0 (FP64).  Fast path (n <= 32,
+//           m <= 512, matrix held in registers): CholeskyQR2 -- Gram matrix,
+//           Cholesky factor and its inverse, Q1 = M R1^-1, then the same on
+//           Q1, whose Gram matrix I + E is so close to I that its factor is
+//           taken to first order in E when |E| <= 1e-7.  When a Cholesky pivot
+//           is below (1e-7 ||M||_F)^2 the matrix is ill-conditioned or
+//           rank-deficient and the operation falls back to Householder with
+//           the identity-reflector rule: a column whose remaining norm is
+//           <= tol ||M||_F gets no reflector and R_jj = 0.  `rho` < n caps the
+//           number of proper reflectors (later columns get the identity
+//           reflector); the runtime uses it where the rank is bounded by
+//           construction.
+//   NORMG   g normalisation of Section 3.4.1 (G_m absorbs ||g||).
+//   COPY    copy of n doubles with an optional FP32 copy.
+//   COMMIT  history append and time step, or restore of the old state when
+//           the slice was not finite.
+#include "tt_internal.h"
+
+namespace ttk {
+namespace {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int kCT = kChainThreads;
+constexpr int kCW = kCT / 64;
+
+// LDS layout (in doubles; 160 KB).  GEMM and QR operations never overlap in
+// time, so their regions alias.  The small QR buffers come first so that
+// their addresses fit the LDS instructions' immediate offsets.
+constexpr int kLdsTotal = 20480;
+// GEMM: staged k-chunks of A and B, split-k partial blocks
+constexpr int kStageCap = 14336;
+constexpr int kLdsPart = 14336;     // 4096
+// QR
+constexpr int kLdsRow = 0;          // 256: rows of R broadcast to the wave
+constexpr int kLdsRed = 256;        // 64: reductions
+constexpr int kLdsFlag = 320;       // 8: flags
+constexpr int kLdsTau = 328;        // 256: Householder tau
+constexpr int kLdsSgn = 584;        // 256: Householder signs
+constexpr int kLdsW = 840;          // 1024: Gram matrix, then R2
+constexpr int kLdsR1 = 1864;        // 1024: R1
+constexpr int kLdsRi = 2888;        // 1056: R1^-1, then R2^-1 (leading dimension 33)
+constexpr int kLdsMs = 3944;        // 16448: the matrix (up to 512 rows x 32, odd leading dimension)
+constexpr int kQrRows = 512;
+constexpr int kMaxHouseholderCols = 256;
+
+// The chain kernels' dynamic LDS.  Operands are addressed by offsets into
+// it, so every access compiles to an LDS instruction with a 32-bit address.
+extern __shared__ double s_lds[];
+
+constexpr double kCholRel = 1e-7;   // pivot threshold of the fast path, relative to ||M||_F
+constexpr double kFirstOrder = 1e-7;
+
+__device__ __forceinline__ int round16(int x) { return (x + 15) & ~15; }
+
+__device__ __forceinline__ double read_lane(double x, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Workgroup sum (fixed order: reproducible); every thread gets the total.
+__device__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int i = 0; i < kCW; ++i) s += red[i];
+  return s;
+}
+
+__device__ double block_max(double v, double* red) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wid] = v;
+  __syncthreads();
+  double s = red[0];
+#pragma unroll
+  for (int i = 1; i < kCW; ++i) s = fmax(s, red[i]);
+  return s;
+}
+
+// ------------------------------------------------------------------ MFMA on LDS
+
+// A matrix in LDS: element (i, j) at s_lds[off + i * rs + j * cs],
+// zero-padded to whole 16-row blocks and 4-value k-steps so that the inner
+// loop needs no bounds checks.
+struct View {
+  int off;
+  int rs, cs;
+};
+
+// How a wave takes part in a product of nbm x nbn output blocks over nks
+// k-steps.  With at least 16 blocks each wave owns blocks w, w+16, ... (at
+// most 4), split into P phases over the k-steps when it owns fewer than 3 so
+// that at least three chains are in flight.  With fewer blocks and `split`
+// the k-steps are divided into ks groups spread over the idle waves and the
+// partial blocks are added afterwards in a fixed order; without `split` wave
+// w < nb takes block w alone.  Slot q (q < na) accumulates block blk(q) over
+// the k-steps s0 + ph(q) + P t below s1.
+struct Plan {
+  int na, P;   // slots, phases per block
+  int w, nbm, nb;
+  int sb;      // the block of a k-split wave, or -1
+  int s0, s1;  // k-step range
+  int ks, kg;  // k groups, this wave's group (-1: idle)
+};
+
+__device__ __forceinline__ int slot_blk(const Plan& p, int q) { return p.sb >= 0 ? p.sb : p.w + kCW * (q / p.P); }
+__device__ __forceinline__ int slot_ph(const Plan& p, int q) { return q % p.P; }
+
+__device__ __forceinline__ Plan wave_plan(int nbm, int nb, int nks, int w, bool split) {
+  Plan p;
+  p.w = w;
+  p.nbm = nbm;
+  p.nb = nb;
+  p.sb = -1;
+  p.na = 0;
+  p.P = 1;
+  p.ks = 1;
+  p.kg = 0;
+  p.s0 = 0;
+  p.s1 = nks;
+  if (nb >= kCW) {
+    const int mine = (nb - w + kCW - 1) / kCW;  // blocks w, w+16, ... below nb (at most 4)
+    p.P = mine >= 3 ? 1 : (mine == 2 ? 2 : 4);
+    p.na = mine * p.P;
+    return p;
+  }
+  int ks = split ? kCW / nb : 1;
+  if (ks > nks) ks = nks;
+  if (ks < 1) ks = 1;
+  p.ks = ks;
+  if (w < nb * ks) {
+    p.sb = w % nb;
+    p.kg = w / nb;
+    p.s0 = nks * p.kg / ks;
+    p.s1 = nks * (p.kg + 1) / ks;
+    p.P = 4;
+    p.na = 4;
+  } else {
+    p.kg = -1;
+  }
+  return p;
+}
+
+// acc[q] += A(block row of slot q, k-steps) B(k-steps, block column of slot q)
+// for the slots of plan p over k-steps [s0, s1) (4 values of k per step).
+// MFMA operand layout: lane l supplies A(l%16, l/16) and B(l/16, l%16); the
+// result holds D(4v + l/16, l%16) in element v.  The slots are independent,
+// so the matrix pipe overlaps them.  The operand pointers advance by P
+// k-steps; the last, partial round loads only what it uses.
+template <int NA>
+__device__ __forceinline__ void mma_slots(const View& A, const View& B, const Plan& p, int s0, int s1, v4d* acc) {
+  const int lane = threadIdx.x & 63;
+  const int li = lane & 15, lk = lane >> 4;
+  int pa[NA], pb[NA], ph[NA];
+#pragma unroll
+  for (int q = 0; q < NA; ++q) {
+    const int b = slot_blk(p, q);
+    ph[q] = slot_ph(p, q);
+    const int k0 = 4 * (s0 + ph[q]) + lk;
+    pa[q] = A.off + (16 * (b % p.nbm) + li) * A.rs + k0 * A.cs;
+    pb[q] = B.off + k0 * B.rs + (16 * (b / p.nbm) + li) * B.cs;
+  }
+  const int da = 4 * p.P * A.cs, db = 4 * p.P * B.rs;
+  int s = s0;
+  for (; s + p.P <= s1; s += p.P) {
+    double a[NA], b[NA];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      a[q] = s_lds[pa[q]];
+      b[q] = s_lds[pb[q]];
+      pa[q] += da;
+      pb[q] += db;
+    }
+#pragma unroll
+    for (int q = 0; q < NA; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc[q], 0, 0, 0);
+  }
+  if (s < s1) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q)
+      if (s + ph[q] < s1) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(s_lds[pa[q]], s_lds[pb[q]], acc[q], 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void mma_dispatch(const View& A, const View& B, const Plan& p, int s0, int s1, v4d* acc) {
+  switch (p.na) {
+    case 1: mma_slots<1>(A, B, p, s0, s1, acc); break;
+    case 2: mma_slots<2>(A, B, p, s0, s1, acc); break;
+    case 3: mma_slots<3>(A, B, p, s0, s1, acc); break;
+    case 4: mma_slots<4>(A, B, p, s0, s1, acc); break;
+    default: break;
+  }
+}
+
+// Finishes a product by storing each block straight from the registers:
+// every block's phase slots are added in order.  store(i, j, value) receives
+// every output element of the i < M, j < N range.  Ends with a barrier.
+// Only for plans without k split (used for small outputs in LDS).
+template <class Store>
+__device__ void finish_direct(const Plan& p, int M, int N, const v4d* acc, Store store) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (q < p.na && slot_ph(p, q) == 0) {
+      v4d s = acc[q];
+#pragma unroll
+      for (int f = 1; f < 4; ++f)
+        if (q + f < 4 && f < p.P) s += acc[q + f < 4 ? q + f : 3];
+      const int b = slot_blk(p, q);
+      const int i0 = (b % p.nbm) * 16, j0 = (b / p.nbm) * 16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = i0 + 4 * v + (lane >> 4), j = j0 + (lane & 15);
+        if (i < M && j < N) store(i, j, s[v]);
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Finishes a product through LDS: each wave puts its block sums (or, with k
+// split, its partial block) in buf[((kg nb + b) 4 + v) 64 + l]; after a
+// barrier the threads walk the output with i fastest (ifast) or j fastest,
+// adding the k groups in order, so that consecutive threads store to
+// consecutive addresses.  Ends with a barrier.
+template <class Store>
+__device__ void finish_lds(const Plan& p, int M, int N, const v4d* acc, double* buf, bool ifast, Store store) {
+  const int lane = threadIdx.x & 63;
+  if (p.ks == 1) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q < p.na && slot_ph(p, q) == 0) {
+        v4d s = acc[q];
+#pragma unroll
+        for (int f = 1; f < 4; ++f)
+          if (q + f < 4 && f < p.P) s += acc[q + f < 4 ? q + f : 3];
+        const int b = slot_blk(p, q);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) buf[(b * 4 + v) * 64 + lane] = s[v];
+      }
+    }
+  } else if (p.kg >= 0) {
+    const v4d s = acc[0] + acc[1] + acc[2] + acc[3];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) buf[((p.kg * p.nb + p.sb) * 4 + v) * 64 + lane] = s[v];
+  }
+  __syncthreads();
+  const int rows = 16 * p.nbm, total = p.nb * 256, cols = total / rows;
+  // (i, j) of element e, advanced without division
+  const int nf = ifast ? rows : cols, df = kCT % nf, ds = kCT / nf;
+  int f = threadIdx.x % nf, sl = threadIdx.x / nf;
+  for (int e = threadIdx.x; e < total; e += kCT) {
+    const int i = ifast ? f : sl, j = ifast ? sl : f;
+    f += df;
+    sl += ds;
+    if (f >= nf) {
+      f -= nf;
+      ++sl;
+    }
+    if (i < M && j < N) {
+      const int b = (i >> 4) + p.nbm * (j >> 4), il = i & 15, jl = j & 15;
+      const int o = (b * 4 + (il >> 2)) * 64 + ((il & 3) << 4) + jl;
+      double s = 0.0;
+      for (int g = 0; g < p.ks; ++g) s += buf[g * p.nb * 256 + o];
+      store(i, j, s);
+    }
+  }
+  __syncthreads();
+}
+
+// C = A B with both operands already in LDS (zero-padded views), nks
+// k-steps, at most 64 output blocks; no k split.  Ends with a barrier.
+template <class Store>
+__device__ void gemm_lds(int M, int N, int nks, const View& A, const View& B, Store store) {
+  const int w = threadIdx.x >> 6;
+  const int nbm = (M + 15) >> 4, nbn = (N + 15) >> 4;
+  const Plan p = wave_plan(nbm, nbm * nbn, nks, w, false);
+  v4d acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = (v4d){0.0, 0.0, 0.0, 0.0};
+  if (p.na > 0) mma_dispatch(A, B, p, p.s0, p.s1, acc);
+  finish_direct(p, M, N, acc, store);
+}
+
+// ------------------------------------------------------------------ GEMM (global operands)
+
+struct Gemm {
+  int64_t M, N, K;
+  const double* A;
+  int64_t ars, acs;
+  const double* B;
+  int64_t brs, bcs;
+  double* C;
+  int64_t crs, ccs;
+  float* C32;
+};
+
+// Copies the rows x cols block whose element (i, j) is src[i * rs + j * cs]
+// into LDS at dst[i * drs + j * dcs], zero outside i < r_valid, j < c_valid.
+// The walk follows the smaller source stride so that the loads coalesce,
+// with eight loads in flight per thread.
+__device__ void stage(int dst, int drs, int dcs, int rows, int cols, const double* src, int64_t rs, int64_t cs,
+                      int r_valid, int c_valid) {
+  constexpr int U = 8;  // loads in flight per thread
+  const int total = rows * cols;
+  // walk (f, s) = (fast, slow) index; each thread advances by kCT elements
+  const bool rfast = rs <= cs;
+  const int nf = rfast ? rows : cols;
+  const int fv = rfast ? r_valid : c_valid, sv = rfast ? c_valid : r_valid;
+  const int64_t fs = rfast ? rs : cs, ss = rfast ? cs : rs;
+  const int dfs = rfast ? drs : dcs, dss = rfast ? dcs : drs;
+  const int df = kCT % nf, ds = kCT / nf;
+  int f = threadIdx.x % nf, sl = threadIdx.x / nf;
+  for (int e0 = threadIdx.x; e0 < total; e0 += U * kCT) {
+    double x[U];
+    int fi[U], si[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      fi[u] = f;
+      si[u] = sl;
+      x[u] = (e0 + u * kCT < total && f < fv && sl < sv) ? src[f * fs + sl * ss] : 0.0;
+      f += df;
+      sl += ds;
+      if (f >= nf) {
+        f -= nf;
+        ++sl;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (e0 + u * kCT < total) s_lds[dst + fi[u] * dfs + si[u] * dss] = x[u];
+  }
+}
+
+// C = A B from global operands.  The output is cut into tiles of at most
+// 64 blocks; for each tile the needed rows of A and columns of B go through
+// LDS one k-chunk at a time.
+__device__ void wg_gemm(const Gemm& g) {
+  const int M = (int)g.M, N = (int)g.N, K = (int)g.K;
+  if (M <= 0 || N <= 0) {
+    __syncthreads();
+    return;
+  }
+  const int w = threadIdx.x >> 6;
+  const int nbm_all = (M + 15) >> 4, nbn_all = (N + 15) >> 4;
+  const int nks = (K + 3) >> 2;
+  const int TR = nbm_all < 64 ? nbm_all : 64;
+  const int TC = nbn_all < 64 / TR ? nbn_all : 64 / TR;
+  double* part = s_lds + kLdsPart;
+  for (int cb0 = 0; cb0 < nbn_all; cb0 += TC) {
+    for (int rb0 = 0; rb0 < nbm_all; rb0 += TR) {
+      const int nbm = nbm_all - rb0 < TR ? nbm_all - rb0 : TR;
+      const int nbn = nbn_all - cb0 < TC ? nbn_all - cb0 : TC;
+      const int Mp = 16 * nbm, Np = 16 * nbn;
+      const int Mv = M - 16 * rb0, Nv = N - 16 * cb0;
+      const Plan p = wave_plan(nbm, nbm * nbn, nks, w, true);
+      // without k split the whole LDS may hold operands (the blocks are
+      // collected at offset 0 afterwards); with it the partial blocks need
+      // their own region
+      int chunk = (p.ks == 1 ? kLdsTotal : kStageCap) / (4 * (Mp + Np));  // k-steps staged at a time
+      if (chunk < 1) chunk = 1;
+      v4d acc[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = (v4d){0.0, 0.0, 0.0, 0.0};
+      const double* Ag = g.A + (int64_t)16 * rb0 * g.ars;
+      const double* Bg = g.B + (int64_t)16 * cb0 * g.bcs;
+      for (int c0 = 0; c0 < nks; c0 += chunk) {
+        const int c1 = c0 + chunk < nks ? c0 + chunk : nks;
+        const int kc = 4 * (c1 - c0);
+        const int As = 0;            // Mp x kc, element (i, k) at i + Mp k
+        const int Bs = Mp * kc;      // kc x Np, element (k, j) at j + Np k
+        __syncthreads();
+        stage(As, 1, Mp, Mp, kc, Ag + (int64_t)4 * c0 * g.acs, g.ars, g.acs, Mv, K - 4 * c0);
+        stage(Bs, Np, 1, kc, Np, Bg + (int64_t)4 * c0 * g.brs, g.brs, g.bcs, K - 4 * c0, Nv);
+        __syncthreads();
+        const int s0 = p.s0 > c0 ? p.s0 : c0, s1 = p.s1 < c1 ? p.s1 : c1;
+        if (p.na > 0 && s0 < s1) {
+          const View A{As, 1, Mp}, B{Bs, Np, 1};
+          mma_dispatch(A, B, p, s0 - c0, s1 - c0, acc);
+        }
+      }
+      __syncthreads();
+      const int64_t ro = (int64_t)16 * rb0, co = (int64_t)16 * cb0;
+      finish_lds(p, Mv, Nv, acc, p.ks == 1 ? s_lds : part, g.crs <= g.ccs, [&](int i, int j, double v) {
+        const int64_t o = (ro + i) * g.crs + (co + j) * g.ccs;
+        if (g.C) g.C[o] = v;
+        if (g.C32) g.C32[o] = (float)v;
+      });
+    }
+  }
+}
+
+// ------------------------------------------------------------------ Cholesky
+
+// 1/sqrt(d) for d > 0: hardware estimate and NEWTON Newton steps (two give
+// full FP64).
+template <int NEWTON>
+__device__ __forceinline__ double rsqrt_pos(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+  const double h = 0.5 * d;
+#pragma unroll
+  for (int i = 0; i < NEWTON; ++i) y = y * fma(-h * y, y, 1.5);
+  return y;
+}
+
+// Cholesky factor of the 32 x 32 symmetric matrix W (LDS, column-major) and
+// its inverse, by one wave.  Lanes 0..31 hold column c of W and turn it into
+// column c of R (W = R^T R, R upper triangular); lanes 32..63 hold column c of
+// X, which starts as the identity and receives the same elimination steps, so
+// that it ends as R^-T.  Step j scales row j by 1/sqrt(pivot) and removes
+// R(j,:)^T R(j,:) from the rows below.  The steps go in blocks of four: inside
+// a block the few entries needed come from single lanes, and the rows below
+// receive the block's four updates at once from an LDS broadcast, so there
+// are eight LDS round trips instead of thirty-two.  Only pivots of the first
+// n columns are tested against thr2.  Writes R (zeros below the diagonal,
+// leading dimension 32) and R^-1 (leading dimension 33); R may alias W.
+// NEWTON = 1 leaves the pivots' square roots good to about 1e-10 relative,
+// which suffices when a second CholeskyQR pass corrects the factor: R and
+// R^-1 are exact inverses of each other either way.
+template <int NEWTON>
+__device__ __forceinline__ bool chol_inv32(const double* W, double* R, double* Ri, double* rowbuf, double thr2,
+                                           int n) {
+  const int lane = threadIdx.x & 63;
+  int c = lane & 31;
+  // opaque to the optimiser: keeps the identity set-up below from being
+  // hoisted out of the operation loop (32 live values would spill)
+  asm volatile("" : "+v"(c));
+  const bool xh = lane >= 32;
+  double v[32];
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    const double w = W[i + 32 * c];
+    v[i] = xh ? (i == c ? 1.0 : 0.0) : w;
+  }
+  bool ok = true;
+#pragma unroll
+  for (int jb = 0; jb < 32; jb += 4) {
+#pragma unroll
+    for (int j = jb; j < jb + 4; ++j) {
+      const double d = read_lane(v[j], j);
+      ok = ok && (j >= n || d > thr2);
+      v[j] *= rsqrt_pos<NEWTON>(d);
+#pragma unroll
+      for (int i = j + 1; i < jb + 4; ++i) v[i] = fma(-read_lane(v[j], i), v[j], v[i]);
+    }
+    if (jb + 4 < 32) {
+      double* mine = rowbuf + 4 * lane;
+      mine[0] = v[jb];
+      mine[1] = v[jb + 1];
+      mine[2] = v[jb + 2];
+      mine[3] = v[jb + 3];
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int i0 = jb + 4; i0 < 32; i0 += 4) {
+#pragma unroll
+        for (int i = i0; i < i0 + 4; ++i) {
+          const double* r = rowbuf + 4 * i;  // R(jb..jb+3, i), written by lane i
+          v[i] = fma(-r[0], v[jb], v[i]);
+          v[i] = fma(-r[1], v[jb + 1], v[i]);
+          v[i] = fma(-r[2], v[jb + 2], v[i]);
+          v[i] = fma(-r[3], v[jb + 3], v[i]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 32; ++i) {
+    double* dst = xh ? Ri + c + 33 * i : R + i + 32 * c;
+    *dst = (xh || i <= c) ? v[i] : 0.0;
+  }
+  return ok;
+}
+
+// ------------------------------------------------------------------ QR
+
+struct Qr {
+  int m, n, rho;
+  const double* M;
+  int64_t mrs, mcs;
+  double* Q;
+  int64_t qrs, qcs;
+  double* R;     // n x n column-major, or null
+  double* aux;   // m * n doubles of device scratch
+  double tol;
+};
+
+// Householder factorisation of the m x n column-major matrix A (leading
+// dimension lda) in place: R on and above the diagonal, the reflector vectors
+// (unit leading entry implied) below it, tau[j] their scalars,
+// H_j = I - tau_j v_j v_j^T, H_j x = beta e_1 with beta = -sign(x_1) ||x||.
+// Column j gets the identity reflector (tau = 0, zeroed from the diagonal
+// down) when its remaining norm is <= thr, or once rho proper reflectors
+// have been built (the rank is then exhausted: without pivoting the
+// independent columns may be anywhere, so this counts reflectors, not
+// columns).
+__device__ void hh_factor(double* A, int m, int n, int lda, double thr, int rho, bool need_r, double* tau,
+                          double* red) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  int built = 0;
+  for (int j = 0; j < n; ++j) {
+    double* cj = A + (int64_t)j * lda;
+    double nrm = 0.0;
+    if (built >= rho && !need_r) {
+      // rank exhausted and R not wanted: the remaining columns are identity
+      // reflectors; only their tau is needed
+      for (int c = j + tid; c < n; c += kCT) tau[c] = 0.0;
+      __syncthreads();
+      return;
+    }
+    if (built < rho) {
+      double p = 0.0;
+      for (int i = j + tid; i < m; i += kCT) {
+        const double x = cj[i];
+        p = fma(x, x, p);
+      }
+      nrm = sqrt(block_sum(p, red));
+    }
+    const double alpha = cj[j];
+    __syncthreads();
+    if (!(nrm > thr)) {
+      for (int i = j + tid; i < m; i += kCT) cj[i] = 0.0;
+      if (tid == 0) tau[j] = 0.0;
+      __syncthreads();
+      continue;
+    }
+    ++built;
+    const double beta = alpha >= 0.0 ? -nrm : nrm;
+    const double scal = 1.0 / (alpha - beta);
+    for (int i = j + 1 + tid; i < m; i += kCT) cj[i] *= scal;
+    const double t = (beta - alpha) / beta;
+    __syncthreads();
+    if (tid == 0) {
+      cj[j] = beta;
+      tau[j] = t;
+    }
+    for (int c = j + 1 + wid; c < n; c += kCW) {
+      double* cc = A + (int64_t)c * lda;
+      double d = (lane == 0) ? cc[j] : 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) d = fma(cj[i], cc[i], d);
+      d = wave_sum(d);
+      const double tw = t * d;
+      if (lane == 0) cc[j] -= tw;
+      for (int i = j + 1 + lane; i < m; i += 64) cc[i] = fma(-tw, cj[i], cc[i]);
+    }
+    __syncthreads();
+  }
+}
+
+// Overwrites the factored A with the thin Q = H_0 ... H_{n-1} [I; 0]
+// (backward accumulation) and flips column j when sgn[j] < 0.  Columns with
+// the identity reflector (tau = 0) hold no reflector data, so they all become
+// unit vectors in one pass; each proper reflector then costs two barriers.
+__device__ void hh_form_q(double* A, int m, int n, int lda, const double* tau, const double* sgn) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int j = 0; j < n; ++j)
+    if (tau[j] == 0.0) {
+      double* cj = A + (int64_t)j * lda;
+      for (int i = tid; i < m; i += kCT) cj[i] = (i == j) ? 1.0 : 0.0;
+    }
+  __syncthreads();
+  for (int j = n - 1; j >= 0; --j) {
+    const double t = tau[j];
+    if (t == 0.0) continue;
+    double* cj = A + (int64_t)j * lda;
+    for (int c = j + 1 + wid; c < n; c += kCW) {
+      double* cc = A + (int64_t)c * lda;
+      double d = (lane == 0) ? cc[j] : 0.0;
+      for (int i = j + 1 + lane; i < m; i += 64) d = fma(cj[i], cc[i], d);
+      d = wave_sum(d);
+      const double tw = t * d;
+      if (lane == 0) cc[j] -= tw;
+      for (int i = j + 1 + lane; i < m; i += 64) cc[i] = fma(-tw, cj[i], cc[i]);
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += kCT) {
+      double v;
+      if (i < j) v = 0.0;
+      else if (i == j) v = 1.0 - t;
+      else v = -t * cj[i];
+      cj[i] = v;
+    }
+    __syncthreads();  // the next reflector reads this column
+  }
+  for (int j = 0; j < n; ++j) {
+    if (sgn[j] < 0.0) {
+      double* cj = A + (int64_t)j * lda;
+      for (int i = tid; i < m; i += kCT) cj[i] = -cj[i];
+    }
+  }
+  __syncthreads();
+}
+
+// Householder QR of q.M, already copied into A (column-major, leading
+// dimension lda; LDS or the scratch buffer).
+__device__ void householder_qr(const Qr& q, double* A, int lda) {
+  double* tau = s_lds + kLdsTau;
+  double* sgn = s_lds + kLdsSgn;
+  double* red = s_lds + kLdsRed;
+  const int m = q.m, n = q.n, tid = threadIdx.x;
+  double p = 0.0;
+  for (int j = 0; j < n; ++j)
+    for (int i = tid; i < m; i += kCT) {
+      const double x = A[i + (int64_t)j * lda];
+      p = fma(x, x, p);
+    }
+  const double fro = sqrt(block_sum(p, red));
+  hh_factor(A, m, n, lda, q.tol * fro, q.rho, q.R != nullptr, tau, red);
+  for (int j = tid; j < n; j += kCT) sgn[j] = (tau[j] != 0.0 && A[j + (int64_t)j * lda] < 0.0) ? -1.0 : 1.0;
+  __syncthreads();
+  if (q.R) {
+    for (int e = tid; e < n * n; e += kCT) {
+      const int i = e % n, j = e / n;
+      q.R[e] = (i <= j) ? sgn[i] * A[i + (int64_t)j * lda] : 0.0;
+    }
+  }
+  __syncthreads();
+  hh_form_q(A, m, n, lda, tau, sgn);
+  for (int64_t e = tid; e < (int64_t)m * n; e += kCT) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    q.Q[i * q.qrs + j * q.qcs] = A[i + (int64_t)j * lda];
+  }
+  __syncthreads();
+}
+
+// Partial Gram blocks of a wave's 32-row stripe held in row fragments
+// f[s][cb] = X(r0 + 4s + l/16, 16 cb + l%16): blocks (0,0), (1,0), (1,1) of
+// X^T X go to part[(3 w + blk) * 256 + 64 v + l] (zero for a stripe wholly
+// below the matrix, live = false); after a barrier the 16 stripes are added
+// in order into W (32 x 32, column-major, mirrored).
+__device__ __forceinline__ void stripe_gram(const double (&f)[8][2], bool live, double* part, double* W) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  v4d g00 = {0.0, 0.0, 0.0, 0.0}, g10 = g00, g11 = g00;
+  if (live) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      g00 = __builtin_amdgcn_mfma_f64_16x16x4f64(f[s][0], f[s][0], g00, 0, 0, 0);
+      g10 = __builtin_amdgcn_mfma_f64_16x16x4f64(f[s][1], f[s][0], g10, 0, 0, 0);
+      g11 = __builtin_amdgcn_mfma_f64_16x16x4f64(f[s][1], f[s][1], g11, 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    part[(3 * w + 0) * 256 + 64 * v + lane] = g00[v];
+    part[(3 * w + 1) * 256 + 64 * v + lane] = g10[v];
+    part[(3 * w + 2) * 256 + 64 * v + lane] = g11[v];
+  }
+  __syncthreads();
+  if (tid < 768) {
+    const int blk = tid >> 8, e = tid & 255, v = e >> 6, l = e & 63;
+    const int bi = blk == 0 ? 0 : 1, bj = blk == 2 ? 1 : 0;
+    double sum = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < kCW; ++ww) sum += part[(3 * ww + blk) * 256 + e];
+    const int i = 16 * bi + 4 * v + (l >> 4), j = 16 * bj + (l & 15);
+    W[i + 32 * j] = sum;
+    if (bi != bj) W[j + 32 * i] = sum;
+  }
+  __syncthreads();
+}
+
+// CholeskyQR2 of an m x n matrix (m <= 512, n <= 32) with the data in
+// registers: wave w owns rows 32w .. 32w+31.  Row fragments (rows along the
+// MFMA k index) feed the Gram matrices, column fragments (rows along the
+// block index) feed Q = M R^-1.  Only the 32 x 32 Gram matrices and
+// triangular factors go through LDS, plus one transposition of Q1.  Returns
+// false, with nothing written, when a pivot test fails.
+__device__ bool cholqr2_reg(const Qr& q) {
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int m = q.m, n = q.n;
+  const int r0 = 32 * w;
+  const bool live = r0 < m;  // this wave's stripe holds rows of the matrix
+  double* part = s_lds + kLdsMs;  // 12288 doubles, then the Q1 transposition (ld = 513)
+  double* W = s_lds + kLdsW;
+  double* R1 = s_lds + kLdsR1;
+  double* Ri = s_lds + kLdsRi;
+  double* rowbuf = s_lds + kLdsRow;
+  double* red = s_lds + kLdsRed;
+  int* flag = reinterpret_cast<int*>(s_lds + kLdsFlag);
+  constexpr int ldq = 513;
+
+  // pass 1: W = M^T M from row fragments
+  double f[8][2];
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const int row = r0 + 4 * s + lk, col = 16 * cb + li;
+      f[s][cb] = (row < m && col < n) ? q.M[row * q.mrs + col * q.mcs] : 0.0;
+    }
+  __syncthreads();
+  stripe_gram(f, live, part, W);
+  {
+    const int i = tid & 31, j = tid >> 5;
+    if (i >= n || j >= n) W[i + 32 * j] = (i == j) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  double fro2 = 0.0;
+  for (int i = 0; i < n; ++i) fro2 += W[i * 33];
+  if (tid < 64) {
+    const bool ok = chol_inv32<1>(W, R1, Ri, rowbuf, kCholRel * kCholRel * fro2, n);
+    if (tid == 0) flag[0] = ok ? 1 : 0;
+  }
+  __syncthreads();
+  if (!flag[0]) return false;
+
+  // Q1 = M R1^-1: column fragments of M (second read, cached), result in
+  // row-fragment order: block (t, cb) element v is Q1(r0 + 16t + 4v + l/16, 16cb + l%16)
+  {
+    double g[2][8];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int kc = 0; kc < 8; ++kc) {
+        const int row = r0 + 16 * t + li, col = 4 * kc + lk;
+        g[t][kc] = (row < m && col < n) ? q.M[row * q.mrs + col * q.mcs] : 0.0;
+      }
+    v4d acc[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) acc[t][cb] = (v4d){0.0, 0.0, 0.0, 0.0};
+    if (live) {
+      // R^-1 is upper triangular: column block 0 only meets k < 16
+#pragma unroll
+      for (int kc = 0; kc < 8; ++kc) {
+        const double b1 = Ri[(4 * kc + lk) + 33 * (16 + li)];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[t][kc], b1, acc[t][1], 0, 0, 0);
+        if (kc < 4) {
+          const double b0 = Ri[(4 * kc + lk) + 33 * li];
+#pragma unroll
+          for (int t = 0; t < 2; ++t) acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[t][kc], b0, acc[t][0], 0, 0, 0);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) f[4 * t + v][cb] = acc[t][cb][v];
+  }
+  __syncthreads();  // Ri is read above and rewritten below
+  // pass 2: W = Q1^T Q1 = I + E
+  stripe_gram(f, live, part, W);
+  const int i = tid & 31, j = tid >> 5;
+  const double e = (i < n && j < n) ? W[i + 32 * j] - (i == j ? 1.0 : 0.0) : 0.0;
+  const double emax = block_max(fabs(e), red);
+  if (emax <= kFirstOrder) {
+    // R2 = I + U and R2^-1 = I - U to first order, U the upper triangle of E
+    // with half its diagonal (error O(|E|^2)); R2 overwrites W
+    const double u = (i < j) ? e : (i == j ? 0.5 * e : 0.0);
+    W[i + 32 * j] = (i == j ? 1.0 : 0.0) + u;
+    Ri[i + 33 * j] = (i == j ? 1.0 : 0.0) - u;
+    __syncthreads();
+  } else {
+    if (i >= n || j >= n) W[i + 32 * j] = (i == j) ? 1.0 : 0.0;
+    __syncthreads();
+    if (tid < 64) {
+      const bool ok = chol_inv32<2>(W, W, Ri, rowbuf, 0.25, n);
+      if (tid == 0) flag[0] = ok ? 1 : 0;
+    }
+    __syncthreads();
+    if (!flag[0]) return false;
+  }
+  // Q = Q1 R2^-1: Q1 goes through LDS to become column fragments
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) part[(r0 + 4 * s + lk) + ldq * (16 * cb + li)] = f[s][cb];
+  __syncthreads();
+  {
+    v4d acc[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) acc[t][cb] = (v4d){0.0, 0.0, 0.0, 0.0};
+    if (live) {
+#pragma unroll
+      for (int kc = 0; kc < 8; ++kc) {
+        const double b1 = Ri[(4 * kc + lk) + 33 * (16 + li)];
+        const double b0 = kc < 4 ? Ri[(4 * kc + lk) + 33 * li] : 0.0;
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const double a = part[(r0 + 16 * t + li) + ldq * (4 * kc + lk)];
+          if (kc < 4) acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b0, acc[t][0], 0, 0, 0);
+          acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b1, acc[t][1], 0, 0, 0);
+        }
+      }
+    }
+    // Q goes back through LDS so that the global stores are contiguous
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) part[(r0 + 16 * t + 4 * v + lk) + ldq * (16 * cb + li)] = acc[t][cb][v];
+    __syncthreads();
+    const bool ifast = q.qrs <= q.qcs;
+    for (int e = tid; e < m * n; e += kCT) {
+      const int row = ifast ? e % m : e / n, col = ifast ? e / m : e % n;
+      q.Q[row * q.qrs + col * q.qcs] = part[row + ldq * col];
+    }
+  }
+  if (q.R) {
+    const View R2v{kLdsW, 1, 32}, R1v{kLdsR1, 1, 32};
+    gemm_lds(n, n, 8, R2v, R1v, [&](int ii, int jj, double v) { q.R[ii + n * jj] = v; });
+  }
+  __syncthreads();
+  return true;
+}
+
+__device__ void wg_qr(const Qr& q) {
+  const int m = q.m, n = q.n;
+  if (q.rho >= n && m <= kQrRows && n <= 32 && cholqr2_reg(q)) return;
+  if (m <= kQrRows && n <= 32) {
+    // Householder in LDS
+    const int mp = round16(m);
+    const int ld = mp + 1;  // odd: walks across columns hit distinct banks
+    __syncthreads();
+    stage(kLdsMs, 1, ld, mp, 32, q.M, q.mrs, q.mcs, m, n);
+    __syncthreads();
+    householder_qr(q, s_lds + kLdsMs, ld);
+    return;
+  }
+  // larger matrices: Householder in the device scratch buffer
+  const int tid = threadIdx.x;
+  for (int64_t e = tid; e < (int64_t)m * n; e += kCT) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    q.aux[e] = q.M[i * q.mrs + j * q.mcs];
+  }
+  __syncthreads();
+  householder_qr(q, q.aux, m);
+}
+
+// ------------------------------------------------------------------ ops
+
+__device__ __forceinline__ void exec_op(const ChainOp& op) {
+  const int tid = threadIdx.x;
+  switch (op.type) {
+    case kOpGemm:
+      wg_gemm(Gemm{op.m, op.n, op.k, op.a, op.ars, op.acs, op.b, op.brs, op.bcs, op.c, op.crs, op.ccs, op.c32});
+      break;
+    case kOpQr:
+      wg_qr(Qr{(int)op.m, (int)op.n, op.rho, op.a, op.ars, op.acs, op.c, op.crs, op.ccs, op.r, op.aux, op.tol});
+      break;
+    case kOpNormG: {
+      // a = g in, c = g out (m = r_m); b = G_m in, r = G_m out (k elements)
+      double p = 0.0;
+      for (int i = tid; i < op.m; i += kCT) p = fma(op.a[i], op.a[i], p);
+      const double nu = sqrt(block_sum(p, s_lds + kLdsRed));
+      if (nu > 0.0) {
+        const double inv = 1.0 / nu;
+        for (int i = tid; i < op.m; i += kCT) op.c[i] = op.a[i] * inv;
+        for (int64_t e = tid; e < op.k; e += kCT) op.r[e] = op.b[e] * nu;
+      } else {
+        for (int i = tid; i < op.m; i += kCT) op.c[i] = (i == 0) ? 1.0 : 0.0;
+        for (int64_t e = tid; e < op.k; e += kCT) op.r[e] = op.b[e];
+      }
+      __syncthreads();
+      break;
+    }
+    case kOpCopy:
+      for (int64_t e = tid; e < op.m; e += kCT) {
+        const double x = op.a[e];
+        if (op.c) op.c[e] = x;
+        if (op.c32) op.c32[e] = (float)x;
+      }
+      __syncthreads();
+      break;
+    case kOpCommit: {
+      // a = new g (m = r_m); b = old state, c = new state (k doubles)
+      const int f = *op.flag;
+      const int64_t t = *op.tdev;
+      if (f == 0) {
+        if (op.hist && op.hist_cap > 0) {
+          const int64_t row = t % op.hist_cap;
+          for (int i = tid; i < op.m; i += kCT) op.hist[row * op.m + i] = op.a[i];
+        }
+      } else {
+        for (int64_t e = tid; e < op.k; e += kCT) op.c[e] = op.b[e];
+      }
+      __syncthreads();
+      if (tid == 0) {
+        if (f == 0) *op.tdev = t + 1;
+        else *op.rejected += 1;
+        *op.flag = 0;
+      }
+      __syncthreads();
+      break;
+    }
+    default:
+      break;
+  }
+}
+
+__global__ void __launch_bounds__(kCT) k_chain(const ChainOp* __restrict__ ops, int count, int64_t* trace) {
+  for (int i = 0; i < count; ++i) {
+    const ChainOp op = ops[i];
+    if (trace && threadIdx.x == 0) trace[2 * i] = (int64_t)wall_clock64();
+    exec_op(op);
+    __syncthreads();
+    if (trace && threadIdx.x == 0) trace[2 * i + 1] = (int64_t)wall_clock64();
+  }
+}
+
+__global__ void __launch_bounds__(kCT) k_chain_one(ChainOp op) { exec_op(op); }
+
+constexpr size_t kChainLds = (size_t)kLdsTotal * sizeof(double);
+bool g_chain_ready = false;
+
+}  // namespace
+
+hipError_t chain_setup(size_t lds_limit) {
+  if (lds_limit < kChainLds) return hipErrorInvalidValue;
+  hipError_t e = hipFuncSetAttribute((const void*)k_chain, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kChainLds);
+  if (e != hipSuccess) return e;
+  e = hipFuncSetAttribute((const void*)k_chain_one, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kChainLds);
+  if (e != hipSuccess) return e;
+  g_chain_ready = true;
+  return hipSuccess;
+}
+
+bool chain_op_supported(const ChainOp& op) {
+  if (op.type == kOpQr) return op.n >= 1 && op.m >= op.n && op.n <= kMaxHouseholderCols && op.m <= INT32_MAX;
+  if (op.type == kOpGemm) return op.m <= INT32_MAX && op.n <= INT32_MAX && op.k <= INT32_MAX;
+  return true;
+}
+
+hipError_t chain_run(hipStream_t st, const ChainOp* ops_dev, int count, int64_t* trace) {
+  if (count <= 0) return hipSuccess;
+  if (!g_chain_ready) return hipErrorNotInitialized;
+  hipLaunchKernelGGL(k_chain, dim3(1), dim3(kCT), kChainLds, st, ops_dev, count, trace);
+  return hipGetLastError();
+}
+
+hipError_t chain_run_one(hipStream_t st, const ChainOp& op) {
+  if (!g_chain_ready) return hipErrorNotInitialized;
+  hipLaunchKernelGGL(k_chain_one, dim3(1), dim3(kCT), kChainLds, st, op);
+  return hipGetLastError();
+}
+
+}  // namespace ttk

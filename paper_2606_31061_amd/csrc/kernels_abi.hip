@@ -5,7 +5,6 @@
 #include <string>
 
 namespace ttk {
-hipError_t qr64_setup(size_t lds_limit);
 hipError_t pass_setup();
 }  // namespace ttk
 
@@ -63,10 +62,23 @@ tt_status tt_kernel_qr(int32_t m, int32_t n, const double* M, double* Q, double*
                        void* hip_stream) {
   if (!M || !Q || !workspace) return kfail(TT_ERR_INVALID_ARG, "null");
   if (n < 1 || m < n) return kfail(TT_ERR_INVALID_ARG, "size");
-  const size_t lds = lds_limit();
-  if (ttk::qr64_setup(lds) != hipSuccess) return kfail(TT_ERR_DEVICE, "setup");
-  hipError_t e = ttk::qr64(static_cast<hipStream_t>(hip_stream), m, n, M, 1, m, Q, 1, m, R,
-                           64.0 * 2.220446049250313e-16, workspace, lds);
+  ttk::ChainOp op;
+  op.type = ttk::kOpQr;
+  op.m = m;
+  op.n = n;
+  op.rho = n;
+  op.a = M;
+  op.ars = 1;
+  op.acs = m;
+  op.c = Q;
+  op.crs = 1;
+  op.ccs = m;
+  op.r = R;
+  op.aux = workspace;
+  op.tol = 64.0 * 2.220446049250313e-16;
+  if (!ttk::chain_op_supported(op)) return kfail(TT_ERR_UNSUPPORTED, "more than 256 columns");
+  if (ttk::chain_setup(lds_limit()) != hipSuccess) return kfail(TT_ERR_DEVICE, "setup");
+  hipError_t e = ttk::chain_run_one(static_cast<hipStream_t>(hip_stream), op);
   return e == hipSuccess ? TT_OK : kfail(TT_ERR_DEVICE, "qr", e);
 }
 

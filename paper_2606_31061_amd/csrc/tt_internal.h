@@ -12,46 +12,68 @@ namespace ttk {
 // Records `msg` as the calling thread's last error and returns `st`.
 tt_status set_error(tt_status st, const char* msg);
 
-// Threads of the one-workgroup FP64 factorisation kernels.
-constexpr int kQrThreads = 256;
+// Threads of the workgroup that runs the chain operation lists.
+constexpr int kChainThreads = 1024;
+
+// ---------------------------------------------------------------- chain lists
+// One operation of the update's FP64 chain, executed by the one-workgroup
+// kernel of chain_exec.hip.  Field use by type:
+//   kOpGemm   C(i,j) = sum_k A(i,k) B(k,j): m = rows, n = cols, k = depth;
+//             a/ars/acs, b/brs/bcs, c/crs/ccs element strides; c may be null
+//             when c32 (same strides) receives an FP32 copy.
+//   kOpQr     thin QR of the m x n matrix a (strides ars, acs) into Q = c
+//             (strides crs, ccs) and, if r != null, R (n x n column-major);
+//             aux holds m*n doubles; rho = cap on proper reflectors; tol = rank
+//             threshold relative to ||M||_F.  a may alias c.
+//   kOpNormG  a = g in, c = g out (m = r_m); b = G_m in, r = G_m out (k values).
+//   kOpCopy   c[e] = a[e] and/or c32[e] = (float)a[e], e < m.
+//   kOpCommit if *flag == 0: hist row (t mod hist_cap) = a (m values), t += 1;
+//             else c = b (k doubles, restoring the old state), *rejected += 1;
+//             then *flag = 0.
+enum : int32_t { kOpGemm = 1, kOpQr = 2, kOpNormG = 3, kOpCopy = 4, kOpCommit = 5 };
+struct ChainOp {
+  int32_t type = 0;
+  int32_t rho = 0;
+  int64_t m = 0, n = 0, k = 0;
+  const double* a = nullptr;
+  int64_t ars = 0, acs = 0;
+  const double* b = nullptr;
+  int64_t brs = 0, bcs = 0;
+  double* c = nullptr;
+  int64_t crs = 0, ccs = 0;
+  float* c32 = nullptr;
+  double* r = nullptr;
+  double* aux = nullptr;
+  double tol = 0.0;
+  int* flag = nullptr;
+  int* rejected = nullptr;
+  int64_t* tdev = nullptr;
+  double* hist = nullptr;
+  int64_t hist_cap = 0;
+};
+// Sets the kernels' LDS size; once per process before the first launch.
+hipError_t chain_setup(size_t lds_limit);
+bool chain_op_supported(const ChainOp& op);
+// Runs ops_dev[0..count) (device array) in order on one workgroup.  If trace
+// is not null, trace[2i] and trace[2i+1] receive the device wall clock at the
+// start and end of op i.
+hipError_t chain_run(hipStream_t st, const ChainOp* ops_dev, int count, int64_t* trace = nullptr);
+// Runs one operation passed by value.
+hipError_t chain_run_one(hipStream_t st, const ChainOp& op);
 // Rows of the slice staged per wave in pass 2 (multiple of 8).
 constexpr int kPass2SlabMax = 72;
 constexpr int kPass2Waves = 8;
 
 // ---------------------------------------------------------------- chain (FP64)
-// C(i,j) = sum_k A(i,k) B(k,j) with element strides; optional FP32 copy of C.
+// C(i,j) = sum_k A(i,k) B(k,j) over the whole GPU, element strides; C may be
+// null when C32 (same strides) receives an FP32 copy.
 hipError_t gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K,
                   const double* A, int64_t ars, int64_t acs,
                   const double* B, int64_t brs, int64_t bcs,
                   double* C, int64_t crs, int64_t ccs, float* C32);
 
-// Thin Householder QR of an m x n matrix M (element (i,j) at M[i*mrs + j*mcs]).
-// Writes Q (m x n) at Q[i*qrs + j*qcs]; if R != nullptr writes R (n x n,
-// column-major, leading dimension n).  diag(R) >= 0; a column whose remaining
-// norm is <= tol*||M||_F gets the identity reflector (R_jj = 0).  gwork holds
-// m*n doubles when the matrix does not fit in LDS.  The input may alias Q.
-hipError_t qr64(hipStream_t st, int m, int n, const double* M, int64_t mrs, int64_t mcs,
-                double* Q, int64_t qrs, int64_t qcs, double* R, double tol,
-                double* gwork, size_t lds_limit);
-
-// dst[i] = src[i] * (*scale_src) if scale_src else src[i]; count n.
-hipError_t copy64(hipStream_t st, double* dst, const double* src, int64_t n);
-
-// g normalisation (Section 3.4.1): nu = ||g||; if nu > 0: Gm_out = nu * Gm_in,
-// g_out = g_in / nu; else g_out = e_1 and Gm_out = Gm_in.
-hipError_t normalize_g(hipStream_t st, const double* g_in, double* g_out, int rm,
-                       const double* Gm_in, double* Gm_out, int64_t gm_len);
-
-// Commit: if *flag == 0 copy new state (len doubles) into master, append g to
-// the history ring and advance t; else count a rejected update.
-hipError_t commit(hipStream_t st, int* flag, const double* new_state, double* master, int64_t len,
-                  const double* g_new, int rm, double* history, int64_t hist_cap,
-                  int64_t* t_dev, int* rejected);
-
 // Element conversion FP64 -> out dtype (F64/F32).
 hipError_t convert_out(hipStream_t st, const double* src, void* dst, tt_dtype dt, int64_t n);
-
-// Host slice (F64/F32/BF16) already on device: nonfinite scan not needed (passes flag it).
 
 // ---------------------------------------------------------------- passes (FP32)
 // Pass 1: Z(p,a) = sum_j X(p,j) B(a,j), X P x J (p fastest) of dtype `xdt`,

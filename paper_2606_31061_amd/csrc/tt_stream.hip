@@ -1,9 +1,9 @@
 // Host runtime of the C ABI declared in include/tt_stream.h.
 //
-// One handle holds one stream's state on one GPU: the committed FP64 cores
-// G_1..G_m and temporal vector g (the "master" state), plus the workspace of
-// one update.  A push launches the update as a fixed sequence of kernels on
-// the handle's HIP stream:
+// One handle holds one stream's state on one GPU: two FP64 state buffers
+// (cores G_1..G_m then the temporal vector g) used in turn, the committed one
+// being state[cur], plus the workspace of one update.  An update (Algorithm 1)
+// is planned once, at creation, for each of the two parities:
 //   right-orthogonalisation   normalise g, LQ sweep k = m..2 (Section 3.4.1)
 //   right interfaces          B_k = G_{k+1} x_3 B_{k+1}, k = m-1..k*
 //   pass 1                    Z = X^<k*> B_{k*}^T          (slice stream)
@@ -12,8 +12,12 @@
 //   pass 2                    Y = A_{k*+1}^T X^<k*>          (slice stream)
 //   tail                      for k = k*+1..m: G~_k = Y_k B_k^T, thin QR,
 //                             Y_{k+1} = G_k^T Y_k; g = Y_{m+1}
-//   commit                    if the slice was finite, new state -> master
-// Nothing is read back to the host during a push.
+//   commit                    history row and t, or restore of the old state
+//                             when the slice was not finite
+// The new state is written to state[cur ^ 1]; the host flips cur after
+// enqueueing.  Small steps are grouped into operation lists run by one
+// workgroup (chain_exec.hip); large contractions and the passes are launches
+// of their own.  Nothing is read back to the host during a push.
 #include "tt_internal.h"
 
 #include <algorithm>
@@ -25,9 +29,7 @@
 #include <vector>
 
 namespace ttk {
-hipError_t qr64_setup(size_t lds_limit);
 hipError_t pass_setup();
-hipError_t to_f32(hipStream_t st, const double* src, float* dst, int64_t n);
 }  // namespace ttk
 
 namespace {
@@ -35,6 +37,21 @@ namespace {
 constexpr uint64_t kMagic = 0x54545354524d3031ULL;  // "TTSTRM01"
 constexpr uint64_t kDead = 0xdeadbeefdeadbeefULL;
 constexpr double kQrTol = 64.0 * 2.220446049250313e-16;
+// A contraction of at least this many multiply-adds is launched over the whole
+// GPU instead of being run by the chain workgroup.
+constexpr double kWideFma = 1.0e6;
+
+enum StepKind { kStepChain = 0, kStepWide = 1, kStepPass1 = 2, kStepPass2 = 3 };
+struct Step {
+  int kind;
+  int first;
+  int count;
+};
+struct UpdatePlan {
+  std::vector<ttk::ChainOp> ops;
+  std::vector<Step> steps;
+  ttk::ChainOp* dev = nullptr;
+};
 
 thread_local std::string g_last_error = "no error";
 
@@ -104,10 +121,15 @@ struct tt_stream {
   size_t device_bytes = 0;
   std::vector<void*> owned;
 
-  double* master = nullptr;
+  double* state[2] = {nullptr, nullptr};
+  int cur = 0;               // state[cur] is the committed state
+  UpdatePlan plan[2];        // plan[p] reads state[p], writes state[p ^ 1]
   double* work = nullptr;
-  double* fresh = nullptr;
   double* Rbuf = nullptr;
+  int64_t* trace = nullptr;  // 2 stamps per chain op (TT_FLAG_PROFILE_OPS)
+  int64_t trace_len = 0;
+  int traced_plan = -1;      // plan of the last traced push
+  int wall_khz = 100000;
   std::vector<double*> B;    // B[k] for k = kstar..m-1
   float* B32 = nullptr;
   double* Z = nullptr;
@@ -134,6 +156,7 @@ struct tt_stream {
 
   double* g_of(double* st) const { return st + coff[m + 1]; }
   double* G_of(double* st, int k) const { return st + coff[k]; }
+  double* master() const { return state[cur]; }
 };
 
 namespace {
@@ -212,92 +235,213 @@ int choose_split(const tt_stream* s) {
   return best;
 }
 
-tt_status launch_update(tt_stream* s, const void* X, tt_dtype xdt) {
-  hipStream_t st = s->stream;
+void plan_chain(UpdatePlan& p, const ttk::ChainOp& op) {
+  p.ops.push_back(op);
+  const int idx = (int)p.ops.size() - 1;
+  if (!p.steps.empty() && p.steps.back().kind == kStepChain && p.steps.back().first + p.steps.back().count == idx)
+    p.steps.back().count++;
+  else
+    p.steps.push_back({kStepChain, idx, 1});
+}
+
+// C = A B (see ttk::ChainOp); large products become launches of their own.
+void plan_gemm(UpdatePlan& p, int64_t M, int64_t N, int64_t K, const double* A, int64_t ars, int64_t acs,
+               const double* B, int64_t brs, int64_t bcs, double* C, int64_t crs, int64_t ccs, float* C32) {
+  ttk::ChainOp op;
+  op.type = ttk::kOpGemm;
+  op.m = M;
+  op.n = N;
+  op.k = K;
+  op.a = A;
+  op.ars = ars;
+  op.acs = acs;
+  op.b = B;
+  op.brs = brs;
+  op.bcs = bcs;
+  op.c = C;
+  op.crs = crs;
+  op.ccs = ccs;
+  op.c32 = C32;
+  if ((double)M * (double)N * (double)K >= kWideFma) {
+    p.ops.push_back(op);
+    p.steps.push_back({kStepWide, (int)p.ops.size() - 1, 1});
+  } else {
+    plan_chain(p, op);
+  }
+}
+
+// Thin QR of the m x n matrix M into Q (strides as in ttk::ChainOp).
+void plan_qr(UpdatePlan& p, const tt_stream* s, int64_t m, int64_t n, int rho, const double* M, int64_t mrs,
+             int64_t mcs, double* Q, int64_t qrs, int64_t qcs, double* R) {
+  ttk::ChainOp op;
+  op.type = ttk::kOpQr;
+  op.m = m;
+  op.n = n;
+  op.rho = rho;
+  op.a = M;
+  op.ars = mrs;
+  op.acs = mcs;
+  op.c = Q;
+  op.crs = qrs;
+  op.ccs = qcs;
+  op.r = R;
+  op.aux = s->qrwork;
+  op.tol = kQrTol;
+  plan_chain(p, op);
+}
+
+void plan_copy(UpdatePlan& p, const double* src, double* dst, float* dst32, int64_t n) {
+  ttk::ChainOp op;
+  op.type = ttk::kOpCopy;
+  op.m = n;
+  op.a = src;
+  op.c = dst;
+  op.c32 = dst32;
+  plan_chain(p, op);
+}
+
+// The update that reads state[par] and writes state[par ^ 1].
+void build_plan(tt_stream* s, int par) {
+  UpdatePlan& P = s->plan[par];
+  P.ops.clear();
+  P.steps.clear();
+  double* master = s->state[par];
+  double* fresh = s->state[par ^ 1];
+  double* work = s->work;
   const int m = s->m, ks = s->kstar;
   const auto& I = s->I;
   const auto& r = s->r;
   const auto& Pk = s->Pk;
   const auto& Jk = s->Jk;
-  const size_t lds = s->lds_limit;
 
-  // right-orthogonalisation: normalise g into the work state, then LQ sweep
-  TT_HIP(ttk::normalize_g(st, s->g_of(s->master), s->g_of(s->work), (int)r[m], s->G_of(s->master, m),
-                          s->G_of(s->work, m), r[m - 1] * I[m] * r[m]));
+  // right-orthogonalisation: normalise g into the work state, then the LQ sweep
+  {
+    ttk::ChainOp op;
+    op.type = ttk::kOpNormG;
+    op.a = s->g_of(master);
+    op.c = s->g_of(work);
+    op.m = r[m];
+    op.b = s->G_of(master, m);
+    op.r = s->G_of(work, m);
+    op.k = r[m - 1] * I[m] * r[m];
+    plan_chain(P, op);
+  }
+  auto Bk = [&](int k) -> double* { return k == m ? s->g_of(work) : s->B[k]; };
   for (int k = m; k >= 2; --k) {
     const int64_t rows = I[k] * r[k];
-    const int n = (int)r[k - 1];
-    double* Gk = s->G_of(s->work, k);
+    const int64_t n = r[k - 1];
+    double* Gk = s->G_of(work, k);
     // LQ of the r_{k-1} x (I_k r_k) unfolding = QR of its transpose
-    TT_HIP(ttk::qr64(st, (int)rows, n, Gk, n, 1, Gk, n, 1, s->Rbuf, kQrTol, s->qrwork, lds));
+    plan_qr(P, s, rows, n, (int)n, Gk, n, 1, Gk, n, 1, s->Rbuf);
     // G_{k-1} <- G_{k-1} x_3 L with L = R^T
     const int64_t rows2 = r[k - 2] * I[k - 1];
-    TT_HIP(ttk::gemm64(st, rows2, n, n, s->G_of(s->master, k - 1), 1, rows2, s->Rbuf, n, 1,
-                       s->G_of(s->work, k - 1), 1, rows2, nullptr));
+    plan_gemm(P, rows2, n, n, s->G_of(master, k - 1), 1, rows2, s->Rbuf, n, 1, s->G_of(work, k - 1), 1, rows2,
+              nullptr);
+    // right interface B_{k-1} = G_k x_3 B_k, once G_k is final (B_{k*} after the sweep)
+    if (k - 1 > ks) {
+      const int j = k - 1;
+      const int64_t rj = r[j] * I[j + 1];
+      plan_gemm(P, rj, Jk[j + 1], r[j + 1], s->G_of(work, j + 1), 1, rj, Bk(j + 1), 1, r[j + 1], s->B[j], 1, rj,
+                nullptr);
+    }
+  }
+  if (ks < m) {
+    const int64_t rj = r[ks] * I[ks + 1];
+    plan_gemm(P, rj, Jk[ks + 1], r[ks + 1], s->G_of(work, ks + 1), 1, rj, Bk(ks + 1), 1, r[ks + 1], nullptr, 1, rj,
+              s->B32);
+  } else {
+    plan_copy(P, s->g_of(work), nullptr, s->B32, r[m]);
   }
 
-  // right interfaces B_k for k = m-1 .. kstar (B_m = g)
-  auto Bk = [&](int k) -> const double* { return k == m ? s->g_of(s->work) : s->B[k]; };
-  for (int k = m - 1; k >= ks; --k) {
-    const int64_t rows = r[k] * I[k + 1];
-    TT_HIP(ttk::gemm64(st, rows, Jk[k + 1], r[k + 1], s->G_of(s->work, k + 1), 1, rows, Bk(k + 1), 1, r[k + 1],
-                       s->B[k], 1, rows, k == ks ? s->B32 : nullptr));
-  }
-  if (ks == m) TT_HIP(ttk::to_f32(st, s->g_of(s->work), s->B32, r[m]));
+  P.steps.push_back({kStepPass1, 0, 0});
 
-  // pass 1
-  TT_HIP(ttk::pass1(st, X, xdt, s->p1, Pk[ks], Jk[ks], (int)r[ks], s->B32, s->Z, s->ws, s->flag));
-
-  // head: Z_k for k < kstar from the pre-sweep cores
+  // head: Z_k for k < k* from the right-orthogonal cores
   auto Zof = [&](int k) -> double* { return k == ks ? s->Z : s->Zk[k]; };
   for (int k = ks - 1; k >= 1; --k) {
     const int64_t Kd = I[k + 1] * r[k + 1];
-    TT_HIP(ttk::gemm64(st, Pk[k], r[k], Kd, Zof(k + 1), 1, Pk[k], s->G_of(s->work, k + 1), r[k], 1, Zof(k), 1,
-                       Pk[k], nullptr));
+    plan_gemm(P, Pk[k], r[k], Kd, Zof(k + 1), 1, Pk[k], s->G_of(work, k + 1), r[k], 1, Zof(k), 1, Pk[k], nullptr);
   }
-  // forward sweep k = 1..kstar
+  // forward sweep k = 1..k*
   for (int k = 1; k <= ks; ++k) {
     const int64_t rows = r[k - 1] * I[k];
-    const int n = (int)r[k];
+    const int64_t n = r[k];
     const double* Gt;
     if (k == 1) {
       Gt = Zof(1);
     } else {
-      const double* Ak = (k == 2) ? s->G_of(s->fresh, 1) : s->A[k];
-      TT_HIP(ttk::gemm64(st, r[k - 1], I[k] * r[k], Pk[k - 1], Ak, Pk[k - 1], 1, Zof(k), 1, Pk[k - 1], s->Gt, 1,
-                         r[k - 1], nullptr));
+      const double* Ak = (k == 2) ? s->G_of(fresh, 1) : s->A[k];
+      plan_gemm(P, r[k - 1], I[k] * r[k], Pk[k - 1], Ak, Pk[k - 1], 1, Zof(k), 1, Pk[k - 1], s->Gt, 1, r[k - 1],
+                nullptr);
       Gt = s->Gt;
     }
-    double* Gnew = s->G_of(s->fresh, k);
-    TT_HIP(ttk::qr64(st, (int)rows, n, Gt, 1, rows, Gnew, 1, rows, nullptr, kQrTol, s->qrwork, lds));
+    double* Gnew = s->G_of(fresh, k);
+    plan_qr(P, s, rows, n, (int)std::min<int64_t>(n, Jk[k]), Gt, 1, rows, Gnew, 1, rows, nullptr);
     if (k >= 2) {
-      const double* Ak = (k == 2) ? s->G_of(s->fresh, 1) : s->A[k];
-      TT_HIP(ttk::gemm64(st, Pk[k - 1], I[k] * r[k], r[k - 1], Ak, 1, Pk[k - 1], Gnew, 1, r[k - 1], s->A[k + 1], 1,
-                         Pk[k - 1], k == ks ? s->A32 : nullptr));
+      const double* Ak = (k == 2) ? s->G_of(fresh, 1) : s->A[k];
+      double* Anext = (k == ks) ? nullptr : s->A[k + 1];
+      plan_gemm(P, Pk[k - 1], I[k] * r[k], r[k - 1], Ak, 1, Pk[k - 1], Gnew, 1, r[k - 1], Anext, 1, Pk[k - 1],
+                k == ks ? s->A32 : nullptr);
     } else if (ks == 1) {
-      TT_HIP(ttk::to_f32(st, Gnew, s->A32, Pk[1] * r[1]));
+      plan_copy(P, Gnew, nullptr, s->A32, Pk[1] * r[1]);
     }
   }
 
-  // pass 2
-  TT_HIP(ttk::pass2(st, X, xdt, Pk[ks], Jk[ks], (int)r[ks], s->A32, s->Y[0], s->flag));
+  P.steps.push_back({kStepPass2, 0, 0});
 
-  // tail k = kstar+1 .. m
+  // tail k = k*+1 .. m; the local solution has rank <= J_k
   int cur = 0;
   for (int k = ks + 1; k <= m; ++k) {
     const int64_t rows = r[k - 1] * I[k];
-    const int n = (int)r[k];
-    TT_HIP(ttk::gemm64(st, rows, n, Jk[k], s->Y[cur], 1, rows, Bk(k), r[k], 1, s->Gt, 1, rows, nullptr));
-    double* Gnew = s->G_of(s->fresh, k);
-    TT_HIP(ttk::qr64(st, (int)rows, n, s->Gt, 1, rows, Gnew, 1, rows, nullptr, kQrTol, s->qrwork, lds));
-    double* dst = (k == m) ? s->g_of(s->fresh) : s->Y[cur ^ 1];
-    TT_HIP(ttk::gemm64(st, n, Jk[k], rows, Gnew, rows, 1, s->Y[cur], 1, rows, dst, 1, n, nullptr));
+    const int64_t n = r[k];
+    plan_gemm(P, rows, n, Jk[k], s->Y[cur], 1, rows, Bk(k), r[k], 1, s->Gt, 1, rows, nullptr);
+    double* Gnew = s->G_of(fresh, k);
+    plan_qr(P, s, rows, n, (int)std::min<int64_t>(n, Jk[k]), s->Gt, 1, rows, Gnew, 1, rows, nullptr);
+    double* dst = (k == m) ? s->g_of(fresh) : s->Y[cur ^ 1];
+    plan_gemm(P, n, Jk[k], rows, Gnew, rows, 1, s->Y[cur], 1, rows, dst, 1, n, nullptr);
     cur ^= 1;
   }
-  if (ks == m) TT_HIP(ttk::copy64(st, s->g_of(s->fresh), s->Y[0], r[m]));
+  if (ks == m) plan_copy(P, s->Y[0], s->g_of(fresh), nullptr, r[m]);
 
-  TT_HIP(ttk::commit(st, s->flag, s->fresh, s->master, s->state_len, s->g_of(s->fresh), (int)r[m], s->hist,
-                     s->hist_cap, s->tdev, s->rejected));
+  {
+    ttk::ChainOp op;
+    op.type = ttk::kOpCommit;
+    op.a = s->g_of(fresh);
+    op.m = r[m];
+    op.b = master;
+    op.c = fresh;
+    op.k = s->state_len;
+    op.flag = s->flag;
+    op.rejected = s->rejected;
+    op.tdev = s->tdev;
+    op.hist = s->hist;
+    op.hist_cap = s->hist_cap;
+    plan_chain(P, op);
+  }
+}
+
+tt_status run_plan(tt_stream* s, const UpdatePlan& P, const void* X, tt_dtype xdt) {
+  hipStream_t st = s->stream;
+  const int ks = s->kstar;
+  for (const Step& step : P.steps) {
+    switch (step.kind) {
+      case kStepChain:
+        TT_HIP(ttk::chain_run(st, P.dev + step.first, step.count, s->trace ? s->trace + 2 * step.first : nullptr));
+        break;
+      case kStepWide: {
+        const ttk::ChainOp& o = P.ops[step.first];
+        TT_HIP(ttk::gemm64(st, o.m, o.n, o.k, o.a, o.ars, o.acs, o.b, o.brs, o.bcs, o.c, o.crs, o.ccs, o.c32));
+        break;
+      }
+      case kStepPass1:
+        TT_HIP(ttk::pass1(st, X, xdt, s->p1, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->B32, s->Z, s->ws, s->flag));
+        break;
+      case kStepPass2:
+        TT_HIP(ttk::pass2(st, X, xdt, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->A32, s->Y[0], s->flag));
+        break;
+      default:
+        return fail(TT_ERR_DEVICE, "corrupt update plan");
+    }
+  }
   return TT_OK;
 }
 
@@ -333,7 +477,7 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
   }
   if (cfg->compute != TT_F32 && cfg->compute != TT_BF16) return fail(TT_ERR_INVALID_ARG, "compute must be F32/BF16");
   if (cfg->compute == TT_BF16) return fail(TT_ERR_UNSUPPORTED, "BF16 contractions are not built in this version");
-  if (cfg->flags & ~(TT_FLAG_SYNC_PUSH)) return fail(TT_ERR_UNSUPPORTED, "unsupported flags");
+  if (cfg->flags & ~(TT_FLAG_SYNC_PUSH | TT_FLAG_PROFILE_OPS)) return fail(TT_ERR_UNSUPPORTED, "unsupported flags");
   if (cfg->split_point < 0 || cfg->split_point > m) return fail(TT_ERR_INVALID_ARG, "split_point out of range");
 
   tt_stream* s = new (std::nothrow) tt_stream();
@@ -382,7 +526,7 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device) != hipSuccess)
     return bail(TT_ERR_DEVICE, "cannot query LDS size");
   s->lds_limit = (size_t)lds;
-  if (ttk::qr64_setup(s->lds_limit) != hipSuccess || ttk::pass_setup() != hipSuccess)
+  if (ttk::pass_setup() != hipSuccess || ttk::chain_setup(s->lds_limit) != hipSuccess)
     return bail(TT_ERR_DEVICE, "kernel attribute setup failed");
 
   const int m_ = m;
@@ -412,9 +556,9 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
     ok = ok && p;
     return p;
   };
-  s->master = D(s->state_len);
+  s->state[0] = D(s->state_len);
+  s->state[1] = D(s->state_len);
   s->work = D(s->state_len);
-  s->fresh = D(s->state_len);
   s->Rbuf = D(rmax * rmax);
   s->B.assign(m_ + 1, nullptr);
   for (int k = ks; k <= m_ - 1; ++k) s->B[k] = D(r[k] * s->Jk[k]);
@@ -423,7 +567,7 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
   s->Zk.assign(m_ + 1, nullptr);
   for (int k = 1; k < ks; ++k) s->Zk[k] = D(s->Pk[k] * r[k]);
   s->A.assign(m_ + 2, nullptr);
-  for (int k = 3; k <= ks + 1; ++k) s->A[k] = D(s->Pk[k - 1] * r[k - 1]);
+  for (int k = 3; k <= ks; ++k) s->A[k] = D(s->Pk[k - 1] * r[k - 1]);
   s->A32 = F(s->Pk[ks] * r[ks]);
   s->Gt = D(gtmax);
   s->Y[0] = D(ymax);
@@ -455,7 +599,27 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
   else normal_fill(init, cfg->seed);
   for (double v : init)
     if (!std::isfinite(v)) return bail(TT_ERR_NONFINITE, "initial cores contain NaN/Inf");
-  TT_HIP_BAIL(hipMemcpyAsync(s->master, init.data(), sizeof(double) * s->state_len, hipMemcpyHostToDevice, s->stream));
+  TT_HIP_BAIL(hipMemcpyAsync(s->state[0], init.data(), sizeof(double) * s->state_len, hipMemcpyHostToDevice,
+                             s->stream));
+  s->cur = 0;
+  for (int par = 0; par < 2; ++par) {
+    build_plan(s, par);
+    UpdatePlan& P = s->plan[par];
+    for (const ttk::ChainOp& op : P.ops)
+      if (!ttk::chain_op_supported(op)) return bail(TT_ERR_UNSUPPORTED, "a core re-orthogonalisation exceeds 256 columns");
+    P.dev = static_cast<ttk::ChainOp*>(dev_alloc(s, sizeof(ttk::ChainOp) * P.ops.size()));
+    if (!P.dev) return bail(TT_ERR_OOM, "plan allocation failed");
+    TT_HIP_BAIL(hipMemcpyAsync(P.dev, P.ops.data(), sizeof(ttk::ChainOp) * P.ops.size(), hipMemcpyHostToDevice,
+                               s->stream));
+  }
+  if (s->flags & TT_FLAG_PROFILE_OPS) {
+    s->trace_len = (int64_t)std::max(s->plan[0].ops.size(), s->plan[1].ops.size());
+    s->trace = static_cast<int64_t*>(dev_alloc(s, sizeof(int64_t) * 2 * s->trace_len));
+    if (!s->trace) return bail(TT_ERR_OOM, "profile buffer");
+    TT_HIP_BAIL(hipMemsetAsync(s->trace, 0, sizeof(int64_t) * 2 * s->trace_len, s->stream));
+    (void)hipDeviceGetAttribute(&s->wall_khz, hipDeviceAttributeWallClockRate, s->device);
+    if (s->wall_khz <= 0) s->wall_khz = 100000;
+  }
   TT_HIP_BAIL(hipStreamSynchronize(s->stream));
 #undef TT_HIP_BAIL
   *out = s;
@@ -480,8 +644,10 @@ tt_status tt_stream_push_slice(tt_stream* s, const void* slice, tt_dtype dtype, 
     X = s->stage;
   }
   TT_HIP(hipEventRecord(s->ev0, s->stream));
-  tt_status st = launch_update(s, X, dtype);
+  tt_status st = run_plan(s, s->plan[s->cur], X, dtype);
   if (st != TT_OK) return st;
+  s->traced_plan = s->cur;
+  s->cur ^= 1;
   TT_HIP(hipEventRecord(s->ev1, s->stream));
   s->timed = true;
   s->pushes++;
@@ -522,8 +688,8 @@ tt_status tt_stream_info(const tt_stream* s, int64_t* cores_len, int64_t* r_last
 tt_status tt_stream_get_state(tt_stream* s, double* cores, double* g, int64_t* t_out) {
   if (!valid(s)) return fail(TT_ERR_INVALID_ARG, "invalid handle");
   TT_HIP(hipStreamSynchronize(s->stream));
-  if (cores) TT_HIP(hipMemcpy(cores, s->master, sizeof(double) * s->cores_len, hipMemcpyDeviceToHost));
-  if (g) TT_HIP(hipMemcpy(g, s->g_of(s->master), sizeof(double) * s->r[s->m], hipMemcpyDeviceToHost));
+  if (cores) TT_HIP(hipMemcpy(cores, s->master(), sizeof(double) * s->cores_len, hipMemcpyDeviceToHost));
+  if (g) TT_HIP(hipMemcpy(g, s->g_of(s->master()), sizeof(double) * s->r[s->m], hipMemcpyDeviceToHost));
   if (t_out) TT_HIP(hipMemcpy(t_out, s->tdev, sizeof(int64_t), hipMemcpyDeviceToHost));
   return TT_OK;
 }
@@ -536,8 +702,8 @@ tt_status tt_stream_set_state(tt_stream* s, const double* cores, const double* g
   for (int64_t i = 0; i < s->r[s->m]; ++i)
     if (!std::isfinite(g[i])) return fail(TT_ERR_NONFINITE, "g contains NaN/Inf");
   TT_HIP(hipStreamSynchronize(s->stream));
-  TT_HIP(hipMemcpy(s->master, cores, sizeof(double) * s->cores_len, hipMemcpyHostToDevice));
-  TT_HIP(hipMemcpy(s->g_of(s->master), g, sizeof(double) * s->r[s->m], hipMemcpyHostToDevice));
+  TT_HIP(hipMemcpy(s->master(), cores, sizeof(double) * s->cores_len, hipMemcpyHostToDevice));
+  TT_HIP(hipMemcpy(s->g_of(s->master()), g, sizeof(double) * s->r[s->m], hipMemcpyHostToDevice));
   TT_HIP(hipMemcpy(s->tdev, &t, sizeof(int64_t), hipMemcpyHostToDevice));
   return TT_OK;
 }
@@ -576,13 +742,13 @@ tt_status tt_stream_reconstruct(tt_stream* s, void* out, tt_dtype dtype, int on_
   }
   hipStream_t st = s->stream;
   // V_{m+1} = g; V_k = G_k^L V_{k+1}, viewed as r_{k-1} x (I_k .. I_m)
-  const double* V = s->g_of(s->master);
+  const double* V = s->g_of(s->master());
   int64_t cols = 1;
   int cur = 0;
   for (int k = s->m; k >= 1; --k) {
     const int64_t rows = s->r[k - 1] * s->I[k];
     double* dst = s->recon[cur];
-    TT_HIP(ttk::gemm64(st, rows, cols, s->r[k], s->G_of(s->master, k), 1, rows, V, 1, s->r[k], dst, 1, rows,
+    TT_HIP(ttk::gemm64(st, rows, cols, s->r[k], s->G_of(s->master(), k), 1, rows, V, 1, s->r[k], dst, 1, rows,
                        nullptr));
     V = dst;
     cols *= s->I[k];
@@ -608,6 +774,34 @@ tt_status tt_stream_last_push_ms(tt_stream* s, float* ms) {
   if (!s->timed) return fail(TT_ERR_STATE, "no push yet");
   TT_HIP(hipEventSynchronize(s->ev1));
   TT_HIP(hipEventElapsedTime(ms, s->ev0, s->ev1));
+  return TT_OK;
+}
+
+tt_status tt_stream_op_profile(tt_stream* s, int64_t cap, int32_t* kinds, int64_t* dims, double* us,
+                               int64_t* count) {
+  if (!valid(s) || !count || (cap > 0 && (!kinds || !dims || !us))) return fail(TT_ERR_INVALID_ARG, "null argument");
+  if (!s->trace) return fail(TT_ERR_STATE, "stream was not created with TT_FLAG_PROFILE_OPS");
+  if (s->traced_plan < 0) return fail(TT_ERR_STATE, "no push yet");
+  TT_HIP(hipStreamSynchronize(s->stream));
+  const UpdatePlan& P = s->plan[s->traced_plan];
+  std::vector<int64_t> stamps(2 * P.ops.size());
+  TT_HIP(hipMemcpy(stamps.data(), s->trace, sizeof(int64_t) * stamps.size(), hipMemcpyDeviceToHost));
+  // ops launched over the whole GPU are not timed here
+  std::vector<int> chain_ops;
+  for (const Step& step : P.steps)
+    if (step.kind == kStepChain)
+      for (int i = step.first; i < step.first + step.count; ++i) chain_ops.push_back(i);
+  *count = (int64_t)chain_ops.size();
+  const int64_t n = std::min<int64_t>(cap, *count);
+  for (int64_t q = 0; q < n; ++q) {
+    const int i = chain_ops[q];
+    const ttk::ChainOp& o = P.ops[i];
+    kinds[q] = o.type;
+    dims[3 * q] = o.m;
+    dims[3 * q + 1] = o.n;
+    dims[3 * q + 2] = o.type == ttk::kOpQr ? o.rho : o.k;
+    us[q] = (double)(stamps[2 * i + 1] - stamps[2 * i]) * 1000.0 / (double)s->wall_khz;
+  }
   return TT_OK;
 }
 
