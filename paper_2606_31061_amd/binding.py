@@ -89,6 +89,11 @@ def load_library(path: str = LIB_PATH):
                                          POINTER(c_int64)]),
         "tt_last_error_string": (c_char_p, []),
         "tt_version": (c_char_p, []),
+        "tt_batch_create": (c_int, [POINTER(c_void_p), c_int32, sv, POINTER(c_void_p)]),
+        "tt_batch_push": (c_int, [sv, POINTER(c_void_p), c_int]),
+        "tt_batch_synchronize": (c_int, [sv, POINTER(c_int32)]),
+        "tt_batch_info": (c_int, [sv, POINTER(c_int32), POINTER(c_int32)]),
+        "tt_batch_destroy": (c_int, [sv]),
         "tt_kernel_pass1": (c_int, [sv, c_int, c_int64, c_int64, c_int32, sv, sv, sv, sv, sv]),
         "tt_kernel_pass1_workspace": (c_size_t, [c_int64, c_int64, c_int32]),
         "tt_kernel_pass2": (c_int, [sv, c_int, c_int64, c_int64, c_int32, sv, sv, sv, sv]),
@@ -204,6 +209,7 @@ class TTStream:
             flat = np.concatenate(parts)
         self._stream = stream
         sp = int(stream.cuda_stream) if stream is not None else self._current_stream_handle()
+        self.hip_stream = sp
         self._h = tt_stream_create(self.modes, self.ranks, init_cores=flat, seed=seed, hip_stream=sp,
                                    keep_history=keep_history, history_capacity=history_capacity,
                                    split_point=split_point,
@@ -353,3 +359,53 @@ def tt_kernel_qr(M, Q, R, workspace, hip_stream: int = 0) -> int:
     return load_library().tt_kernel_qr(m, n, c_void_p(M.data_ptr()), c_void_p(Q.data_ptr()),
                                        c_void_p(R.data_ptr()) if R is not None else None,
                                        c_void_p(workspace.data_ptr()), c_void_p(hip_stream or None))
+
+
+class TTBatch:
+    """Streams advanced together (include/tt_batch.h): each push runs one
+    update of every member, every step of the update launched once per group
+    of same-shape members.  Members must share the HIP stream they were
+    created with and must outlive the batch."""
+
+    def __init__(self, streams):
+        self._lib = load_library()
+        self.streams = list(streams)
+        n = len(self.streams)
+        handles = (c_void_p * n)(*[s._h.value for s in self.streams])
+        sp = self.streams[0].hip_stream
+        self._h = c_void_p()
+        _check(self._lib.tt_batch_create(handles, n, c_void_p(sp or None), byref(self._h)), "tt_batch_create")
+
+    def push(self, slices) -> None:
+        """slices: one contiguous CUDA tensor per member, all of one dtype."""
+        if len(slices) != len(self.streams):
+            raise ValueError("one slice per member")
+        for x, s in zip(slices, self.streams):
+            if not x.is_cuda or not x.is_contiguous() or x.numel() != s.n:
+                raise ValueError("device slices must be contiguous CUDA tensors with N elements")
+        ptrs = (c_void_p * len(slices))(*[x.data_ptr() for x in slices])
+        _check(self._lib.tt_batch_push(self._h, ptrs, _dtype_code_torch(slices[0])), "tt_batch_push")
+
+    def synchronize(self):
+        """Waits; returns the per-member counts of rejected (non-finite) slices."""
+        rej = (c_int32 * len(self.streams))()
+        st = self._lib.tt_batch_synchronize(self._h, rej)
+        if st not in (TT_OK, TT_ERR_NONFINITE):
+            _check(st, "tt_batch_synchronize")
+        return [int(v) for v in rej]
+
+    def info(self):
+        n, g = c_int32(), c_int32()
+        _check(self._lib.tt_batch_info(self._h, byref(n), byref(g)), "tt_batch_info")
+        return {"streams": n.value, "groups": g.value}
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            _check(self._lib.tt_batch_destroy(self._h), "tt_batch_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -71,6 +71,15 @@ constexpr double kFirstOrder = 1e-7;
 
 __device__ __forceinline__ int round16(int x) { return (x + 15) & ~15; }
 
+// The thread index, opaque to the optimiser: the chain kernel loops over
+// operations, and quantities derived from the thread index would otherwise be
+// hoisted out of that loop and kept live (and spilled) across every operation.
+__device__ __forceinline__ int tix() {
+  int t = threadIdx.x;
+  asm volatile("" : "+v"(t));
+  return t;
+}
+
 __device__ __forceinline__ double read_lane(double x, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
@@ -186,7 +195,7 @@ __device__ __forceinline__ Plan wave_plan(int nbm, int nb, int nks, int w, bool 
 // k-steps; the last, partial round loads only what it uses.
 template <int NA>
 __device__ __forceinline__ void mma_slots(const View& A, const View& B, const Plan& p, int s0, int s1, v4d* acc) {
-  const int lane = threadIdx.x & 63;
+  const int lane = tix() & 63;
   const int li = lane & 15, lk = lane >> 4;
   int pa[NA], pb[NA], ph[NA];
 #pragma unroll
@@ -234,7 +243,7 @@ __device__ __forceinline__ void mma_dispatch(const View& A, const View& B, const
 // Only for plans without k split (used for small outputs in LDS).
 template <class Store>
 __device__ void finish_direct(const Plan& p, int M, int N, const v4d* acc, Store store) {
-  const int lane = threadIdx.x & 63;
+  const int lane = tix() & 63;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
     if (q < p.na && slot_ph(p, q) == 0) {
@@ -261,7 +270,7 @@ __device__ void finish_direct(const Plan& p, int M, int N, const v4d* acc, Store
 // consecutive addresses.  Ends with a barrier.
 template <class Store>
 __device__ void finish_lds(const Plan& p, int M, int N, const v4d* acc, double* buf, bool ifast, Store store) {
-  const int lane = threadIdx.x & 63;
+  const int lane = tix() & 63;
   if (p.ks == 1) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -284,8 +293,8 @@ __device__ void finish_lds(const Plan& p, int M, int N, const v4d* acc, double* 
   const int rows = 16 * p.nbm, total = p.nb * 256, cols = total / rows;
   // (i, j) of element e, advanced without division
   const int nf = ifast ? rows : cols, df = kCT % nf, ds = kCT / nf;
-  int f = threadIdx.x % nf, sl = threadIdx.x / nf;
-  for (int e = threadIdx.x; e < total; e += kCT) {
+  int f = tix() % nf, sl = tix() / nf;
+  for (int e = tix(); e < total; e += kCT) {
     const int i = ifast ? f : sl, j = ifast ? sl : f;
     f += df;
     sl += ds;
@@ -308,7 +317,7 @@ __device__ void finish_lds(const Plan& p, int M, int N, const v4d* acc, double* 
 // k-steps, at most 64 output blocks; no k split.  Ends with a barrier.
 template <class Store>
 __device__ void gemm_lds(int M, int N, int nks, const View& A, const View& B, Store store) {
-  const int w = threadIdx.x >> 6;
+  const int w = tix() >> 6;
   const int nbm = (M + 15) >> 4, nbn = (N + 15) >> 4;
   const Plan p = wave_plan(nbm, nbm * nbn, nks, w, false);
   v4d acc[4];
@@ -346,8 +355,8 @@ __device__ void stage(int dst, int drs, int dcs, int rows, int cols, const doubl
   const int64_t fs = rfast ? rs : cs, ss = rfast ? cs : rs;
   const int dfs = rfast ? drs : dcs, dss = rfast ? dcs : drs;
   const int df = kCT % nf, ds = kCT / nf;
-  int f = threadIdx.x % nf, sl = threadIdx.x / nf;
-  for (int e0 = threadIdx.x; e0 < total; e0 += U * kCT) {
+  int f = tix() % nf, sl = tix() / nf;
+  for (int e0 = tix(); e0 < total; e0 += U * kCT) {
     double x[U];
     int fi[U], si[U];
 #pragma unroll
@@ -377,7 +386,7 @@ __device__ void wg_gemm(const Gemm& g) {
     __syncthreads();
     return;
   }
-  const int w = threadIdx.x >> 6;
+  const int w = tix() >> 6;
   const int nbm_all = (M + 15) >> 4, nbn_all = (N + 15) >> 4;
   const int nks = (K + 3) >> 2;
   const int TR = nbm_all < 64 ? nbm_all : 64;
@@ -456,7 +465,7 @@ __device__ __forceinline__ double rsqrt_pos(double d) {
 template <int NEWTON>
 __device__ __forceinline__ bool chol_inv32(const double* W, double* R, double* Ri, double* rowbuf, double thr2,
                                            int n) {
-  const int lane = threadIdx.x & 63;
+  const int lane = tix() & 63;
   int c = lane & 31;
   // opaque to the optimiser: keeps the identity set-up below from being
   // hoisted out of the operation loop (32 live values would spill)
@@ -533,7 +542,7 @@ struct Qr {
 // columns).
 __device__ void hh_factor(double* A, int m, int n, int lda, double thr, int rho, bool need_r, double* tau,
                           double* red) {
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tid = tix(), lane = tid & 63, wid = tid >> 6;
   int built = 0;
   for (int j = 0; j < n; ++j) {
     double* cj = A + (int64_t)j * lda;
@@ -589,7 +598,7 @@ __device__ void hh_factor(double* A, int m, int n, int lda, double thr, int rho,
 // the identity reflector (tau = 0) hold no reflector data, so they all become
 // unit vectors in one pass; each proper reflector then costs two barriers.
 __device__ void hh_form_q(double* A, int m, int n, int lda, const double* tau, const double* sgn) {
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tid = tix(), lane = tid & 63, wid = tid >> 6;
   for (int j = 0; j < n; ++j)
     if (tau[j] == 0.0) {
       double* cj = A + (int64_t)j * lda;
@@ -634,7 +643,7 @@ __device__ void householder_qr(const Qr& q, double* A, int lda) {
   double* tau = s_lds + kLdsTau;
   double* sgn = s_lds + kLdsSgn;
   double* red = s_lds + kLdsRed;
-  const int m = q.m, n = q.n, tid = threadIdx.x;
+  const int m = q.m, n = q.n, tid = tix();
   double p = 0.0;
   for (int j = 0; j < n; ++j)
     for (int i = tid; i < m; i += kCT) {
@@ -666,7 +675,7 @@ __device__ void householder_qr(const Qr& q, double* A, int lda) {
 // below the matrix, live = false); after a barrier the 16 stripes are added
 // in order into W (32 x 32, column-major, mirrored).
 __device__ __forceinline__ void stripe_gram(const double (&f)[8][2], bool live, double* part, double* W) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = tix(), lane = tid & 63, w = tid >> 6;
   v4d g00 = {0.0, 0.0, 0.0, 0.0}, g10 = g00, g11 = g00;
   if (live) {
 #pragma unroll
@@ -703,7 +712,7 @@ __device__ __forceinline__ void stripe_gram(const double (&f)[8][2], bool live, 
 // triangular factors go through LDS, plus one transposition of Q1.  Returns
 // false, with nothing written, when a pivot test fails.
 __device__ bool cholqr2_reg(const Qr& q) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = tix(), lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int m = q.m, n = q.n;
   const int r0 = 32 * w;
@@ -864,7 +873,7 @@ __device__ void wg_qr(const Qr& q) {
     return;
   }
   // larger matrices: Householder in the device scratch buffer
-  const int tid = threadIdx.x;
+  const int tid = tix();
   for (int64_t e = tid; e < (int64_t)m * n; e += kCT) {
     const int i = (int)(e % m), j = (int)(e / m);
     q.aux[e] = q.M[i * q.mrs + j * q.mcs];
@@ -876,7 +885,7 @@ __device__ void wg_qr(const Qr& q) {
 // ------------------------------------------------------------------ ops
 
 __device__ __forceinline__ void exec_op(const ChainOp& op) {
-  const int tid = threadIdx.x;
+  const int tid = tix();
   switch (op.type) {
     case kOpGemm:
       wg_gemm(Gemm{op.m, op.n, op.k, op.a, op.ars, op.acs, op.b, op.brs, op.bcs, op.c, op.crs, op.ccs, op.c32});
@@ -934,7 +943,19 @@ __device__ __forceinline__ void exec_op(const ChainOp& op) {
   }
 }
 
-__global__ void __launch_bounds__(kCT) k_chain(const ChainOp* __restrict__ ops, int count, int64_t* trace) {
+// Workgroup b runs ops lists[b][first .. first + count): one workgroup per
+// stream of a batch (one stream alone: a batch of one).
+// The lists are read-only while the kernel runs: reading them through the
+// constant address space lets every operation descriptor arrive in scalar
+// registers (through a generic pointer they would be fetched per lane and kept
+// in vector registers, which spill).
+typedef const TT_CONSTANT_AS ChainOp ConstChainOp;
+typedef const TT_CONSTANT_AS uint64_t ConstWord;
+
+__global__ void __launch_bounds__(kCT) k_chain(const ChainOp* const* __restrict__ lists, int first, int count,
+                                                int64_t* trace) {
+  const uint64_t base = ((ConstWord*)(const void*)lists)[blockIdx.x];
+  ConstChainOp* ops = (ConstChainOp*)base + first;
   for (int i = 0; i < count; ++i) {
     const ChainOp op = ops[i];
     if (trace && threadIdx.x == 0) trace[2 * i] = (int64_t)wall_clock64();
@@ -967,10 +988,12 @@ bool chain_op_supported(const ChainOp& op) {
   return true;
 }
 
-hipError_t chain_run(hipStream_t st, const ChainOp* ops_dev, int count, int64_t* trace) {
+hipError_t chain_run(hipStream_t st, const ChainOp* const* lists_dev, int nlists, int first, int count,
+                     int64_t* trace) {
   if (count <= 0) return hipSuccess;
   if (!g_chain_ready) return hipErrorNotInitialized;
-  hipLaunchKernelGGL(k_chain, dim3(1), dim3(kCT), kChainLds, st, ops_dev, count, trace);
+  if (nlists < 1 || (trace && nlists != 1)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_chain, dim3(nlists), dim3(kCT), kChainLds, st, lists_dev, first, count, trace);
   return hipGetLastError();
 }
 

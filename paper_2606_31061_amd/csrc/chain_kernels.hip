@@ -1,7 +1,7 @@
 // FP64 contractions launched over the whole GPU: the interface products of
 // the update that are too large for the one-workgroup chain (chain_exec.hip),
-// and the reconstruction of a slice from the cores (output conversion
-// included).  The slice contractions that stream the whole slice live in
+// for one stream or a batch of same-shape streams, and the reconstruction of
+// a slice from the cores (output conversion included).  The slice contractions that stream the whole slice live in
 // pass_kernels.hip.
 #include "tt_internal.h"
 
@@ -33,6 +33,34 @@ __global__ void __launch_bounds__(256) k_gemm64(int64_t M, int64_t N, int64_t K,
   }
 }
 
+typedef const TT_CONSTANT_AS ChainOp ConstChainOp;
+typedef const TT_CONSTANT_AS uint64_t ConstWord;
+
+// The same product for the GEMM op lists[blockIdx.y][idx] of a batch.  The
+// lists are read-only during the launch; reading them through the constant
+// address space keeps the descriptor in scalar registers.
+__global__ void __launch_bounds__(256) k_gemm64_ops(const ChainOp* const* __restrict__ lists, int idx, int ks) {
+  const uint64_t base = ((ConstWord*)(const void*)lists)[blockIdx.y];
+  const ChainOp op = ((ConstChainOp*)base)[idx];
+  const int64_t M = op.m, N = op.n, K = op.k;
+  const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int q = (int)(gt % ks);
+  const int64_t out = gt / ks;
+  const bool valid = out < M * N;
+  const int64_t i = valid ? out % M : 0, j = valid ? out / M : 0;
+  double acc = 0.0;
+  if (valid) {
+    const double* a = op.a + i * op.ars;
+    const double* b = op.b + j * op.bcs;
+    for (int64_t k = q; k < K; k += ks) acc = fma(a[k * op.acs], b[k * op.brs], acc);
+  }
+  for (int o = ks >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (valid && q == 0) {
+    if (op.c) op.c[i * op.crs + j * op.ccs] = acc;
+    if (op.c32) op.c32[i * op.crs + j * op.ccs] = (float)acc;
+  }
+}
+
 __global__ void k_convert_out(const double* src, void* dst, int dt, int64_t n) {
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
     if (dt == TT_F64) static_cast<double*>(dst)[e] = src[e];
@@ -61,6 +89,19 @@ hipError_t gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K,
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_gemm64, dim3((unsigned)blocks), dim3(256), 0, st, M, N, K, ks, A, ars, acs, B, brs, bcs,
                      C, crs, ccs, C32);
+  return hipGetLastError();
+}
+
+hipError_t gemm64_ops(hipStream_t st, const ChainOp* const* lists_dev, int nlists, int idx, int64_t M, int64_t N,
+                      int64_t K) {
+  if (M <= 0 || N <= 0) return hipSuccess;
+  if (nlists < 1 || nlists > 65535) return hipErrorInvalidValue;
+  int ks = 1;
+  while (ks < 64 && (int64_t)ks * 8 < K) ks <<= 1;
+  const int64_t threads = M * N * ks;
+  const int64_t blocks = (threads + 255) / 256;
+  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gemm64_ops, dim3((unsigned)blocks, nlists), dim3(256), 0, st, lists_dev, idx, ks);
   return hipGetLastError();
 }
 

@@ -13,6 +13,16 @@ namespace ttk {
 tt_status set_error(tt_status st, const char* msg);
 
 // Threads of the workgroup that runs the chain operation lists.
+// Device data that no thread writes while a kernel runs, reached through a
+// pointer: in the device pass it is read through the constant address space,
+// so uniform reads (operation descriptors) go to scalar registers.  The host
+// pass never dereferences such pointers.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define TT_CONSTANT_AS __attribute__((address_space(4)))
+#else
+#define TT_CONSTANT_AS
+#endif
+
 constexpr int kChainThreads = 1024;
 
 // ---------------------------------------------------------------- chain lists
@@ -54,10 +64,12 @@ struct ChainOp {
 // Sets the kernels' LDS size; once per process before the first launch.
 hipError_t chain_setup(size_t lds_limit);
 bool chain_op_supported(const ChainOp& op);
-// Runs ops_dev[0..count) (device array) in order on one workgroup.  If trace
-// is not null, trace[2i] and trace[2i+1] receive the device wall clock at the
-// start and end of op i.
-hipError_t chain_run(hipStream_t st, const ChainOp* ops_dev, int count, int64_t* trace = nullptr);
+// Runs lists[b][first .. first + count) in order, one workgroup per list b
+// (lists_dev: device array of nlists op-list pointers).  If trace is not null
+// (nlists == 1 only), trace[2i] and trace[2i+1] receive the device wall clock
+// at the start and end of op first + i.
+hipError_t chain_run(hipStream_t st, const ChainOp* const* lists_dev, int nlists, int first, int count,
+                     int64_t* trace = nullptr);
 // Runs one operation passed by value.
 hipError_t chain_run_one(hipStream_t st, const ChainOp& op);
 // Rows of the slice staged per wave in pass 2 (multiple of 8).
@@ -72,6 +84,11 @@ hipError_t gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K,
                   const double* B, int64_t brs, int64_t bcs,
                   double* C, int64_t crs, int64_t ccs, float* C32);
 
+// The GEMM lists[b][idx] (kOpGemm, m x n x k equal across b) over the whole
+// GPU for every list b.
+hipError_t gemm64_ops(hipStream_t st, const ChainOp* const* lists_dev, int nlists, int idx, int64_t M, int64_t N,
+                      int64_t K);
+
 // Element conversion FP64 -> out dtype (F64/F32).
 hipError_t convert_out(hipStream_t st, const double* src, void* dst, tt_dtype dt, int64_t n);
 
@@ -79,6 +96,17 @@ hipError_t convert_out(hipStream_t st, const double* src, void* dst, tt_dtype dt
 // Pass 1: Z(p,a) = sum_j X(p,j) B(a,j), X P x J (p fastest) of dtype `xdt`,
 // B r x J FP32; Z written FP64 (P x r column-major) from FP32 partial tiles
 // (ws, plan.ws_floats floats) added in FP64.  Sets *flag if Z is non-finite.
+// Per-member pointers of a batch of same-shape streams: the slice x (its
+// element type is the batch's), the interface w (B for pass 1, A for pass 2),
+// the output (Z or Y), pass 1's partial tiles and the non-finite flag.
+struct PassPtrs {
+  const void* x;
+  const float* w;
+  double* out;
+  float* ws;
+  int* flag;
+};
+
 struct Pass1Plan {
   int vec = 1;        // rows per lane (row tile = 32 vec)
   int ntn = 1;        // 32-column MFMA tiles of the rank (r <= 32 ntn)
@@ -90,13 +118,17 @@ struct Pass1Plan {
 Pass1Plan pass1_plan(int64_t P, int64_t J, int r, int cus);
 // Recomputes tiles and ws_floats after vec/ntn/waves/chunks were set.
 Pass1Plan finish_plan(Pass1Plan plan, int64_t P);
+// With batch != null (device array of nbatch entries) the grid gains a member
+// index and every member's pointers come from the array (X, B, Z, ws, flag
+// are then ignored).
 hipError_t pass1(hipStream_t st, const void* X, tt_dtype xdt, const Pass1Plan& plan, int64_t P, int64_t J, int r,
-                 const float* B, double* Z, float* ws, int* flag);
+                 const float* B, double* Z, float* ws, int* flag, const PassPtrs* batch = nullptr,
+                 int nbatch = 1);
 
 // Pass 2: Y(a,j) = sum_p A(p,a) X(p,j); A P x r FP32 column-major; Y FP64
 // r x J column-major.  Sets *flag if Y non-finite.
 hipError_t pass2(hipStream_t st, const void* X, tt_dtype xdt, int64_t P, int64_t J, int r,
-                 const float* A, double* Y, int* flag);
+                 const float* A, double* Y, int* flag, const PassPtrs* batch = nullptr, int nbatch = 1);
 
 // Reconstruction of the latest slice: out = G_1 x ... x G_m x g (FP64 chain).
 // Implemented on the runtime side with gemm64.

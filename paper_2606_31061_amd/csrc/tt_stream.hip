@@ -19,6 +19,7 @@
 // workgroup (chain_exec.hip); large contractions and the passes are launches
 // of their own.  Nothing is read back to the host during a push.
 #include "tt_internal.h"
+#include "tt_batch.h"
 
 #include <algorithm>
 #include <cmath>
@@ -124,6 +125,7 @@ struct tt_stream {
   double* state[2] = {nullptr, nullptr};
   int cur = 0;               // state[cur] is the committed state
   UpdatePlan plan[2];        // plan[p] reads state[p], writes state[p ^ 1]
+  ttk::ChainOp** plist = nullptr;  // device {plan[0].dev, plan[1].dev}
   double* work = nullptr;
   double* Rbuf = nullptr;
   int64_t* trace = nullptr;  // 2 stamps per chain op (TT_FLAG_PROFILE_OPS)
@@ -419,24 +421,30 @@ void build_plan(tt_stream* s, int par) {
   }
 }
 
-tt_status run_plan(tt_stream* s, const UpdatePlan& P, const void* X, tt_dtype xdt) {
-  hipStream_t st = s->stream;
+// Runs the steps of plan P for n streams that share its structure:
+// lists_dev holds their n op-list pointers; p1/p2 (device arrays of n
+// entries) carry their pass pointers, or are null for one stream, whose own
+// buffers s and slice X are used.
+tt_status run_steps(hipStream_t st, const tt_stream* s, const UpdatePlan& P, const ttk::ChainOp* const* lists_dev,
+                    int n, const void* X, tt_dtype xdt, const ttk::PassPtrs* p1, const ttk::PassPtrs* p2,
+                    int64_t* trace) {
   const int ks = s->kstar;
   for (const Step& step : P.steps) {
     switch (step.kind) {
       case kStepChain:
-        TT_HIP(ttk::chain_run(st, P.dev + step.first, step.count, s->trace ? s->trace + 2 * step.first : nullptr));
+        TT_HIP(ttk::chain_run(st, lists_dev, n, step.first, step.count, trace ? trace + 2 * step.first : nullptr));
         break;
       case kStepWide: {
         const ttk::ChainOp& o = P.ops[step.first];
-        TT_HIP(ttk::gemm64(st, o.m, o.n, o.k, o.a, o.ars, o.acs, o.b, o.brs, o.bcs, o.c, o.crs, o.ccs, o.c32));
+        TT_HIP(ttk::gemm64_ops(st, lists_dev, n, step.first, o.m, o.n, o.k));
         break;
       }
       case kStepPass1:
-        TT_HIP(ttk::pass1(st, X, xdt, s->p1, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->B32, s->Z, s->ws, s->flag));
+        TT_HIP(ttk::pass1(st, X, xdt, s->p1, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->B32, s->Z, s->ws, s->flag, p1,
+                          n));
         break;
       case kStepPass2:
-        TT_HIP(ttk::pass2(st, X, xdt, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->A32, s->Y[0], s->flag));
+        TT_HIP(ttk::pass2(st, X, xdt, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->A32, s->Y[0], s->flag, p2, n));
         break;
       default:
         return fail(TT_ERR_DEVICE, "corrupt update plan");
@@ -445,9 +453,203 @@ tt_status run_plan(tt_stream* s, const UpdatePlan& P, const void* X, tt_dtype xd
   return TT_OK;
 }
 
+tt_status run_plan(tt_stream* s, const void* X, tt_dtype xdt) {
+  return run_steps(s->stream, s, s->plan[s->cur], s->plist + s->cur, 1, X, xdt, nullptr, nullptr, s->trace);
+}
+
+}  // namespace
+
+// A group of same-shape members of a batch and its launch descriptors: op
+// list pointers and pass pointers, uploaded per push from a ring of pinned
+// host slots (a slot is rewritten only after its previous copy completed).
+struct BatchGroup {
+  std::vector<int> idx;
+  ttk::ChainOp** lists_dev = nullptr;
+  ttk::PassPtrs* p1_dev = nullptr;
+  ttk::PassPtrs* p2_dev = nullptr;
+  static constexpr int kSlots = 8;
+  char* host[kSlots] = {};
+  hipEvent_t done[kSlots] = {};
+  bool used[kSlots] = {};
+  int next = 0;
+  size_t bytes = 0;
+};
+
+constexpr uint64_t kBatchMagic = 0x54544241544348ULL;  // "TTBATCH"
+
+struct tt_batch {
+  uint64_t magic = kBatchMagic;
+  hipStream_t stream = nullptr;
+  std::vector<tt_stream*> members;
+  std::vector<BatchGroup> groups;
+  std::vector<int> rejected_seen;
+};
+
+namespace {
+
+bool batch_valid(const tt_batch* b) { return b != nullptr && b->magic == kBatchMagic; }
+
+// Same step sequence: same shapes, split point and plan structure.
+bool same_structure(const tt_stream* a, const tt_stream* b) {
+  if (a->m != b->m || a->kstar != b->kstar || a->I != b->I || a->r != b->r || a->compute != b->compute) return false;
+  const UpdatePlan &pa = a->plan[0], &pb = b->plan[0];
+  if (pa.ops.size() != pb.ops.size() || pa.steps.size() != pb.steps.size()) return false;
+  for (size_t i = 0; i < pa.steps.size(); ++i)
+    if (pa.steps[i].kind != pb.steps[i].kind || pa.steps[i].first != pb.steps[i].first ||
+        pa.steps[i].count != pb.steps[i].count)
+      return false;
+  for (size_t i = 0; i < pa.ops.size(); ++i) {
+    const ttk::ChainOp &x = pa.ops[i], &y = pb.ops[i];
+    if (x.type != y.type || x.m != y.m || x.n != y.n || x.k != y.k || x.rho != y.rho) return false;
+  }
+  return true;
+}
+
+void batch_release(tt_batch* b) {
+  for (BatchGroup& g : b->groups) {
+    if (g.lists_dev) (void)hipFree(g.lists_dev);
+    for (int k = 0; k < BatchGroup::kSlots; ++k) {
+      if (g.done[k]) (void)hipEventDestroy(g.done[k]);
+      if (g.host[k]) (void)hipHostFree(g.host[k]);
+    }
+  }
+  b->groups.clear();
+}
+
 }  // namespace
 
 extern "C" {
+
+tt_status tt_batch_create(tt_stream* const* streams, int32_t n, void* hip_stream, tt_batch** out) {
+  if (!streams || !out || n < 1) return fail(TT_ERR_INVALID_ARG, "null argument or n < 1");
+  *out = nullptr;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(TT_ERR_DEVICE, "hipGetDevice failed");
+  for (int i = 0; i < n; ++i) {
+    const tt_stream* s = streams[i];
+    if (!valid(s)) return fail(TT_ERR_INVALID_ARG, "invalid stream handle");
+    if (s->device != dev) return fail(TT_ERR_INVALID_ARG, "stream lives on another device");
+    if (s->stream != static_cast<hipStream_t>(hip_stream)) return fail(TT_ERR_INVALID_ARG, "stream uses another HIP stream");
+    if (s->trace) return fail(TT_ERR_INVALID_ARG, "streams with TT_FLAG_PROFILE_OPS cannot be batched");
+    for (int j = 0; j < i; ++j)
+      if (streams[j] == s) return fail(TT_ERR_INVALID_ARG, "duplicate stream");
+  }
+  tt_batch* b = new (std::nothrow) tt_batch();
+  if (!b) return fail(TT_ERR_OOM, "host allocation failed");
+  b->stream = static_cast<hipStream_t>(hip_stream);
+  b->members.assign(streams, streams + n);
+  b->rejected_seen.resize(n);
+  for (int i = 0; i < n; ++i) {
+    bool placed = false;
+    for (BatchGroup& g : b->groups)
+      if (same_structure(b->members[g.idx[0]], b->members[i])) {
+        g.idx.push_back(i);
+        placed = true;
+        break;
+      }
+    if (!placed) {
+      b->groups.emplace_back();
+      b->groups.back().idx.push_back(i);
+    }
+    b->rejected_seen[i] = b->members[i]->rejected_seen;
+  }
+  for (BatchGroup& g : b->groups) {
+    const size_t k = g.idx.size();
+    g.bytes = k * (sizeof(ttk::ChainOp*) + 2 * sizeof(ttk::PassPtrs));
+    void* d = nullptr;
+    if (hipMalloc(&d, g.bytes) != hipSuccess) {
+      batch_release(b);
+      delete b;
+      return fail(TT_ERR_OOM, "batch descriptor allocation failed");
+    }
+    g.lists_dev = static_cast<ttk::ChainOp**>(d);
+    g.p1_dev = reinterpret_cast<ttk::PassPtrs*>(static_cast<char*>(d) + k * sizeof(ttk::ChainOp*));
+    g.p2_dev = g.p1_dev + k;
+    for (int q = 0; q < BatchGroup::kSlots; ++q) {
+      void* h = nullptr;
+      if (hipHostMalloc(&h, g.bytes, hipHostMallocDefault) != hipSuccess ||
+          hipEventCreateWithFlags(&g.done[q], hipEventDisableTiming) != hipSuccess) {
+        if (h) (void)hipHostFree(h);
+        batch_release(b);
+        delete b;
+        return fail(TT_ERR_OOM, "batch staging allocation failed");
+      }
+      g.host[q] = static_cast<char*>(h);
+    }
+  }
+  *out = b;
+  return TT_OK;
+}
+
+tt_status tt_batch_push(tt_batch* b, const void* const* slices, tt_dtype dtype) {
+  if (!batch_valid(b) || !slices) return fail(TT_ERR_INVALID_ARG, "invalid batch or null slices");
+  if (dtype != TT_F64 && dtype != TT_F32 && dtype != TT_BF16) return fail(TT_ERR_INVALID_ARG, "bad dtype");
+  for (size_t i = 0; i < b->members.size(); ++i)
+    if (!slices[i]) return fail(TT_ERR_INVALID_ARG, "null slice");
+  for (BatchGroup& g : b->groups) {
+    const int k = (int)g.idx.size();
+    const int q = g.next;
+    g.next = (g.next + 1) % BatchGroup::kSlots;
+    if (g.used[q]) TT_HIP(hipEventSynchronize(g.done[q]));
+    char* h = g.host[q];
+    ttk::ChainOp** lists = reinterpret_cast<ttk::ChainOp**>(h);
+    ttk::PassPtrs* p1 = reinterpret_cast<ttk::PassPtrs*>(h + k * sizeof(ttk::ChainOp*));
+    ttk::PassPtrs* p2 = p1 + k;
+    for (int i = 0; i < k; ++i) {
+      tt_stream* s = b->members[g.idx[i]];
+      lists[i] = s->plan[s->cur].dev;
+      p1[i] = ttk::PassPtrs{slices[g.idx[i]], s->B32, s->Z, s->ws, s->flag};
+      p2[i] = ttk::PassPtrs{slices[g.idx[i]], s->A32, s->Y[0], nullptr, s->flag};
+    }
+    TT_HIP(hipMemcpyAsync(g.lists_dev, h, g.bytes, hipMemcpyHostToDevice, b->stream));
+    TT_HIP(hipEventRecord(g.done[q], b->stream));
+    g.used[q] = true;
+    tt_stream* s0 = b->members[g.idx[0]];
+    tt_status st = run_steps(b->stream, s0, s0->plan[s0->cur], g.lists_dev, k, nullptr, dtype, g.p1_dev, g.p2_dev,
+                             nullptr);
+    if (st != TT_OK) return st;
+    for (int i = 0; i < k; ++i) {
+      tt_stream* s = b->members[g.idx[i]];
+      s->cur ^= 1;
+      s->pushes++;
+    }
+  }
+  return TT_OK;
+}
+
+tt_status tt_batch_synchronize(tt_batch* b, int32_t* rejected) {
+  if (!batch_valid(b)) return fail(TT_ERR_INVALID_ARG, "invalid batch");
+  TT_HIP(hipStreamSynchronize(b->stream));
+  bool any = false;
+  for (size_t i = 0; i < b->members.size(); ++i) {
+    tt_stream* s = b->members[i];
+    int rej = 0;
+    TT_HIP(hipMemcpy(&rej, s->rejected, sizeof(int), hipMemcpyDeviceToHost));
+    const int fresh = rej - b->rejected_seen[i];
+    if (rejected) rejected[i] = fresh;
+    if (fresh > 0) any = true;
+    b->rejected_seen[i] = rej;
+    s->rejected_seen = rej;
+  }
+  return any ? fail(TT_ERR_NONFINITE, "a slice contained NaN/Inf; its stream's update was discarded") : TT_OK;
+}
+
+tt_status tt_batch_info(const tt_batch* b, int32_t* n_streams, int32_t* n_groups) {
+  if (!batch_valid(b)) return fail(TT_ERR_INVALID_ARG, "invalid batch");
+  if (n_streams) *n_streams = (int32_t)b->members.size();
+  if (n_groups) *n_groups = (int32_t)b->groups.size();
+  return TT_OK;
+}
+
+tt_status tt_batch_destroy(tt_batch* b) {
+  if (!batch_valid(b)) return fail(TT_ERR_INVALID_ARG, "invalid batch");
+  (void)hipStreamSynchronize(b->stream);
+  batch_release(b);
+  b->magic = kDead;
+  delete b;
+  return TT_OK;
+}
+
 
 const char* tt_last_error_string(void) { return g_last_error.c_str(); }
 
@@ -612,6 +814,12 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
     TT_HIP_BAIL(hipMemcpyAsync(P.dev, P.ops.data(), sizeof(ttk::ChainOp) * P.ops.size(), hipMemcpyHostToDevice,
                                s->stream));
   }
+  {
+    ttk::ChainOp* lists[2] = {s->plan[0].dev, s->plan[1].dev};
+    s->plist = static_cast<ttk::ChainOp**>(dev_alloc(s, sizeof(lists)));
+    if (!s->plist) return bail(TT_ERR_OOM, "plan allocation failed");
+    TT_HIP_BAIL(hipMemcpy(s->plist, lists, sizeof(lists), hipMemcpyHostToDevice));
+  }
   if (s->flags & TT_FLAG_PROFILE_OPS) {
     s->trace_len = (int64_t)std::max(s->plan[0].ops.size(), s->plan[1].ops.size());
     s->trace = static_cast<int64_t*>(dev_alloc(s, sizeof(int64_t) * 2 * s->trace_len));
@@ -644,7 +852,7 @@ tt_status tt_stream_push_slice(tt_stream* s, const void* slice, tt_dtype dtype, 
     X = s->stage;
   }
   TT_HIP(hipEventRecord(s->ev0, s->stream));
-  tt_status st = run_plan(s, s->plan[s->cur], X, dtype);
+  tt_status st = run_plan(s, X, dtype);
   if (st != TT_OK) return st;
   s->traced_plan = s->cur;
   s->cur ^= 1;

@@ -92,6 +92,11 @@ def test_null_handles_are_rejected():
     assert lib.tt_stream_destroy(None) == binding.TT_ERR_INVALID_ARG
     assert lib.tt_stream_synchronize(None) == binding.TT_ERR_INVALID_ARG
     assert lib.tt_stream_create(None, None) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_batch_create(None, 0, None, None) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_batch_push(None, None, 1) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_batch_synchronize(None, None) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_batch_info(None, None, None) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_batch_destroy(None) == binding.TT_ERR_INVALID_ARG
     assert lib.tt_kernel_pass1_workspace(0, 1, 1) == 0
 
 

@@ -1,0 +1,123 @@
+"""Batches of streams (include/tt_batch.h) on the GPU: every member of a batch
+is computed exactly as when pushed alone (bitwise equal state), members of
+different shapes form separate groups, a non-finite slice is rejected for its
+own stream only, and batched results match the FP64 oracle."""
+
+import numpy as np
+import pytest
+
+from oracle import ttals
+from tests.gpu_util import say, to_device_slice, torch_cuda, rel
+from ttgen import exact_tt_stream, config_c3
+
+pytestmark = pytest.mark.gpu
+
+M_TOL = 1e-5
+
+
+def _members(shapes, T, seed0=100):
+    out = []
+    for q, (modes, ranks) in enumerate(shapes):
+        st = exact_tt_stream(modes, ranks, ranks, T, seed0 + 2 * q, seed0 + 2 * q + 1, sigma=1e-2)
+        init = st.init()
+        out.append((st, init, list(st.frames(1, T))))
+    return out
+
+
+def _states_equal(a, b):
+    ca, ga, ta = a.get_state()
+    cb, gb, tb = b.get_state()
+    return ta == tb and all(np.array_equal(x, y) for x, y in zip(ca, cb)) and np.array_equal(ga, gb)
+
+
+def _run_alone_and_batched(torch, members, T):
+    from paper_2606_31061_amd import TTBatch, TTStream
+    alone = [TTStream(st.modes, st.ranks, init=init) for st, init, _ in members]
+    batched = [TTStream(st.modes, st.ranks, init=init) for st, init, _ in members]
+    batch = TTBatch(batched)
+    dev = [[to_device_slice(torch, X) for X in xs] for _, _, xs in members]
+    for t in range(T):
+        for s, xs in zip(alone, dev):
+            s.push(xs[t])
+        batch.push([xs[t] for xs in dev])
+    assert batch.synchronize() == [0] * len(members)
+    for s in alone:
+        s.synchronize()
+    return alone, batched, batch
+
+
+def test_same_shape_batch_is_bitwise_equal_to_solo_runs():
+    torch = torch_cuda()
+    T = 6
+    members = _members([((24, 20, 3), (4, 4, 3))] * 5, T)
+    say("batch: 5 streams of (24,20,3) r=(4,4,3)")
+    alone, batched, batch = _run_alone_and_batched(torch, members, T)
+    assert batch.info() == {"streams": 5, "groups": 1}
+    for a, b in zip(alone, batched):
+        assert _states_equal(a, b)
+    # and the batched reconstructions follow the oracle
+    for (st, init, xs), s in zip(members, batched):
+        ref = ttals.run_stream(xs, init[0], init[1], keep_M=True)
+        assert rel(s.reconstruct(), ref.infos[-1].M, np.linalg.norm(xs[-1])) <= M_TOL
+    batch.close()
+
+
+def test_mixed_shapes_form_groups_and_match_solo_runs():
+    torch = torch_cuda()
+    T = 5
+    shapes = [((32, 32), (4, 4)), ((12, 10, 3), (4, 4, 3)), ((32, 32), (4, 4)),
+              ((6, 5, 4, 3), (3, 4, 4, 2)), ((12, 10, 3), (4, 4, 3)), ((9,), (4,))]
+    members = _members(shapes, T, seed0=300)
+    say("batch: 6 streams in 4 shape groups")
+    alone, batched, batch = _run_alone_and_batched(torch, members, T)
+    assert batch.info() == {"streams": 6, "groups": 4}
+    for a, b in zip(alone, batched):
+        assert _states_equal(a, b)
+    batch.close()
+
+
+def test_full_size_order9_batch_matches_solo_runs():
+    torch = torch_cuda()
+    from paper_2606_31061_amd import TTBatch, TTStream
+    st = config_c3(T=3)
+    init = st.init()
+    xs = [to_device_slice(torch, X) for X in st.frames(1, 3)]
+    say("batch: 2 config-3 streams (order 9, 6.2M-element slices)")
+    a = TTStream(st.modes, st.ranks, init=init)
+    b1 = TTStream(st.modes, st.ranks, init=init)
+    b2 = TTStream(st.modes, st.ranks, init=init)
+    batch = TTBatch([b1, b2])
+    for t in range(3):
+        a.push(xs[t])
+        batch.push([xs[t], xs[(t + 1) % 3]])
+    assert batch.synchronize() == [0, 0]
+    a.synchronize()
+    assert _states_equal(a, b1)
+    batch.close()
+
+
+def test_nonfinite_slice_is_rejected_for_its_member_only():
+    torch = torch_cuda()
+    from paper_2606_31061_amd import TTBatch, TTStream
+    T = 3
+    members = _members([((24, 20, 3), (4, 4, 3))] * 3, T, seed0=500)
+    say("batch: non-finite slice in member 1")
+    streams = [TTStream(st.modes, st.ranks, init=init) for st, init, _ in members]
+    solo = [TTStream(st.modes, st.ranks, init=init) for st, init, _ in members]
+    batch = TTBatch(streams)
+    dev = [[to_device_slice(torch, X) for X in xs] for _, _, xs in members]
+    bad = dev[1][1].clone()
+    bad[7] = float("nan")
+    batch.push([d[0] for d in dev])
+    batch.push([dev[0][1], bad, dev[2][1]])
+    rej = batch.synchronize()
+    assert rej == [0, 1, 0]
+    for i, s in enumerate(solo):
+        s.push(dev[i][0])
+        if i != 1:
+            s.push(dev[i][1])
+        s.synchronize()
+    for a, b in zip(solo, streams):
+        assert _states_equal(a, b)
+    assert [s.time() for s in streams] == [2, 1, 2]
+    batch.close()
