@@ -43,44 +43,25 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def pass_bytes(P, J, r):
-    """Algorithmic HBM bytes of one pass-1 and one pass-2 launch (FP32 slice)."""
-    p1 = 4 * P * J + 4 * r * J + 8 * P * r       # read X, read B_{k*}, write Z (FP64)
-    p2 = 4 * P * J + 4 * P * r + 8 * r * J       # read X, read A_{k*+1}, write Y (FP64)
+def pass_bytes(P, J, r, xbytes=4):
+    """Algorithmic HBM bytes of one pass-1 and one pass-2 launch (slice of
+    xbytes per element; FP32 interfaces; FP64 outputs)."""
+    p1 = xbytes * P * J + 4 * r * J + 8 * P * r  # read X, read B_{k*}, write Z (FP64)
+    p2 = xbytes * P * J + 4 * P * r + 8 * r * J  # read X, read A_{k*+1}, write Y (FP64)
     return p1, p2
 
 
-def time_pass_kernels(torch, pool, P, J, r, reps):
-    """Average device time of the two slice-streaming kernels, launched through
-    the kernel entry points with the update's own shapes and launch
-    configuration, on torch's current stream, timed with HIP events."""
-    from paper_2606_31061_amd import binding
-    stream = torch.cuda.current_stream()
-    sp = int(stream.cuda_stream)
-    B = torch.randn(r * J, dtype=torch.float32, device="cuda")
-    A = torch.randn(P * r, dtype=torch.float32, device="cuda")
-    Z = torch.empty(P * r, dtype=torch.float64, device="cuda")
-    Y = torch.empty(r * J, dtype=torch.float64, device="cuda")
-    ws = torch.zeros(binding.tt_kernel_pass1_workspace(P, J, r), dtype=torch.uint8, device="cuda")
-    flag = torch.zeros(1, dtype=torch.int32, device="cuda")
-    out = {}
-    for name in ("pass1", "pass2"):
-        def launch(i):
-            x = pool[i % len(pool)]
-            if name == "pass1":
-                return binding.tt_kernel_pass1(x, P, J, r, B, Z, ws, flag, sp)
-            return binding.tt_kernel_pass2(x, P, J, r, A, Y, flag, sp)
-        for i in range(5):
-            assert launch(i) == 0
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for i in range(reps):
-            launch(i)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        out[name] = e0.elapsed_time(e1) / reps  # ms per launch
-    return out
+def time_passes_in_update(stream, pool, steps):
+    """Average device time of the two slice passes inside the update: HIP
+    events recorded on the update's stream around each pass (the stream was
+    created with profile_ops)."""
+    t1, t2 = [], []
+    for i in range(steps):
+        stream.push(pool[i % len(pool)])
+        a, b = stream.pass_profile()
+        t1.append(a)
+        t2.append(b)
+    return {"pass1": float(np.mean(t1)), "pass2": float(np.mean(t2))}
 
 
 def cpu_baseline(spec, seconds_budget: float):
@@ -116,6 +97,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
+    ap.add_argument("--compute", default="f32", choices=["f32", "bf16"],
+                    help="contraction precision; bf16 also stores the slices as BF16")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="use the default pass launch shapes instead of tuning them for the workload")
     ap.add_argument("--profile-ops", action="store_true",
                     help="also print the per-operation times of the update's chain (stderr)")
     args = ap.parse_args()
@@ -134,10 +119,12 @@ def main():
     pool = []
     for t in range(1, pool_n + 1):
         X = spec.frame(t)
-        pool.append(torch.from_numpy(np.ascontiguousarray(X.reshape(-1, order="F"))).cuda())
+        x = torch.from_numpy(np.ascontiguousarray(X.reshape(-1, order="F"))).cuda()
+        pool.append(x.to(torch.bfloat16) if args.compute == "bf16" else x)
     torch.cuda.synchronize()
     cores, g = spec.init()
-    s = TTStream(spec.modes, spec.ranks, init=(cores, g))
+    tune = not args.no_autotune
+    s = TTStream(spec.modes, spec.ranks, init=(cores, g), compute=args.compute, autotune=tune)
     info = s.info()
     k = info["split_point"]
     P = int(np.prod(spec.modes[:k]))
@@ -171,19 +158,17 @@ def main():
     s.close()
     log(f"latency p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
 
+    # the passes inside the update, and optionally the chain's operations
+    sp = TTStream(spec.modes, spec.ranks, init=(cores, g), profile_ops=True, compute=args.compute, autotune=tune)
+    kt = time_passes_in_update(sp, pool, args.kernel_reps)
     if args.profile_ops:
-        sp = TTStream(spec.modes, spec.ranks, init=(cores, g), profile_ops=True)
-        for i in range(4):
-            sp.push(pool[i % pool_n])
         prof = sp.op_profile()
-        sp.close()
         tot = sum(p[2] for p in prof)
         log(f"chain operations of one update: {len(prof)} ops, {tot:.1f} us on the chain workgroup")
         for i, (kind, dims, us) in enumerate(prof):
             log(f"  op {i:3d} {kind:6s} m={dims[0]:6d} n={dims[1]:6d} k={dims[2]:6d} {us:9.2f} us")
-
-    kt = time_pass_kernels(torch, pool, P, J, r, args.kernel_reps)
-    b1, b2 = pass_bytes(P, J, r)
+    sp.close()
+    b1, b2 = pass_bytes(P, J, r, 2 if args.compute == "bf16" else 4)
     gbs1 = b1 / (kt["pass1"] * 1e-3) / 1e9
     gbs2 = b2 / (kt["pass2"] * 1e-3) / 1e9
     log(f"pass1 {kt['pass1']*1e3:.1f} us {gbs1:.0f} GB/s; pass2 {kt['pass2']*1e3:.1f} us {gbs2:.0f} GB/s")
@@ -207,7 +192,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": args.compute,
         "data": "synthetic",
         "config": {
             "workload": spec.name,
@@ -217,6 +202,7 @@ def main():
             "split_point": k,
             "frame_pool": pool_n,
             "parallelism": "single stream, one GPU",
+            "pass_plans": "tuned" if tune else "default",
         },
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "device_last": dev_ms},

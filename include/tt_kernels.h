@@ -34,6 +34,24 @@ size_t tt_kernel_pass1_workspace(int64_t P, int64_t J, int32_t r);
 tt_status tt_kernel_pass2(const void* X, tt_dtype x_dtype, int64_t P, int64_t J, int32_t r,
                           const float* A, double* Y, int32_t* nonfinite_flag, void* hip_stream);
 
+/* BF16-input, FP32-accumulate variants of the two passes (the reduced-
+ * precision option of the contractions; the QR and Gram steps of Section 3.4
+ * stay FP64): every element of X (any x_dtype) and of the interface is
+ * rounded to BF16 (round to nearest even), products are accumulated in FP32
+ * per tile and the tiles' partial sums are added in FP64 in a fixed order.
+ * Same shapes, layouts and flag as tt_kernel_pass1 / tt_kernel_pass2; the
+ * result does not depend on block timing.  The workspace (device, caller-
+ * owned, at least the size returned by the matching _workspace function, no
+ * initialisation needed) receives FP32 partial tiles.  A slice value beyond
+ * the BF16 range becomes infinite and sets the flag. */
+size_t tt_kernel_pass1_bf16_workspace(int64_t P, int64_t J, int32_t r);
+tt_status tt_kernel_pass1_bf16(const void* X, tt_dtype x_dtype, int64_t P, int64_t J, int32_t r,
+                               const float* B, double* Z, void* workspace, int32_t* nonfinite_flag,
+                               void* hip_stream);
+size_t tt_kernel_pass2_bf16_workspace(int64_t P, int64_t J, int32_t r);
+tt_status tt_kernel_pass2_bf16(const void* X, tt_dtype x_dtype, int64_t P, int64_t J, int32_t r,
+                               const float* A, double* Y, void* workspace, int32_t* nonfinite_flag,
+                               void* hip_stream);
 /* Thin QR of an m x n FP64 matrix (m >= n >= 1, n <= 256) as used to
  * re-orthogonalise a core (Algorithm 1; Section 3.4.2): M = Q R, Q^T Q = I,
  * diag(R) >= 0.  Well-conditioned matrices with n <= 32 take CholeskyQR2

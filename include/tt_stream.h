@@ -92,6 +92,11 @@ typedef struct {
 #define TT_FLAG_SYNC_PUSH 0x1u   /* push waits for its update and reports NONFINITE */
 #define TT_FLAG_NO_ORTHO 0x2u    /* ablation: skip the LQ sweep and the QR steps    */
 #define TT_FLAG_PROFILE_OPS 0x4u /* time every chain operation (tt_stream_op_profile) */
+/* TT_FLAG_AUTOTUNE: at create, time candidate launch shapes of the two slice
+ * passes for this stream's shape and precision (once per process and shape,
+ * on hip_stream, which is synchronised) and use the fastest; streams of one
+ * shape then share the plan, alone or in a batch. */
+#define TT_FLAG_AUTOTUNE 0x8u
 
 /* Create a stream.  The initial cores are the paper's random initialisation
  * (Algorithm 1, first line): taken from init_cores, else i.i.d. N(0,1) from a
@@ -170,6 +175,13 @@ tt_status tt_stream_last_push_ms(tt_stream* s, float* ms);
  * work.  Errors: INVALID_ARG (null), STATE (flag not set or no push yet). */
 tt_status tt_stream_op_profile(tt_stream* s, int64_t cap, int32_t* kinds, int64_t* dims, double* us,
                                int64_t* count);
+
+/* Device times of the two slice passes of the last push (HIP events recorded
+ * on the handle's stream around each pass's launches; pass 1 includes its
+ * partial-tile reduction), for a stream created with TT_FLAG_PROFILE_OPS.
+ * Waits for the handle's work.  Errors: INVALID_ARG (null), STATE (flag not
+ * set or no push yet). */
+tt_status tt_stream_pass_profile(tt_stream* s, float* pass1_ms, float* pass2_ms);
 
 /* Description of the calling thread's last error (never NULL). */
 const char* tt_last_error_string(void);

@@ -31,6 +31,7 @@ TT_F64, TT_F32, TT_BF16 = 0, 1, 2
 TT_FLAG_SYNC_PUSH = 0x1
 TT_FLAG_NO_ORTHO = 0x2
 TT_FLAG_PROFILE_OPS = 0x4
+TT_FLAG_AUTOTUNE = 0x8
 
 
 class TTError(RuntimeError):
@@ -87,6 +88,7 @@ def load_library(path: str = LIB_PATH):
         "tt_stream_last_push_ms": (c_int, [sv, POINTER(c_float)]),
         "tt_stream_op_profile": (c_int, [sv, c_int64, POINTER(c_int32), POINTER(c_int64), POINTER(c_double),
                                          POINTER(c_int64)]),
+        "tt_stream_pass_profile": (c_int, [sv, POINTER(c_float), POINTER(c_float)]),
         "tt_last_error_string": (c_char_p, []),
         "tt_version": (c_char_p, []),
         "tt_batch_create": (c_int, [POINTER(c_void_p), c_int32, sv, POINTER(c_void_p)]),
@@ -98,6 +100,10 @@ def load_library(path: str = LIB_PATH):
         "tt_kernel_pass1_workspace": (c_size_t, [c_int64, c_int64, c_int32]),
         "tt_kernel_pass2": (c_int, [sv, c_int, c_int64, c_int64, c_int32, sv, sv, sv, sv]),
         "tt_kernel_qr": (c_int, [c_int32, c_int32, sv, sv, sv, sv, sv]),
+        "tt_kernel_pass1_bf16": (c_int, [sv, c_int, c_int64, c_int64, c_int32, sv, sv, sv, sv, sv]),
+        "tt_kernel_pass1_bf16_workspace": (c_size_t, [c_int64, c_int64, c_int32]),
+        "tt_kernel_pass2_bf16": (c_int, [sv, c_int, c_int64, c_int64, c_int32, sv, sv, sv, sv, sv]),
+        "tt_kernel_pass2_bf16_workspace": (c_size_t, [c_int64, c_int64, c_int32]),
     }
     for name, (res, args) in proto.items():
         fn = getattr(lib, name)
@@ -197,7 +203,7 @@ class TTStream:
 
     def __init__(self, modes, ranks, init=None, *, seed: int = 0, stream=None, keep_history: bool = False,
                  history_capacity: int = 0, split_point: int = 0, sync_push: bool = False,
-                 profile_ops: bool = False):
+                 profile_ops: bool = False, compute: str = "f32", autotune: bool = False):
         self.modes = tuple(int(v) for v in modes)
         self.ranks = tuple(int(v) for v in ranks)
         self.n = int(np.prod(self.modes))
@@ -212,9 +218,10 @@ class TTStream:
         self.hip_stream = sp
         self._h = tt_stream_create(self.modes, self.ranks, init_cores=flat, seed=seed, hip_stream=sp,
                                    keep_history=keep_history, history_capacity=history_capacity,
-                                   split_point=split_point,
+                                   split_point=split_point, compute={"f32": TT_F32, "bf16": TT_BF16}[compute],
                                    flags=(TT_FLAG_SYNC_PUSH if sync_push else 0)
-                                   | (TT_FLAG_PROFILE_OPS if profile_ops else 0))
+                                   | (TT_FLAG_PROFILE_OPS if profile_ops else 0)
+                                   | (TT_FLAG_AUTOTUNE if autotune else 0))
         self._lib = load_library()
 
     @staticmethod
@@ -318,6 +325,12 @@ class TTStream:
         names = {1: "gemm", 2: "qr", 3: "normg", 4: "copy", 5: "commit"}
         return [(names.get(kinds[i], "?"), (dims[3 * i], dims[3 * i + 1], dims[3 * i + 2]), us[i]) for i in range(n)]
 
+    def pass_profile(self):
+        """(pass 1 ms, pass 2 ms) of the last push (needs profile_ops=True)."""
+        a, b = c_float(), c_float()
+        _check(self._lib.tt_stream_pass_profile(self._h, byref(a), byref(b)), "tt_stream_pass_profile")
+        return a.value, b.value
+
     def close(self) -> None:
         if self._h is not None and self._h.value:
             _check(tt_stream_destroy(self._h), "tt_stream_destroy")
@@ -352,6 +365,28 @@ def tt_kernel_pass2(X, P: int, J: int, r: int, A, Y, flag, hip_stream: int = 0) 
     return load_library().tt_kernel_pass2(c_void_p(X.data_ptr()), _dtype_code_torch(X), P, J, r,
                                           c_void_p(A.data_ptr()), c_void_p(Y.data_ptr()),
                                           c_void_p(flag.data_ptr()), c_void_p(hip_stream or None))
+
+
+def tt_kernel_pass1_bf16(X, P: int, J: int, r: int, B, Z, workspace, flag, hip_stream: int = 0) -> int:
+    return load_library().tt_kernel_pass1_bf16(c_void_p(X.data_ptr()), _dtype_code_torch(X), P, J, r,
+                                               c_void_p(B.data_ptr()), c_void_p(Z.data_ptr()),
+                                               c_void_p(workspace.data_ptr()), c_void_p(flag.data_ptr()),
+                                               c_void_p(hip_stream or None))
+
+
+def tt_kernel_pass1_bf16_workspace(P: int, J: int, r: int) -> int:
+    return int(load_library().tt_kernel_pass1_bf16_workspace(P, J, r))
+
+
+def tt_kernel_pass2_bf16(X, P: int, J: int, r: int, A, Y, workspace, flag, hip_stream: int = 0) -> int:
+    return load_library().tt_kernel_pass2_bf16(c_void_p(X.data_ptr()), _dtype_code_torch(X), P, J, r,
+                                               c_void_p(A.data_ptr()), c_void_p(Y.data_ptr()),
+                                               c_void_p(workspace.data_ptr()), c_void_p(flag.data_ptr()),
+                                               c_void_p(hip_stream or None))
+
+
+def tt_kernel_pass2_bf16_workspace(P: int, J: int, r: int) -> int:
+    return int(load_library().tt_kernel_pass2_bf16_workspace(P, J, r))
 
 
 def tt_kernel_qr(M, Q, R, workspace, hip_stream: int = 0) -> int:

@@ -17,11 +17,13 @@ tt_status kfail(tt_status st, const char* what, hipError_t e = hipSuccess) {
   return ttk::set_error(st, msg.c_str());
 }
 
-ttk::Pass1Plan plan_for(int64_t P, int64_t J, int r) {
+int device_cus() {
   int dev = 0, cus = 256;
   if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  return ttk::pass1_plan(P, J, r, cus);
+  return cus;
 }
+
+ttk::Pass1Plan plan_for(int64_t P, int64_t J, int r) { return ttk::pass1_plan(P, J, r, device_cus()); }
 
 size_t lds_limit() {
   int dev = 0, lds = 65536;
@@ -56,6 +58,36 @@ tt_status tt_kernel_pass2(const void* X, tt_dtype x_dtype, int64_t P, int64_t J,
   if (ttk::pass_setup() != hipSuccess) return kfail(TT_ERR_DEVICE, "setup");
   hipError_t e = ttk::pass2(static_cast<hipStream_t>(hip_stream), X, x_dtype, P, J, r, A, Y, nonfinite_flag);
   return e == hipSuccess ? TT_OK : kfail(TT_ERR_DEVICE, "pass2", e);
+}
+
+size_t tt_kernel_pass1_bf16_workspace(int64_t P, int64_t J, int32_t r) {
+  if (P < 1 || J < 1 || r < 1 || r > 64) return 0;
+  return ttk::pass1b_plan(P, J, r, device_cus()).ws_bytes;
+}
+
+tt_status tt_kernel_pass1_bf16(const void* X, tt_dtype x_dtype, int64_t P, int64_t J, int32_t r, const float* B,
+                               double* Z, void* workspace, int32_t* nonfinite_flag, void* hip_stream) {
+  if (!X || !B || !Z || !workspace || !nonfinite_flag) return kfail(TT_ERR_INVALID_ARG, "null");
+  if (P < 1 || J < 1 || r < 1 || r > 64) return kfail(TT_ERR_INVALID_ARG, "size");
+  const ttk::PassBPlan pl = ttk::pass1b_plan(P, J, r, device_cus());
+  hipError_t e = ttk::pass1_bf16(static_cast<hipStream_t>(hip_stream), X, x_dtype, pl, P, J, r, B, Z, workspace,
+                                 nonfinite_flag);
+  return e == hipSuccess ? TT_OK : kfail(TT_ERR_DEVICE, "pass1_bf16", e);
+}
+
+size_t tt_kernel_pass2_bf16_workspace(int64_t P, int64_t J, int32_t r) {
+  if (P < 1 || J < 1 || r < 1 || r > 64) return 0;
+  return ttk::pass2b_plan(P, J, r, device_cus()).ws_bytes;
+}
+
+tt_status tt_kernel_pass2_bf16(const void* X, tt_dtype x_dtype, int64_t P, int64_t J, int32_t r, const float* A,
+                               double* Y, void* workspace, int32_t* nonfinite_flag, void* hip_stream) {
+  if (!X || !A || !Y || !workspace || !nonfinite_flag) return kfail(TT_ERR_INVALID_ARG, "null");
+  if (P < 1 || J < 1 || r < 1 || r > 64) return kfail(TT_ERR_INVALID_ARG, "size");
+  const ttk::PassBPlan pl = ttk::pass2b_plan(P, J, r, device_cus());
+  hipError_t e = ttk::pass2_bf16(static_cast<hipStream_t>(hip_stream), X, x_dtype, pl, P, J, r, A, Y, workspace,
+                                 nonfinite_flag);
+  return e == hipSuccess ? TT_OK : kfail(TT_ERR_DEVICE, "pass2_bf16", e);
 }
 
 tt_status tt_kernel_qr(int32_t m, int32_t n, const double* M, double* Q, double* R, double* workspace,

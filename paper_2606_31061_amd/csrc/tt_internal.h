@@ -12,7 +12,6 @@ namespace ttk {
 // Records `msg` as the calling thread's last error and returns `st`.
 tt_status set_error(tt_status st, const char* msg);
 
-// Threads of the workgroup that runs the chain operation lists.
 // Device data that no thread writes while a kernel runs, reached through a
 // pointer: in the device pass it is read through the constant address space,
 // so uniform reads (operation descriptors) go to scalar registers.  The host
@@ -23,6 +22,7 @@ tt_status set_error(tt_status st, const char* msg);
 #define TT_CONSTANT_AS
 #endif
 
+// Threads of the workgroup that runs the chain operation lists.
 constexpr int kChainThreads = 1024;
 
 // ---------------------------------------------------------------- chain lists
@@ -103,7 +103,7 @@ struct PassPtrs {
   const void* x;
   const float* w;
   double* out;
-  float* ws;
+  float* ws;   // the pass's workspace (FP32 partial tiles)
   int* flag;
 };
 
@@ -129,6 +129,45 @@ hipError_t pass1(hipStream_t st, const void* X, tt_dtype xdt, const Pass1Plan& p
 // r x J column-major.  Sets *flag if Y non-finite.
 hipError_t pass2(hipStream_t st, const void* X, tt_dtype xdt, int64_t P, int64_t J, int r,
                  const float* A, double* Y, int* flag, const PassPtrs* batch = nullptr, int nbatch = 1);
+
+// ---------------------------------------------------------------- passes (BF16)
+// The same two contractions with the slice and the interface rounded to BF16
+// (round to nearest even) and FP32 accumulation (v_mfma_f32_32x32x16_bf16).
+// Blocks that split a tile's reduction write FP32 partial tiles to the
+// workspace (no initialisation needed), added in FP64 in chunk order by a
+// second kernel; a block that covers the whole reduction writes the result.
+struct PassBPlan {
+  int vec = 1;        // pass 1: rows per lane (row tile = 32 vec); 8, 4 or 1
+  int waves = 4;      // waves per block
+  int tiles = 1;      // pass 1: row tiles; pass 2: 32-column tiles
+  int chunks = 1;     // pass 1: column-group chunks; pass 2: row chunks
+  int ntn = 1;        // 32-column tiles of the rank
+  size_t ws_bytes = 0;
+};
+PassBPlan pass1b_plan(int64_t P, int64_t J, int r, int cus);
+PassBPlan pass2b_plan(int64_t P, int64_t J, int r, int cus);
+// Recomputes tiles and ws_bytes after the tunable fields were set.
+PassBPlan pass1b_finish(PassBPlan pl, int64_t P, int64_t J);
+PassBPlan pass2b_finish(PassBPlan pl, int64_t P, int64_t J);
+hipError_t pass1_bf16(hipStream_t st, const void* X, tt_dtype xdt, const PassBPlan& plan, int64_t P, int64_t J,
+                      int r, const float* B, double* Z, void* ws, int* flag, const PassPtrs* batch = nullptr,
+                      int nbatch = 1);
+hipError_t pass2_bf16(hipStream_t st, const void* X, tt_dtype xdt, const PassBPlan& plan, int64_t P, int64_t J,
+                      int r, const float* A, double* Y, void* ws, int* flag, const PassPtrs* batch = nullptr,
+                      int nbatch = 1);
+
+// ---------------------------------------------------------------- tuner
+struct PassPlans {
+  Pass1Plan p1;           // FP32 contractions
+  PassBPlan p1b, p2b;     // BF16 contractions
+  bool tuned = false;
+};
+PassPlans default_pass_plans(int64_t P, int64_t J, int r, int cus);
+// Plans of the fastest measured launch shapes for (P, J, r) and the given
+// contraction precision, timed on stream st (synchronised) the first time a
+// shape is seen in the process and cached afterwards.
+hipError_t tuned_pass_plans(int64_t P, int64_t J, int r, tt_dtype compute, int cus, hipStream_t st,
+                            PassPlans* out);
 
 // Reconstruction of the latest slice: out = G_1 x ... x G_m x g (FP64 chain).
 // Implemented on the runtime side with gemm64.

@@ -141,7 +141,8 @@ struct tt_stream {
   double* Gt = nullptr;
   double* Y[2] = {nullptr, nullptr};
   double* qrwork = nullptr;
-  float* ws = nullptr;
+  float* ws = nullptr;       // pass 1 workspace
+  float* ws2 = nullptr;      // pass 2 workspace (BF16 contractions only)
   int* flag = nullptr;
   int* rejected = nullptr;
   int64_t* tdev = nullptr;
@@ -151,9 +152,11 @@ struct tt_stream {
   void* stage = nullptr;
   size_t stage_bytes = 0;
   ttk::Pass1Plan p1;
+  ttk::PassBPlan p1b, p2b;   // BF16 contractions
   int rejected_seen = 0;
   int64_t pushes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evcopy = nullptr;
+  hipEvent_t evpass[4] = {};  // around pass 1 and pass 2 (TT_FLAG_PROFILE_OPS)
   bool timed = false;
 
   double* g_of(double* st) const { return st + coff[m + 1]; }
@@ -190,6 +193,8 @@ void release(tt_stream* s) {
   if (s->ev0) (void)hipEventDestroy(s->ev0);
   if (s->ev1) (void)hipEventDestroy(s->ev1);
   if (s->evcopy) (void)hipEventDestroy(s->evcopy);
+  for (hipEvent_t& e : s->evpass)
+    if (e) (void)hipEventDestroy(e);
 }
 
 tt_status check_shape(int32_t m, const int64_t* modes, const int64_t* ranks) {
@@ -427,7 +432,7 @@ void build_plan(tt_stream* s, int par) {
 // buffers s and slice X are used.
 tt_status run_steps(hipStream_t st, const tt_stream* s, const UpdatePlan& P, const ttk::ChainOp* const* lists_dev,
                     int n, const void* X, tt_dtype xdt, const ttk::PassPtrs* p1, const ttk::PassPtrs* p2,
-                    int64_t* trace) {
+                    int64_t* trace, hipEvent_t const* pass_ev = nullptr) {
   const int ks = s->kstar;
   for (const Step& step : P.steps) {
     switch (step.kind) {
@@ -440,11 +445,23 @@ tt_status run_steps(hipStream_t st, const tt_stream* s, const UpdatePlan& P, con
         break;
       }
       case kStepPass1:
-        TT_HIP(ttk::pass1(st, X, xdt, s->p1, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->B32, s->Z, s->ws, s->flag, p1,
-                          n));
+        if (pass_ev) TT_HIP(hipEventRecord(pass_ev[0], st));
+        if (s->compute == TT_BF16)
+          TT_HIP(ttk::pass1_bf16(st, X, xdt, s->p1b, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->B32, s->Z, s->ws,
+                                 s->flag, p1, n));
+        else
+          TT_HIP(ttk::pass1(st, X, xdt, s->p1, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->B32, s->Z, s->ws, s->flag,
+                            p1, n));
+        if (pass_ev) TT_HIP(hipEventRecord(pass_ev[1], st));
         break;
       case kStepPass2:
-        TT_HIP(ttk::pass2(st, X, xdt, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->A32, s->Y[0], s->flag, p2, n));
+        if (pass_ev) TT_HIP(hipEventRecord(pass_ev[2], st));
+        if (s->compute == TT_BF16)
+          TT_HIP(ttk::pass2_bf16(st, X, xdt, s->p2b, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->A32, s->Y[0], s->ws2,
+                                 s->flag, p2, n));
+        else
+          TT_HIP(ttk::pass2(st, X, xdt, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->A32, s->Y[0], s->flag, p2, n));
+        if (pass_ev) TT_HIP(hipEventRecord(pass_ev[3], st));
         break;
       default:
         return fail(TT_ERR_DEVICE, "corrupt update plan");
@@ -454,7 +471,8 @@ tt_status run_steps(hipStream_t st, const tt_stream* s, const UpdatePlan& P, con
 }
 
 tt_status run_plan(tt_stream* s, const void* X, tt_dtype xdt) {
-  return run_steps(s->stream, s, s->plan[s->cur], s->plist + s->cur, 1, X, xdt, nullptr, nullptr, s->trace);
+  return run_steps(s->stream, s, s->plan[s->cur], s->plist + s->cur, 1, X, xdt, nullptr, nullptr, s->trace,
+                   s->evpass[0] ? s->evpass : nullptr);
 }
 
 }  // namespace
@@ -492,6 +510,14 @@ bool batch_valid(const tt_batch* b) { return b != nullptr && b->magic == kBatchM
 // Same step sequence: same shapes, split point and plan structure.
 bool same_structure(const tt_stream* a, const tt_stream* b) {
   if (a->m != b->m || a->kstar != b->kstar || a->I != b->I || a->r != b->r || a->compute != b->compute) return false;
+  // same launch shapes of the passes (a tuned and an untuned stream differ)
+  const auto same1 = [](const ttk::Pass1Plan& x, const ttk::Pass1Plan& y) {
+    return x.vec == y.vec && x.ntn == y.ntn && x.waves == y.waves && x.chunks == y.chunks;
+  };
+  const auto sameb = [](const ttk::PassBPlan& x, const ttk::PassBPlan& y) {
+    return x.vec == y.vec && x.ntn == y.ntn && x.waves == y.waves && x.chunks == y.chunks;
+  };
+  if (!same1(a->p1, b->p1) || !sameb(a->p1b, b->p1b) || !sameb(a->p2b, b->p2b)) return false;
   const UpdatePlan &pa = a->plan[0], &pb = b->plan[0];
   if (pa.ops.size() != pb.ops.size() || pa.steps.size() != pb.steps.size()) return false;
   for (size_t i = 0; i < pa.steps.size(); ++i)
@@ -599,7 +625,7 @@ tt_status tt_batch_push(tt_batch* b, const void* const* slices, tt_dtype dtype) 
       tt_stream* s = b->members[g.idx[i]];
       lists[i] = s->plan[s->cur].dev;
       p1[i] = ttk::PassPtrs{slices[g.idx[i]], s->B32, s->Z, s->ws, s->flag};
-      p2[i] = ttk::PassPtrs{slices[g.idx[i]], s->A32, s->Y[0], nullptr, s->flag};
+      p2[i] = ttk::PassPtrs{slices[g.idx[i]], s->A32, s->Y[0], s->ws2, s->flag};
     }
     TT_HIP(hipMemcpyAsync(g.lists_dev, h, g.bytes, hipMemcpyHostToDevice, b->stream));
     TT_HIP(hipEventRecord(g.done[q], b->stream));
@@ -678,8 +704,8 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
         return fail(TT_ERR_RANK, "infeasible TT-ranks: need r_k <= r_{k-1} I_k and r_{k-1} <= I_k r_k");
   }
   if (cfg->compute != TT_F32 && cfg->compute != TT_BF16) return fail(TT_ERR_INVALID_ARG, "compute must be F32/BF16");
-  if (cfg->compute == TT_BF16) return fail(TT_ERR_UNSUPPORTED, "BF16 contractions are not built in this version");
-  if (cfg->flags & ~(TT_FLAG_SYNC_PUSH | TT_FLAG_PROFILE_OPS)) return fail(TT_ERR_UNSUPPORTED, "unsupported flags");
+  if (cfg->flags & ~(TT_FLAG_SYNC_PUSH | TT_FLAG_PROFILE_OPS | TT_FLAG_AUTOTUNE))
+    return fail(TT_ERR_UNSUPPORTED, "unsupported flags");
   if (cfg->split_point < 0 || cfg->split_point > m) return fail(TT_ERR_INVALID_ARG, "split_point out of range");
 
   tt_stream* s = new (std::nothrow) tt_stream();
@@ -745,7 +771,16 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
 
   int cus = 256;
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
-  s->p1 = ttk::pass1_plan(s->Pk[ks], s->Jk[ks], (int)r[ks], cus);
+  {
+    ttk::PassPlans plans = ttk::default_pass_plans(s->Pk[ks], s->Jk[ks], (int)r[ks], cus);
+    if ((cfg->flags & TT_FLAG_AUTOTUNE) &&
+        ttk::tuned_pass_plans(s->Pk[ks], s->Jk[ks], (int)r[ks], s->compute, cus, s->stream, &plans) != hipSuccess)
+      return bail(TT_ERR_DEVICE, "tuning the slice passes failed");
+    s->p1 = plans.p1;
+    s->p1b = plans.p1b;
+    s->p2b = plans.p2b;
+  }
+  const bool bf16 = s->compute == TT_BF16;
 
   bool ok = true;
   auto D = [&](size_t n) -> double* {
@@ -775,7 +810,9 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
   s->Y[0] = D(ymax);
   s->Y[1] = D(ymax);
   s->qrwork = D(qrmax);
-  s->ws = F(s->p1.ws_floats);
+  s->ws = bf16 ? static_cast<float*>(dev_alloc(s, s->p1b.ws_bytes)) : F(s->p1.ws_floats);
+  if (bf16) s->ws2 = static_cast<float*>(dev_alloc(s, s->p2b.ws_bytes));
+  if (bf16 && (!s->ws || !s->ws2)) ok = false;
   s->flag = static_cast<int*>(dev_alloc(s, sizeof(int) * 2));
   s->rejected = s->flag + 1;
   s->tdev = static_cast<int64_t*>(dev_alloc(s, sizeof(int64_t)));
@@ -827,6 +864,7 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
     TT_HIP_BAIL(hipMemsetAsync(s->trace, 0, sizeof(int64_t) * 2 * s->trace_len, s->stream));
     (void)hipDeviceGetAttribute(&s->wall_khz, hipDeviceAttributeWallClockRate, s->device);
     if (s->wall_khz <= 0) s->wall_khz = 100000;
+    for (hipEvent_t& e : s->evpass) TT_HIP_BAIL(hipEventCreate(&e));
   }
   TT_HIP_BAIL(hipStreamSynchronize(s->stream));
 #undef TT_HIP_BAIL
@@ -1010,6 +1048,16 @@ tt_status tt_stream_op_profile(tt_stream* s, int64_t cap, int32_t* kinds, int64_
     dims[3 * q + 2] = o.type == ttk::kOpQr ? o.rho : o.k;
     us[q] = (double)(stamps[2 * i + 1] - stamps[2 * i]) * 1000.0 / (double)s->wall_khz;
   }
+  return TT_OK;
+}
+
+tt_status tt_stream_pass_profile(tt_stream* s, float* pass1_ms, float* pass2_ms) {
+  if (!valid(s) || !pass1_ms || !pass2_ms) return fail(TT_ERR_INVALID_ARG, "null argument");
+  if (!s->evpass[0]) return fail(TT_ERR_STATE, "stream was not created with TT_FLAG_PROFILE_OPS");
+  if (s->traced_plan < 0) return fail(TT_ERR_STATE, "no push yet");
+  TT_HIP(hipEventSynchronize(s->evpass[3]));
+  TT_HIP(hipEventElapsedTime(pass1_ms, s->evpass[0], s->evpass[1]));
+  TT_HIP(hipEventElapsedTime(pass2_ms, s->evpass[2], s->evpass[3]));
   return TT_OK;
 }
 

@@ -1,0 +1,64 @@
+"""The launch-shape tuner of the slice passes (TT_FLAG_AUTOTUNE): tuned
+streams follow the FP64 oracle as untuned ones do, streams of one shape share
+the tuned plan (bitwise equal alone and batched), and a tuned and an untuned
+stream of one shape run different plans, so a batch keeps them apart."""
+
+import numpy as np
+import pytest
+
+from oracle import ttals
+from tests.gpu_util import rel, say, to_device_slice, torch_cuda
+from ttgen import exact_tt_stream
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_tuned_stream_matches_oracle(compute):
+    torch = torch_cuda()
+    from paper_2606_31061_amd import TTStream
+    st = exact_tt_stream((48, 40, 3), (8, 8, 3), (8, 8, 3), 8, 1201, 2201, sigma=1e-2)
+    init = st.init()
+    xs = list(st.frames(1, st.T))
+    say(f"tuned stream (48,40,3) {compute}")
+    s = TTStream(st.modes, st.ranks, init=init, compute=compute, autotune=True)
+    res = ttals.run_stream(xs, init[0], init[1], keep_M=True)
+    dt = torch.bfloat16 if compute == "bf16" else torch.float32
+    for X, info in zip(xs, res.infos):
+        s.push(to_device_slice(torch, X, dt))
+        M = s.reconstruct()
+        tol = 1e-5 if compute == "f32" else 2e-2
+        assert rel(M, info.M, np.linalg.norm(X)) <= tol
+    s.close()
+
+
+def test_tuned_streams_batch_bitwise_and_groups():
+    torch = torch_cuda()
+    from paper_2606_31061_amd import TTBatch, TTStream
+    T = 3
+    sts = [exact_tt_stream((48, 40, 3), (8, 8, 3), (8, 8, 3), T, 1300 + q, 1400 + q, sigma=1e-2) for q in range(3)]
+    say("tuned batch of 3 plus an untuned member")
+    solo = [TTStream(st.modes, st.ranks, init=st.init(), autotune=True) for st in sts]
+    members = [TTStream(st.modes, st.ranks, init=st.init(), autotune=True) for st in sts]
+    untuned = TTStream(sts[0].modes, sts[0].ranks, init=sts[0].init())
+    batch = TTBatch(members + [untuned])
+    info = batch.info()
+    assert info["streams"] == 4
+    dev = [[to_device_slice(torch, X) for X in st.frames(1, T)] for st in sts]
+    for t in range(T):
+        for s, xs in zip(solo, dev):
+            s.push(xs[t])
+        batch.push([xs[t] for xs in dev] + [dev[0][t]])
+    assert batch.synchronize() == [0, 0, 0, 0]
+    for a, b in zip(solo, members):
+        ca, ga, ta = a.get_state()
+        cb, gb, tb = b.get_state()
+        assert ta == tb == T
+        assert all(np.array_equal(x, y) for x, y in zip(ca, cb)) and np.array_equal(ga, gb)
+    # the untuned member still follows the tuned solo run to FP32 accuracy
+    cu, gu, _ = untuned.get_state()
+    c0, g0, _ = solo[0].get_state()
+    M_u = ttals.reconstruct(cu, gu)
+    M_0 = ttals.reconstruct(c0, g0)
+    assert np.linalg.norm(M_u - M_0) <= 1e-5 * np.linalg.norm(M_0)
+    batch.close()
