@@ -943,19 +943,19 @@ __device__ __forceinline__ void exec_op(const ChainOp& op) {
   }
 }
 
-// Workgroup b runs ops lists[b][first .. first + count): one workgroup per
-// stream of a batch (one stream alone: a batch of one).
-// The lists are read-only while the kernel runs: reading them through the
-// constant address space lets every operation descriptor arrive in scalar
-// registers (through a generic pointer they would be fetched per lane and kept
-// in vector registers, which spill).
+// Workgroup b runs the operations of segs[b]: one workgroup per stream of a
+// batch (one stream alone: a batch of one).  The segments and operation lists
+// are read-only while the kernel runs: reading them through the constant
+// address space lets every operation descriptor arrive in scalar registers
+// (through a generic pointer they would be fetched per lane and kept in vector
+// registers, which spill).
 typedef const TT_CONSTANT_AS ChainOp ConstChainOp;
-typedef const TT_CONSTANT_AS uint64_t ConstWord;
+typedef const TT_CONSTANT_AS ChainSeg ConstChainSeg;
 
-__global__ void __launch_bounds__(kCT) k_chain(const ChainOp* const* __restrict__ lists, int first, int count,
-                                                int64_t* trace) {
-  const uint64_t base = ((ConstWord*)(const void*)lists)[blockIdx.x];
-  ConstChainOp* ops = (ConstChainOp*)base + first;
+__global__ void __launch_bounds__(kCT) k_chain(const ChainSeg* __restrict__ segs, int64_t* trace) {
+  const ChainSeg sg = ((ConstChainSeg*)(const void*)segs)[blockIdx.x];
+  ConstChainOp* ops = (ConstChainOp*)(uint64_t)sg.ops;
+  const int count = sg.count;
   for (int i = 0; i < count; ++i) {
     const ChainOp op = ops[i];
     if (trace && threadIdx.x == 0) trace[2 * i] = (int64_t)wall_clock64();
@@ -988,12 +988,11 @@ bool chain_op_supported(const ChainOp& op) {
   return true;
 }
 
-hipError_t chain_run(hipStream_t st, const ChainOp* const* lists_dev, int nlists, int first, int count,
-                     int64_t* trace) {
-  if (count <= 0) return hipSuccess;
+hipError_t chain_run(hipStream_t st, const ChainSeg* segs_dev, int nsegs, int64_t* trace) {
+  if (nsegs == 0) return hipSuccess;
   if (!g_chain_ready) return hipErrorNotInitialized;
-  if (nlists < 1 || (trace && nlists != 1)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_chain, dim3(nlists), dim3(kCT), kChainLds, st, lists_dev, first, count, trace);
+  if (nsegs < 0 || (trace && nsegs != 1)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_chain, dim3(nsegs), dim3(kCT), kChainLds, st, segs_dev, trace);
   return hipGetLastError();
 }
 

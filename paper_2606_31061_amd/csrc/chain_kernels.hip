@@ -36,16 +36,27 @@ __global__ void __launch_bounds__(256) k_gemm64(int64_t M, int64_t N, int64_t K,
 typedef const TT_CONSTANT_AS ChainOp ConstChainOp;
 typedef const TT_CONSTANT_AS uint64_t ConstWord;
 
-// The same product for the GEMM op lists[blockIdx.y][idx] of a batch.  The
-// lists are read-only during the launch; reading them through the constant
-// address space keeps the descriptor in scalar registers.
-__global__ void __launch_bounds__(256) k_gemm64_ops(const ChainOp* const* __restrict__ lists, int idx, int ks) {
-  const uint64_t base = ((ConstWord*)(const void*)lists)[blockIdx.y];
-  const ChainOp op = ((ConstChainOp*)base)[idx];
+// Lanes sharing one output element: the depth split of an M x N x K product
+// (a function of K only, the same on host and device).
+__host__ __device__ inline int depth_split(int64_t K) {
+  int ks = 1;
+  while (ks < 64 && (int64_t)ks * 8 < K) ks <<= 1;
+  return ks;
+}
+
+// The same product for the GEMM *ops[blockIdx.y] of a batch; blocks past the
+// product's own grid return.  The op pointers and ops are read-only during
+// the launch; reading them through the constant address space keeps the
+// descriptor in scalar registers.
+__global__ void __launch_bounds__(256) k_gemm64_ops(const ChainOp* const* __restrict__ ops) {
+  const uint64_t addr = ((ConstWord*)(const void*)ops)[blockIdx.y];
+  const ChainOp op = *(ConstChainOp*)addr;
   const int64_t M = op.m, N = op.n, K = op.k;
+  const int ks = depth_split(K);
   const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int q = (int)(gt % ks);
   const int64_t out = gt / ks;
+  if (blockIdx.x * (int64_t)blockDim.x >= M * N * ks) return;
   const bool valid = out < M * N;
   const int64_t i = valid ? out % M : 0, j = valid ? out / M : 0;
   double acc = 0.0;
@@ -82,8 +93,7 @@ hipError_t gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K,
                   const double* B, int64_t brs, int64_t bcs,
                   double* C, int64_t crs, int64_t ccs, float* C32) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  int ks = 1;
-  while (ks < 64 && (int64_t)ks * 8 < K) ks <<= 1;
+  const int ks = depth_split(K);
   const int64_t threads = M * N * ks;
   const int64_t blocks = (threads + 255) / 256;
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
@@ -92,16 +102,15 @@ hipError_t gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K,
   return hipGetLastError();
 }
 
-hipError_t gemm64_ops(hipStream_t st, const ChainOp* const* lists_dev, int nlists, int idx, int64_t M, int64_t N,
-                      int64_t K) {
-  if (M <= 0 || N <= 0) return hipSuccess;
-  if (nlists < 1 || nlists > 65535) return hipErrorInvalidValue;
-  int ks = 1;
-  while (ks < 64 && (int64_t)ks * 8 < K) ks <<= 1;
-  const int64_t threads = M * N * ks;
-  const int64_t blocks = (threads + 255) / 256;
-  if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gemm64_ops, dim3((unsigned)blocks, nlists), dim3(256), 0, st, lists_dev, idx, ks);
+int64_t gemm64_blocks(int64_t M, int64_t N, int64_t K) {
+  if (M <= 0 || N <= 0) return 0;
+  return (M * N * depth_split(K) + 255) / 256;
+}
+
+hipError_t gemm64_ops(hipStream_t st, const ChainOp* const* ops_dev, int nops, int64_t gx) {
+  if (nops == 0 || gx == 0) return hipSuccess;
+  if (nops < 0 || nops > 65535 || gx > 0x7fffffff) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gemm64_ops, dim3((unsigned)gx, nops), dim3(256), 0, st, ops_dev);
   return hipGetLastError();
 }
 

@@ -179,14 +179,19 @@ template <typename T, int VEC, int NW, int NTN>
 __global__ void __launch_bounds__(NW * 64) k_pass1b(const T* __restrict__ X, int64_t P, int64_t J, int r,
                                                     const float* __restrict__ B, float* __restrict__ ws,
                                                     double* __restrict__ Z, int* __restrict__ flag, int tiles,
-                                                    int chunks, const PassPtrs* __restrict__ batch) {
+                                                    int chunks, const PassDesc* __restrict__ batch) {
   if (batch) {
-    const PassPtrs& pp = batch[blockIdx.y];
+    const PassDesc& pp = batch[blockIdx.y];
     X = static_cast<const T*>(pp.x);
     B = pp.w;
     ws = pp.ws;
     Z = pp.out;
     flag = pp.flag;
+    P = pp.P;
+    J = pp.J;
+    r = pp.r;
+    tiles = pp.tiles;
+    chunks = pp.chunks;
   }
   constexpr int TILEF = NTN * VEC * 1024;
   constexpr int SLOTS = slots_for(NW, TILEF);
@@ -296,14 +301,19 @@ template <typename T, int NW, int NTN, bool VX>
 __global__ void __launch_bounds__(NW * 64) k_pass2b(const T* __restrict__ X, int64_t P, int64_t J, int r,
                                                     const float* __restrict__ A, float* __restrict__ ws,
                                                     double* __restrict__ Y, int* __restrict__ flag, int ctiles,
-                                                    int rchunks, const PassPtrs* __restrict__ batch) {
+                                                    int rchunks, const PassDesc* __restrict__ batch) {
   if (batch) {
-    const PassPtrs& pp = batch[blockIdx.y];
+    const PassDesc& pp = batch[blockIdx.y];
     X = static_cast<const T*>(pp.x);
     A = pp.w;
     ws = pp.ws;
     Y = pp.out;
     flag = pp.flag;
+    P = pp.P;
+    J = pp.J;
+    r = pp.r;
+    ctiles = pp.tiles;
+    rchunks = pp.chunks;
   }
   constexpr int TILEF = NTN * 1024;
   constexpr int SLOTS = slots_for(NW, TILEF);
@@ -312,6 +322,7 @@ __global__ void __launch_bounds__(NW * 64) k_pass2b(const T* __restrict__ X, int
   // no XCD grouping: every slice element is read once, and the left
   // interface is small enough to stay in every XCD's L2
   const int ct = (int)blockIdx.x / rchunks, rc = (int)blockIdx.x % rchunks;
+  if (ct >= ctiles) return;  // past this member's columns
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int li = lane & 31, h = lane >> 5;
   int64_t jc = (int64_t)ct * 32 + li;
@@ -432,13 +443,19 @@ __global__ void __launch_bounds__(NW * 64) k_pass2b(const T* __restrict__ X, int
 template <int PASS, int VEC, int NTN>
 __global__ void __launch_bounds__(256) k_reduceb(const float* __restrict__ ws, int tiles, int chunks, int64_t P,
                                                  int64_t J, int r, double* __restrict__ out,
-                                                 int* __restrict__ flag, const PassPtrs* __restrict__ batch) {
+                                                 int* __restrict__ flag, const PassDesc* __restrict__ batch) {
   if (batch) {
-    const PassPtrs& pp = batch[blockIdx.y];
+    const PassDesc& pp = batch[blockIdx.y];
     ws = pp.ws;
     out = pp.out;
     flag = pp.flag;
+    tiles = pp.tiles;
+    chunks = pp.chunks;
+    P = pp.P;
+    J = pp.J;
+    r = pp.r;
   }
+  if (chunks == 1) return;  // finished by the pass kernel
   constexpr int TILEF = NTN * VEC * 1024;
   const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t tile = g / TILEF;
@@ -473,53 +490,60 @@ __global__ void __launch_bounds__(256) k_reduceb(const float* __restrict__ ws, i
 
 template <int PASS, int VEC, int NTN>
 hipError_t launch_reduce(hipStream_t st, const PassBPlan& pl, int64_t P, int64_t J, int r, double* out,
-                         const void* ws, int* flag, const PassPtrs* bt, int nb) {
-  if (pl.chunks == 1) return hipSuccess;
+                         const void* ws, int* flag, const PassLaunch* bl) {
+  if (!bl && pl.chunks == 1) return hipSuccess;
+  if (bl && bl->grx == 0) return hipSuccess;  // no member splits its reduction
   constexpr int TILEF = NTN * VEC * 1024;
   const int64_t threads = (int64_t)pl.tiles * TILEF;
-  hipLaunchKernelGGL((k_reduceb<PASS, VEC, NTN>), dim3((unsigned)((threads + 255) / 256), nb), dim3(256), 0, st,
-                     static_cast<const float*>(ws), pl.tiles, pl.chunks, P, J, r, out, flag, bt);
+  const unsigned grx = bl ? bl->grx : (unsigned)((threads + 255) / 256);
+  hipLaunchKernelGGL((k_reduceb<PASS, VEC, NTN>), dim3(grx, bl ? (unsigned)bl->n : 1u), dim3(256), 0, st,
+                     static_cast<const float*>(ws), pl.tiles, pl.chunks, P, J, r, out, flag, bl ? bl->desc : nullptr);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------ launch
 template <typename T, int VEC, int NW, int NTN>
 hipError_t launch_p1b(hipStream_t st, const T* X, const PassBPlan& pl, int64_t P, int64_t J, int r, const float* B,
-                      double* Z, void* ws, int* flag, const PassPtrs* bt, int nb) {
-  const int groups = (pl.chunks + 7) / 8;
-  hipLaunchKernelGGL((k_pass1b<T, VEC, NW, NTN>), dim3((unsigned)(pl.tiles * groups * 8), nb), dim3(NW * 64), 0, st,
-                     X, P, J, r, B, static_cast<float*>(ws), Z, flag, pl.tiles, pl.chunks, bt);
+                      double* Z, void* ws, int* flag, const PassLaunch* bl) {
+  unsigned gx, grx;
+  pass1b_grids(pl, &gx, &grx);
+  if (bl) gx = bl->gx;
+  hipLaunchKernelGGL((k_pass1b<T, VEC, NW, NTN>), dim3(gx, bl ? (unsigned)bl->n : 1u), dim3(NW * 64), 0, st, X, P, J,
+                     r, B, static_cast<float*>(ws), Z, flag, pl.tiles, pl.chunks, bl ? bl->desc : nullptr);
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  return launch_reduce<1, VEC, NTN>(st, pl, P, J, r, Z, ws, flag, bt, nb);
+  return launch_reduce<1, VEC, NTN>(st, pl, P, J, r, Z, ws, flag, bl);
 }
 
 template <typename T, int NW>
 hipError_t p1b_vec(hipStream_t st, const T* X, const PassBPlan& pl, int64_t P, int64_t J, int r, const float* B,
-                   double* Z, void* ws, int* flag, const PassPtrs* bt, int nb) {
+                   double* Z, void* ws, int* flag, const PassLaunch* bt) {
   if (pl.ntn == 1) {
-    if (pl.vec == 8) return launch_p1b<T, 8, NW, 1>(st, X, pl, P, J, r, B, Z, ws, flag, bt, nb);
-    if (pl.vec == 4) return launch_p1b<T, 4, NW, 1>(st, X, pl, P, J, r, B, Z, ws, flag, bt, nb);
-    if (pl.vec == 2) return launch_p1b<T, 2, NW, 1>(st, X, pl, P, J, r, B, Z, ws, flag, bt, nb);
-    return launch_p1b<T, 1, NW, 1>(st, X, pl, P, J, r, B, Z, ws, flag, bt, nb);
+    if (pl.vec == 8) return launch_p1b<T, 8, NW, 1>(st, X, pl, P, J, r, B, Z, ws, flag, bt);
+    if (pl.vec == 4) return launch_p1b<T, 4, NW, 1>(st, X, pl, P, J, r, B, Z, ws, flag, bt);
+    if (pl.vec == 2) return launch_p1b<T, 2, NW, 1>(st, X, pl, P, J, r, B, Z, ws, flag, bt);
+    return launch_p1b<T, 1, NW, 1>(st, X, pl, P, J, r, B, Z, ws, flag, bt);
   }
-  if (pl.vec == 4) return launch_p1b<T, 4, NW, 2>(st, X, pl, P, J, r, B, Z, ws, flag, bt, nb);
-  if (pl.vec == 2) return launch_p1b<T, 2, NW, 2>(st, X, pl, P, J, r, B, Z, ws, flag, bt, nb);
-  return launch_p1b<T, 1, NW, 2>(st, X, pl, P, J, r, B, Z, ws, flag, bt, nb);
+  if (pl.vec == 4) return launch_p1b<T, 4, NW, 2>(st, X, pl, P, J, r, B, Z, ws, flag, bt);
+  if (pl.vec == 2) return launch_p1b<T, 2, NW, 2>(st, X, pl, P, J, r, B, Z, ws, flag, bt);
+  return launch_p1b<T, 1, NW, 2>(st, X, pl, P, J, r, B, Z, ws, flag, bt);
 }
 
 template <typename T>
 hipError_t p1b_t(hipStream_t st, const T* X, const PassBPlan& pl, int64_t P, int64_t J, int r, const float* B,
-                 double* Z, void* ws, int* flag, const PassPtrs* bt, int nb) {
-  return p1b_vec<T, kWavesB>(st, X, pl, P, J, r, B, Z, ws, flag, bt, nb);
+                 double* Z, void* ws, int* flag, const PassLaunch* bt) {
+  return p1b_vec<T, kWavesB>(st, X, pl, P, J, r, B, Z, ws, flag, bt);
 }
 
 template <typename T, int NW>
 hipError_t p2b_nw(hipStream_t st, const T* X, const PassBPlan& pl, int64_t P, int64_t J, int r, const float* A,
-                  double* Y, void* ws, int* flag, const PassPtrs* bt, int nb) {
-  const dim3 grid((unsigned)(pl.tiles * pl.chunks), nb), block(NW * 64);
+                  double* Y, void* ws, int* flag, const PassLaunch* bl) {
+  unsigned gx0, grx0;
+  pass2b_grids(pl, &gx0, &grx0);
+  const dim3 grid(bl ? bl->gx : gx0, bl ? (unsigned)bl->n : 1u), block(NW * 64);
+  const PassDesc* bt = bl ? bl->desc : nullptr;
   float* w = static_cast<float*>(ws);
-  const bool vx = (P % 8) == 0;
+  const bool vx = pass2b_vx(P);
   if (pl.ntn == 1) {
     if (vx)
       hipLaunchKernelGGL((k_pass2b<T, NW, 1, true>), grid, block, 0, st, X, P, J, r, A, w, Y, flag, pl.tiles,
@@ -539,15 +563,15 @@ hipError_t p2b_nw(hipStream_t st, const T* X, const PassBPlan& pl, int64_t P, in
   }
   const hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (pl.ntn == 1) return launch_reduce<2, 1, 1>(st, pl, P, J, r, Y, ws, flag, bt, nb);
-  return launch_reduce<2, 1, 2>(st, pl, P, J, r, Y, ws, flag, bt, nb);
+  if (pl.ntn == 1) return launch_reduce<2, 1, 1>(st, pl, P, J, r, Y, ws, flag, bl);
+  return launch_reduce<2, 1, 2>(st, pl, P, J, r, Y, ws, flag, bl);
 }
 
 template <typename T>
 hipError_t p2b_t(hipStream_t st, const T* X, const PassBPlan& pl, int64_t P, int64_t J, int r, const float* A,
-                 double* Y, void* ws, int* flag, const PassPtrs* bt, int nb) {
-  if (pl.waves == 8) return p2b_nw<T, 8>(st, X, pl, P, J, r, A, Y, ws, flag, bt, nb);
-  return p2b_nw<T, kWavesB>(st, X, pl, P, J, r, A, Y, ws, flag, bt, nb);
+                 double* Y, void* ws, int* flag, const PassLaunch* bl) {
+  if (pl.waves == 8) return p2b_nw<T, 8>(st, X, pl, P, J, r, A, Y, ws, flag, bl);
+  return p2b_nw<T, kWavesB>(st, X, pl, P, J, r, A, Y, ws, flag, bl);
 }
 
 int chunks_for(int64_t units, int tiles, int cus, int waves, int min_per_wave) {
@@ -601,33 +625,43 @@ PassBPlan pass2b_plan(int64_t P, int64_t J, int r, int cus) {
   return pass2b_finish(pl, P, J);
 }
 
+void pass1b_grids(const PassBPlan& pl, unsigned* gx, unsigned* grx) {
+  *gx = (unsigned)(pl.tiles * ((pl.chunks + 7) / 8) * 8);
+  *grx = pl.chunks == 1 ? 0u : (unsigned)(((int64_t)pl.tiles * pl.ntn * pl.vec * 1024 + 255) / 256);
+}
+
+void pass2b_grids(const PassBPlan& pl, unsigned* gx, unsigned* grx) {
+  *gx = (unsigned)(pl.tiles * pl.chunks);
+  *grx = pl.chunks == 1 ? 0u : (unsigned)(((int64_t)pl.tiles * pl.ntn * 1024 + 255) / 256);
+}
+
+bool pass2b_vx(int64_t P) { return P % 8 == 0; }
+
 hipError_t pass1_bf16(hipStream_t st, const void* X, tt_dtype xdt, const PassBPlan& pl, int64_t P, int64_t J, int r,
-                      const float* B, double* Z, void* ws, int* flag, const PassPtrs* batch, int nbatch) {
-  if (r < 1 || r > 32 * pl.ntn || pl.ntn > 2 || pl.waves != kWavesB || nbatch < 1 || nbatch > 65535)
+                      const float* B, double* Z, void* ws, int* flag, const PassLaunch* bl) {
+  if (r < 1 || r > 32 * pl.ntn || pl.ntn > 2 || pl.waves != kWavesB || (bl && (bl->n < 1 || bl->n > 65535)))
     return hipErrorInvalidValue;
   if (pl.chunks < 1 || pl.tiles != (int)((P + 32 * pl.vec - 1) / (32 * pl.vec))) return hipErrorInvalidValue;
   if (pl.vec != 1 && P % pl.vec != 0) return hipErrorInvalidValue;
   if (pl.vec == 8 && pl.ntn != 1) return hipErrorInvalidValue;
   switch (xdt) {
-    case TT_F32: return p1b_t(st, static_cast<const float*>(X), pl, P, J, r, B, Z, ws, flag, batch, nbatch);
-    case TT_F64: return p1b_t(st, static_cast<const double*>(X), pl, P, J, r, B, Z, ws, flag, batch, nbatch);
-    case TT_BF16:
-      return p1b_t(st, static_cast<const __hip_bfloat16*>(X), pl, P, J, r, B, Z, ws, flag, batch, nbatch);
+    case TT_F32: return p1b_t(st, static_cast<const float*>(X), pl, P, J, r, B, Z, ws, flag, bl);
+    case TT_F64: return p1b_t(st, static_cast<const double*>(X), pl, P, J, r, B, Z, ws, flag, bl);
+    case TT_BF16: return p1b_t(st, static_cast<const __hip_bfloat16*>(X), pl, P, J, r, B, Z, ws, flag, bl);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t pass2_bf16(hipStream_t st, const void* X, tt_dtype xdt, const PassBPlan& pl, int64_t P, int64_t J, int r,
-                      const float* A, double* Y, void* ws, int* flag, const PassPtrs* batch, int nbatch) {
+                      const float* A, double* Y, void* ws, int* flag, const PassLaunch* bl) {
   if (r < 1 || r > 32 * pl.ntn || pl.ntn > 2 || (pl.waves != kWavesB && !(pl.waves == 8 && pl.ntn == 1)) ||
-      nbatch < 1 || nbatch > 65535)
+      (bl && (bl->n < 1 || bl->n > 65535)))
     return hipErrorInvalidValue;
   if (pl.chunks < 1 || pl.tiles != (int)((J + 31) / 32)) return hipErrorInvalidValue;
   switch (xdt) {
-    case TT_F32: return p2b_t(st, static_cast<const float*>(X), pl, P, J, r, A, Y, ws, flag, batch, nbatch);
-    case TT_F64: return p2b_t(st, static_cast<const double*>(X), pl, P, J, r, A, Y, ws, flag, batch, nbatch);
-    case TT_BF16:
-      return p2b_t(st, static_cast<const __hip_bfloat16*>(X), pl, P, J, r, A, Y, ws, flag, batch, nbatch);
+    case TT_F32: return p2b_t(st, static_cast<const float*>(X), pl, P, J, r, A, Y, ws, flag, bl);
+    case TT_F64: return p2b_t(st, static_cast<const double*>(X), pl, P, J, r, A, Y, ws, flag, bl);
+    case TT_BF16: return p2b_t(st, static_cast<const __hip_bfloat16*>(X), pl, P, J, r, A, Y, ws, flag, bl);
   }
   return hipErrorInvalidValue;
 }

@@ -131,12 +131,17 @@ __device__ __forceinline__ int mfma_row(int lane, int v) { return 8 * (v >> 2) +
 template <typename T, int VEC, int NW, int NTN>
 __global__ void __launch_bounds__(NW * 64) k_pass1(const T* __restrict__ X, int64_t P, int64_t J, int r,
                                                    const float* __restrict__ B, float* __restrict__ part,
-                                                   int tiles, int chunks, const PassPtrs* __restrict__ batch) {
-  if (batch) {  // member blockIdx.y of a batch of same-shape streams
-    const PassPtrs& pp = batch[blockIdx.y];
+                                                   int tiles, int chunks, const PassDesc* __restrict__ batch) {
+  if (batch) {  // member blockIdx.y of a batch
+    const PassDesc& pp = batch[blockIdx.y];
     X = static_cast<const T*>(pp.x);
     B = pp.w;
     part = pp.ws;
+    P = pp.P;
+    J = pp.J;
+    r = pp.r;
+    tiles = pp.tiles;
+    chunks = pp.chunks;
   }
   constexpr int TILEF = NTN * VEC * 1024;
   // LDS slots for the wave reduction: waves add into slot w % SLOTS in
@@ -260,12 +265,15 @@ __global__ void __launch_bounds__(NW * 64) k_pass1(const T* __restrict__ X, int6
 template <int VEC, int NTN>
 __global__ void __launch_bounds__(256) k_pass1_reduce(const float* __restrict__ part, int chunks, int64_t P, int r,
                                                       double* __restrict__ Z, int* __restrict__ flag,
-                                                      const PassPtrs* __restrict__ batch) {
+                                                      const PassDesc* __restrict__ batch) {
   if (batch) {
-    const PassPtrs& pp = batch[blockIdx.y];
+    const PassDesc& pp = batch[blockIdx.y];
     part = pp.ws;
     Z = pp.out;
     flag = pp.flag;
+    chunks = pp.chunks;
+    P = pp.P;
+    r = pp.r;
   }
   constexpr int TILEF = NTN * VEC * 1024;
   const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -309,14 +317,20 @@ template <typename T, int VEC, int NTN>
 __global__ void __launch_bounds__(kPass2Waves * 64) k_pass2(const T* __restrict__ X, int64_t P, int64_t J, int r,
                                                             const float* __restrict__ A, double* __restrict__ Y,
                                                             int* __restrict__ flag, int slab, int nchunk,
-                                                            const PassPtrs* __restrict__ batch) {
+                                                            const PassDesc* __restrict__ batch) {
   if (batch) {
-    const PassPtrs& pp = batch[blockIdx.y];
+    const PassDesc& pp = batch[blockIdx.y];
     X = static_cast<const T*>(pp.x);
     A = pp.w;
     Y = pp.out;
     flag = pp.flag;
+    P = pp.P;
+    J = pp.J;
+    r = pp.r;
+    slab = (int)(((P + kPass2Waves - 1) / kPass2Waves + 7) & ~7LL);
+    nchunk = (slab + kPass2SlabMax - 1) / kPass2SlabMax;
   }
+  if ((int64_t)blockIdx.x * 32 >= J) return;  // past this member's columns
   extern __shared__ float lds[];
   constexpr int PER_COL = kPass2SlabMax / VEC;           // vector loads per column and chunk
   constexpr int NLD = (32 * PER_COL + 63) / 64;          // vector loads per lane and chunk
@@ -460,46 +474,50 @@ __global__ void __launch_bounds__(kPass2Waves * 64) k_pass2(const T* __restrict_
 // ------------------------------------------------------------------ launch
 template <typename T, int VEC, int NW, int NTN>
 hipError_t launch_p1(hipStream_t st, const T* X, int64_t P, int64_t J, int r, const float* B, double* Z, float* ws,
-                     int* flag, int chunks, const PassPtrs* batch, int nb) {
+                     int* flag, int chunks, const PassLaunch* bl) {
   const int tiles = (int)((P + 32 * VEC - 1) / (32 * VEC));
   const int groups = (chunks + 7) / 8;
-  hipLaunchKernelGGL((k_pass1<T, VEC, NW, NTN>), dim3(tiles * groups * 8, nb), dim3(NW * 64), 0, st, X, P, J, r, B,
-                     ws, tiles, chunks, batch);
   constexpr int TILEF = NTN * VEC * 1024;
   const int64_t threads = (int64_t)tiles * TILEF;
-  hipLaunchKernelGGL((k_pass1_reduce<VEC, NTN>), dim3((unsigned)((threads + 255) / 256), nb), dim3(256), 0, st, ws,
-                     chunks, P, r, Z, flag, batch);
+  const unsigned gx = bl ? bl->gx : (unsigned)(tiles * groups * 8);
+  const unsigned grx = bl ? bl->grx : (unsigned)((threads + 255) / 256);
+  const unsigned nb = bl ? (unsigned)bl->n : 1u;
+  const PassDesc* d = bl ? bl->desc : nullptr;
+  hipLaunchKernelGGL((k_pass1<T, VEC, NW, NTN>), dim3(gx, nb), dim3(NW * 64), 0, st, X, P, J, r, B, ws, tiles, chunks,
+                     d);
+  hipLaunchKernelGGL((k_pass1_reduce<VEC, NTN>), dim3(grx, nb), dim3(256), 0, st, ws, chunks, P, r, Z, flag, d);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t pass1_t(hipStream_t st, const T* X, const Pass1Plan& pl, int64_t P, int64_t J, int r, const float* B,
-                   double* Z, float* ws, int* flag, const PassPtrs* bt, int nb) {
+                   double* Z, float* ws, int* flag, const PassLaunch* bt) {
   const int c = pl.chunks;
   if (pl.ntn == 1) {
     if (pl.vec == 4) {
-      if (pl.waves == 8) return launch_p1<T, 4, 8, 1>(st, X, P, J, r, B, Z, ws, flag, c, bt, nb);
-      return launch_p1<T, 4, 4, 1>(st, X, P, J, r, B, Z, ws, flag, c, bt, nb);
+      if (pl.waves == 8) return launch_p1<T, 4, 8, 1>(st, X, P, J, r, B, Z, ws, flag, c, bt);
+      return launch_p1<T, 4, 4, 1>(st, X, P, J, r, B, Z, ws, flag, c, bt);
     }
     if (pl.vec == 2) {
-      if (pl.waves == 8) return launch_p1<T, 2, 8, 1>(st, X, P, J, r, B, Z, ws, flag, c, bt, nb);
-      return launch_p1<T, 2, 4, 1>(st, X, P, J, r, B, Z, ws, flag, c, bt, nb);
+      if (pl.waves == 8) return launch_p1<T, 2, 8, 1>(st, X, P, J, r, B, Z, ws, flag, c, bt);
+      return launch_p1<T, 2, 4, 1>(st, X, P, J, r, B, Z, ws, flag, c, bt);
     }
-    if (pl.waves == 16) return launch_p1<T, 1, 16, 1>(st, X, P, J, r, B, Z, ws, flag, c, bt, nb);
-    return launch_p1<T, 1, 8, 1>(st, X, P, J, r, B, Z, ws, flag, c, bt, nb);
+    if (pl.waves == 16) return launch_p1<T, 1, 16, 1>(st, X, P, J, r, B, Z, ws, flag, c, bt);
+    return launch_p1<T, 1, 8, 1>(st, X, P, J, r, B, Z, ws, flag, c, bt);
   }
-  if (pl.vec == 2) return launch_p1<T, 2, 4, 2>(st, X, P, J, r, B, Z, ws, flag, c, bt, nb);
-  return launch_p1<T, 1, 8, 2>(st, X, P, J, r, B, Z, ws, flag, c, bt, nb);
+  if (pl.vec == 2) return launch_p1<T, 2, 4, 2>(st, X, P, J, r, B, Z, ws, flag, c, bt);
+  return launch_p1<T, 1, 8, 2>(st, X, P, J, r, B, Z, ws, flag, c, bt);
 }
 
 template <typename T, int VEC>
 hipError_t pass2_v(hipStream_t st, const T* X, int64_t P, int64_t J, int r, const float* A, double* Y, int* flag,
-                   const PassPtrs* bt, int nb) {
+                   const PassLaunch* bl) {
   int64_t slab = (P + kPass2Waves - 1) / kPass2Waves;
   slab = (slab + 7) & ~7LL;
   const int nchunk = (int)((slab + kPass2SlabMax - 1) / kPass2SlabMax);
   const size_t lds = (size_t)kPass2Waves * 32 * kLdp * sizeof(float);
-  const dim3 grid((unsigned)((J + 31) / 32), nb);
+  const dim3 grid(bl ? bl->gx : pass2_grid(J), bl ? (unsigned)bl->n : 1u);
+  const PassDesc* bt = bl ? bl->desc : nullptr;
   const dim3 block(kPass2Waves * 64);
   if (r <= 32)
     hipLaunchKernelGGL((k_pass2<T, VEC, 1>), grid, block, lds, st, X, P, J, r, A, Y, flag, (int)slab, nchunk, bt);
@@ -510,9 +528,9 @@ hipError_t pass2_v(hipStream_t st, const T* X, int64_t P, int64_t J, int r, cons
 
 template <typename T>
 hipError_t pass2_t(hipStream_t st, const T* X, int64_t P, int64_t J, int r, const float* A, double* Y, int* flag,
-                   const PassPtrs* bt, int nb) {
-  if (P % 4 == 0) return pass2_v<T, 4>(st, X, P, J, r, A, Y, flag, bt, nb);
-  return pass2_v<T, 1>(st, X, P, J, r, A, Y, flag, bt, nb);
+                   const PassLaunch* bl) {
+  if (pass2_vec(P) == 4) return pass2_v<T, 4>(st, X, P, J, r, A, Y, flag, bl);
+  return pass2_v<T, 1>(st, X, P, J, r, A, Y, flag, bl);
 }
 
 template <typename T, int VEC, int NTN>
@@ -551,25 +569,33 @@ Pass1Plan finish_plan(Pass1Plan pl, int64_t P) {
   return pl;
 }
 
+void pass1_grids(const Pass1Plan& pl, int64_t P, unsigned* gx, unsigned* grx) {
+  const int tiles = (int)((P + 32 * pl.vec - 1) / (32 * pl.vec));
+  *gx = (unsigned)(tiles * ((pl.chunks + 7) / 8) * 8);
+  *grx = (unsigned)(((int64_t)tiles * pl.ntn * pl.vec * 1024 + 255) / 256);
+}
+
+unsigned pass2_grid(int64_t J) { return (unsigned)((J + 31) / 32); }
+int pass2_vec(int64_t P) { return P % 4 == 0 ? 4 : 1; }
+
 hipError_t pass1(hipStream_t st, const void* X, tt_dtype xdt, const Pass1Plan& pl, int64_t P, int64_t J, int r,
-                 const float* B, double* Z, float* ws, int* flag, const PassPtrs* batch, int nbatch) {
-  if (r < 1 || r > 64 || nbatch < 1 || nbatch > 65535) return hipErrorInvalidValue;
+                 const float* B, double* Z, float* ws, int* flag, const PassLaunch* bl) {
+  if (r < 1 || r > 64 || (bl && (bl->n < 1 || bl->n > 65535))) return hipErrorInvalidValue;
   switch (xdt) {
-    case TT_F32: return pass1_t(st, static_cast<const float*>(X), pl, P, J, r, B, Z, ws, flag, batch, nbatch);
-    case TT_F64: return pass1_t(st, static_cast<const double*>(X), pl, P, J, r, B, Z, ws, flag, batch, nbatch);
-    case TT_BF16:
-      return pass1_t(st, static_cast<const __hip_bfloat16*>(X), pl, P, J, r, B, Z, ws, flag, batch, nbatch);
+    case TT_F32: return pass1_t(st, static_cast<const float*>(X), pl, P, J, r, B, Z, ws, flag, bl);
+    case TT_F64: return pass1_t(st, static_cast<const double*>(X), pl, P, J, r, B, Z, ws, flag, bl);
+    case TT_BF16: return pass1_t(st, static_cast<const __hip_bfloat16*>(X), pl, P, J, r, B, Z, ws, flag, bl);
   }
   return hipErrorInvalidValue;
 }
 
 hipError_t pass2(hipStream_t st, const void* X, tt_dtype xdt, int64_t P, int64_t J, int r, const float* A, double* Y,
-                 int* flag, const PassPtrs* batch, int nbatch) {
-  if (r < 1 || r > 64 || nbatch < 1 || nbatch > 65535) return hipErrorInvalidValue;
+                 int* flag, const PassLaunch* bl) {
+  if (r < 1 || r > 64 || (bl && (bl->n < 1 || bl->n > 65535))) return hipErrorInvalidValue;
   switch (xdt) {
-    case TT_F32: return pass2_t(st, static_cast<const float*>(X), P, J, r, A, Y, flag, batch, nbatch);
-    case TT_F64: return pass2_t(st, static_cast<const double*>(X), P, J, r, A, Y, flag, batch, nbatch);
-    case TT_BF16: return pass2_t(st, static_cast<const __hip_bfloat16*>(X), P, J, r, A, Y, flag, batch, nbatch);
+    case TT_F32: return pass2_t(st, static_cast<const float*>(X), P, J, r, A, Y, flag, bl);
+    case TT_F64: return pass2_t(st, static_cast<const double*>(X), P, J, r, A, Y, flag, bl);
+    case TT_BF16: return pass2_t(st, static_cast<const __hip_bfloat16*>(X), P, J, r, A, Y, flag, bl);
   }
   return hipErrorInvalidValue;
 }

@@ -64,12 +64,16 @@ struct ChainOp {
 // Sets the kernels' LDS size; once per process before the first launch.
 hipError_t chain_setup(size_t lds_limit);
 bool chain_op_supported(const ChainOp& op);
-// Runs lists[b][first .. first + count) in order, one workgroup per list b
-// (lists_dev: device array of nlists op-list pointers).  If trace is not null
-// (nlists == 1 only), trace[2i] and trace[2i+1] receive the device wall clock
-// at the start and end of op first + i.
-hipError_t chain_run(hipStream_t st, const ChainOp* const* lists_dev, int nlists, int first, int count,
-                     int64_t* trace = nullptr);
+// A run of consecutive operations of one stream's list.
+struct ChainSeg {
+  const ChainOp* ops;
+  int32_t count;
+  int32_t pad;
+};
+// Workgroup b runs segs[b] (device array of nsegs segments; a segment may be
+// empty).  If trace is not null (nsegs == 1 only), trace[2i] and trace[2i+1]
+// receive the device wall clock at the start and end of operation i.
+hipError_t chain_run(hipStream_t st, const ChainSeg* segs_dev, int nsegs, int64_t* trace = nullptr);
 // Runs one operation passed by value.
 hipError_t chain_run_one(hipStream_t st, const ChainOp& op);
 // Rows of the slice staged per wave in pass 2 (multiple of 8).
@@ -84,10 +88,12 @@ hipError_t gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K,
                   const double* B, int64_t brs, int64_t bcs,
                   double* C, int64_t crs, int64_t ccs, float* C32);
 
-// The GEMM lists[b][idx] (kOpGemm, m x n x k equal across b) over the whole
-// GPU for every list b.
-hipError_t gemm64_ops(hipStream_t st, const ChainOp* const* lists_dev, int nlists, int idx, int64_t M, int64_t N,
-                      int64_t K);
+// The GEMMs *ops[b] (kOpGemm; device array of nops op pointers, shapes may
+// differ) over the whole GPU, grid (gx, nops); gx must cover the largest
+// (gemm64_blocks).  Each product's split of the depth depends on its own shape
+// only, so a product computes the same bits in any batch.
+int64_t gemm64_blocks(int64_t M, int64_t N, int64_t K);
+hipError_t gemm64_ops(hipStream_t st, const ChainOp* const* ops_dev, int nops, int64_t gx);
 
 // Element conversion FP64 -> out dtype (F64/F32).
 hipError_t convert_out(hipStream_t st, const double* src, void* dst, tt_dtype dt, int64_t n);
@@ -96,15 +102,27 @@ hipError_t convert_out(hipStream_t st, const double* src, void* dst, tt_dtype dt
 // Pass 1: Z(p,a) = sum_j X(p,j) B(a,j), X P x J (p fastest) of dtype `xdt`,
 // B r x J FP32; Z written FP64 (P x r column-major) from FP32 partial tiles
 // (ws, plan.ws_floats floats) added in FP64.  Sets *flag if Z is non-finite.
-// Per-member pointers of a batch of same-shape streams: the slice x (its
-// element type is the batch's), the interface w (B for pass 1, A for pass 2),
-// the output (Z or Y), pass 1's partial tiles and the non-finite flag.
-struct PassPtrs {
+// One member of a batched pass launch: the slice x (the batch's element
+// type), the interface w (B for pass 1, A for pass 2), the output (Z or Y),
+// the pass's workspace (FP32 partial tiles), the non-finite flag, the
+// member's P, J, r and its plan's tiles and chunks.  Members of one launch
+// share the kernel's template shape (rows per lane, waves, rank tiles).
+struct PassDesc {
   const void* x;
   const float* w;
   double* out;
-  float* ws;   // the pass's workspace (FP32 partial tiles)
+  float* ws;
   int* flag;
+  int64_t P, J;
+  int32_t r, tiles, chunks, pad;
+};
+// A batched pass launch: n members (device array), grid.x of the main and
+// the reduction kernel covering the largest member (blocks past a member's
+// own grid return at once).
+struct PassLaunch {
+  const PassDesc* desc;
+  int n;
+  unsigned gx, grx;
 };
 
 struct Pass1Plan {
@@ -118,17 +136,22 @@ struct Pass1Plan {
 Pass1Plan pass1_plan(int64_t P, int64_t J, int r, int cus);
 // Recomputes tiles and ws_floats after vec/ntn/waves/chunks were set.
 Pass1Plan finish_plan(Pass1Plan plan, int64_t P);
-// With batch != null (device array of nbatch entries) the grid gains a member
-// index and every member's pointers come from the array (X, B, Z, ws, flag
-// are then ignored).
+// With bl != null the grid gains a member index and every member's pointers,
+// shape and tiles come from bl->desc (X, P, J, r, B, Z, ws, flag and the
+// plan's tiles and chunks are then ignored; the plan's template shape must be
+// every member's).  pass1_grids gives the main and reduction grid.x of a
+// member.
 hipError_t pass1(hipStream_t st, const void* X, tt_dtype xdt, const Pass1Plan& plan, int64_t P, int64_t J, int r,
-                 const float* B, double* Z, float* ws, int* flag, const PassPtrs* batch = nullptr,
-                 int nbatch = 1);
+                 const float* B, double* Z, float* ws, int* flag, const PassLaunch* bl = nullptr);
+void pass1_grids(const Pass1Plan& plan, int64_t P, unsigned* gx, unsigned* grx);
 
 // Pass 2: Y(a,j) = sum_p A(p,a) X(p,j); A P x r FP32 column-major; Y FP64
 // r x J column-major.  Sets *flag if Y non-finite.
 hipError_t pass2(hipStream_t st, const void* X, tt_dtype xdt, int64_t P, int64_t J, int r,
-                 const float* A, double* Y, int* flag, const PassPtrs* batch = nullptr, int nbatch = 1);
+                 const float* A, double* Y, int* flag, const PassLaunch* bl = nullptr);
+unsigned pass2_grid(int64_t J);
+// Template shape of pass 2 for these sizes (members of one launch share it).
+int pass2_vec(int64_t P);
 
 // ---------------------------------------------------------------- passes (BF16)
 // The same two contractions with the slice and the interface rounded to BF16
@@ -150,11 +173,14 @@ PassBPlan pass2b_plan(int64_t P, int64_t J, int r, int cus);
 PassBPlan pass1b_finish(PassBPlan pl, int64_t P, int64_t J);
 PassBPlan pass2b_finish(PassBPlan pl, int64_t P, int64_t J);
 hipError_t pass1_bf16(hipStream_t st, const void* X, tt_dtype xdt, const PassBPlan& plan, int64_t P, int64_t J,
-                      int r, const float* B, double* Z, void* ws, int* flag, const PassPtrs* batch = nullptr,
-                      int nbatch = 1);
+                      int r, const float* B, double* Z, void* ws, int* flag, const PassLaunch* bl = nullptr);
 hipError_t pass2_bf16(hipStream_t st, const void* X, tt_dtype xdt, const PassBPlan& plan, int64_t P, int64_t J,
-                      int r, const float* A, double* Y, void* ws, int* flag, const PassPtrs* batch = nullptr,
-                      int nbatch = 1);
+                      int r, const float* A, double* Y, void* ws, int* flag, const PassLaunch* bl = nullptr);
+void pass1b_grids(const PassBPlan& plan, unsigned* gx, unsigned* grx);
+void pass2b_grids(const PassBPlan& plan, unsigned* gx, unsigned* grx);
+// Pass 2 (BF16) loads 8-row vectors when P % 8 == 0 (part of its template
+// shape: members of one launch share it).
+bool pass2b_vx(int64_t P);
 
 // ---------------------------------------------------------------- tuner
 struct PassPlans {

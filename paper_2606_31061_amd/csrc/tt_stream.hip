@@ -27,6 +27,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <array>
 #include <vector>
 
 namespace ttk {
@@ -51,7 +52,9 @@ struct Step {
 struct UpdatePlan {
   std::vector<ttk::ChainOp> ops;
   std::vector<Step> steps;
-  ttk::ChainOp* dev = nullptr;
+  ttk::ChainOp* dev = nullptr;     // the ops on the device
+  ttk::ChainSeg* segs = nullptr;   // segs[i]: step i's operations (device; chain steps)
+  ttk::ChainOp** opptr = nullptr;  // opptr[i] = dev + i (device)
 };
 
 thread_local std::string g_last_error = "no error";
@@ -125,7 +128,6 @@ struct tt_stream {
   double* state[2] = {nullptr, nullptr};
   int cur = 0;               // state[cur] is the committed state
   UpdatePlan plan[2];        // plan[p] reads state[p], writes state[p ^ 1]
-  ttk::ChainOp** plist = nullptr;  // device {plan[0].dev, plan[1].dev}
   double* work = nullptr;
   double* Rbuf = nullptr;
   int64_t* trace = nullptr;  // 2 stamps per chain op (TT_FLAG_PROFILE_OPS)
@@ -426,41 +428,39 @@ void build_plan(tt_stream* s, int par) {
   }
 }
 
-// Runs the steps of plan P for n streams that share its structure:
-// lists_dev holds their n op-list pointers; p1/p2 (device arrays of n
-// entries) carry their pass pointers, or are null for one stream, whose own
-// buffers s and slice X are used.
-tt_status run_steps(hipStream_t st, const tt_stream* s, const UpdatePlan& P, const ttk::ChainOp* const* lists_dev,
-                    int n, const void* X, tt_dtype xdt, const ttk::PassPtrs* p1, const ttk::PassPtrs* p2,
+// Runs the steps of plan P of stream s with slice X.  trace (if not null)
+// receives two stamps per chain operation; pass_ev (if not null) four events
+// around the two passes.
+tt_status run_steps(hipStream_t st, const tt_stream* s, const UpdatePlan& P, const void* X, tt_dtype xdt,
                     int64_t* trace, hipEvent_t const* pass_ev = nullptr) {
   const int ks = s->kstar;
-  for (const Step& step : P.steps) {
+  for (size_t si = 0; si < P.steps.size(); ++si) {
+    const Step& step = P.steps[si];
     switch (step.kind) {
       case kStepChain:
-        TT_HIP(ttk::chain_run(st, lists_dev, n, step.first, step.count, trace ? trace + 2 * step.first : nullptr));
+        TT_HIP(ttk::chain_run(st, P.segs + si, 1, trace ? trace + 2 * step.first : nullptr));
         break;
       case kStepWide: {
         const ttk::ChainOp& o = P.ops[step.first];
-        TT_HIP(ttk::gemm64_ops(st, lists_dev, n, step.first, o.m, o.n, o.k));
+        TT_HIP(ttk::gemm64_ops(st, P.opptr + step.first, 1, ttk::gemm64_blocks(o.m, o.n, o.k)));
         break;
       }
       case kStepPass1:
         if (pass_ev) TT_HIP(hipEventRecord(pass_ev[0], st));
         if (s->compute == TT_BF16)
           TT_HIP(ttk::pass1_bf16(st, X, xdt, s->p1b, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->B32, s->Z, s->ws,
-                                 s->flag, p1, n));
+                                 s->flag));
         else
-          TT_HIP(ttk::pass1(st, X, xdt, s->p1, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->B32, s->Z, s->ws, s->flag,
-                            p1, n));
+          TT_HIP(ttk::pass1(st, X, xdt, s->p1, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->B32, s->Z, s->ws, s->flag));
         if (pass_ev) TT_HIP(hipEventRecord(pass_ev[1], st));
         break;
       case kStepPass2:
         if (pass_ev) TT_HIP(hipEventRecord(pass_ev[2], st));
         if (s->compute == TT_BF16)
           TT_HIP(ttk::pass2_bf16(st, X, xdt, s->p2b, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->A32, s->Y[0], s->ws2,
-                                 s->flag, p2, n));
+                                 s->flag));
         else
-          TT_HIP(ttk::pass2(st, X, xdt, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->A32, s->Y[0], s->flag, p2, n));
+          TT_HIP(ttk::pass2(st, X, xdt, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->A32, s->Y[0], s->flag));
         if (pass_ev) TT_HIP(hipEventRecord(pass_ev[3], st));
         break;
       default:
@@ -471,35 +471,52 @@ tt_status run_steps(hipStream_t st, const tt_stream* s, const UpdatePlan& P, con
 }
 
 tt_status run_plan(tt_stream* s, const void* X, tt_dtype xdt) {
-  return run_steps(s->stream, s, s->plan[s->cur], s->plist + s->cur, 1, X, xdt, nullptr, nullptr, s->trace,
-                   s->evpass[0] ? s->evpass : nullptr);
+  return run_steps(s->stream, s, s->plan[s->cur], X, xdt, s->trace, s->evpass[0] ? s->evpass : nullptr);
 }
 
 }  // namespace
 
-// A group of same-shape members of a batch and its launch descriptors: op
-// list pointers and pass pointers, uploaded per push from a ring of pinned
-// host slots (a slot is rewritten only after its previous copy completed).
-struct BatchGroup {
-  std::vector<int> idx;
-  ttk::ChainOp** lists_dev = nullptr;
-  ttk::PassPtrs* p1_dev = nullptr;
-  ttk::PassPtrs* p2_dev = nullptr;
-  static constexpr int kSlots = 8;
-  char* host[kSlots] = {};
-  hipEvent_t done[kSlots] = {};
-  bool used[kSlots] = {};
-  int next = 0;
-  size_t bytes = 0;
+// A batch runs one update of every member with launches shared by all
+// members, whatever their shapes: the update's steps are cut at the two slice
+// passes into three phases; inside a phase each member alternates chain
+// segments and whole-GPU products, and slot w of every member runs in one
+// launch (chain segment w on one workgroup per member, then product w of the
+// members that have one).  Each pass runs as one launch per kernel template
+// shape, over the members of that shape.  Every member computes exactly what
+// it computes alone: the same operations, kernels and launch shapes.
+enum BatchLaunchKind { kBlChain = 0, kBlWide = 1, kBlPass1 = 2, kBlPass2 = 3 };
+struct BatchLaunch {
+  int kind = 0;
+  int phase = 0, slot = 0;       // chain/wide: phase and slot
+  std::vector<int> members;      // participating members (batch order)
+  size_t off = 0;                // descriptor offset in the upload
+  int64_t gx = 0;                // wide: grid.x; passes: main grid.x
+  unsigned grx = 0;              // passes: reduction grid.x
+  int rep = -1;                  // passes: a member whose plan gives the template shape
+};
+// Per member and phase: chain segments (first, count) and, between them,
+// whole-GPU product op indices (segments = products + 1).
+struct MemberPhase {
+  std::vector<std::pair<int, int>> segs;
+  std::vector<int> wides;
 };
 
 constexpr uint64_t kBatchMagic = 0x54544241544348ULL;  // "TTBATCH"
+constexpr int kBatchSlots = 8;
 
 struct tt_batch {
   uint64_t magic = kBatchMagic;
   hipStream_t stream = nullptr;
   std::vector<tt_stream*> members;
-  std::vector<BatchGroup> groups;
+  std::vector<std::array<MemberPhase, 3>> phases;
+  std::vector<BatchLaunch> launches;
+  int n_groups = 0;              // distinct update structures (informational)
+  size_t bytes = 0;              // descriptor upload per push
+  char* dev = nullptr;
+  char* host[kBatchSlots] = {};
+  hipEvent_t done[kBatchSlots] = {};
+  bool used[kBatchSlots] = {};
+  int next = 0;
   std::vector<int> rejected_seen;
 };
 
@@ -507,10 +524,9 @@ namespace {
 
 bool batch_valid(const tt_batch* b) { return b != nullptr && b->magic == kBatchMagic; }
 
-// Same step sequence: same shapes, split point and plan structure.
+// Same update structure: shapes, split point, precision, pass plans and ops.
 bool same_structure(const tt_stream* a, const tt_stream* b) {
   if (a->m != b->m || a->kstar != b->kstar || a->I != b->I || a->r != b->r || a->compute != b->compute) return false;
-  // same launch shapes of the passes (a tuned and an untuned stream differ)
   const auto same1 = [](const ttk::Pass1Plan& x, const ttk::Pass1Plan& y) {
     return x.vec == y.vec && x.ntn == y.ntn && x.waves == y.waves && x.chunks == y.chunks;
   };
@@ -531,15 +547,159 @@ bool same_structure(const tt_stream* a, const tt_stream* b) {
   return true;
 }
 
-void batch_release(tt_batch* b) {
-  for (BatchGroup& g : b->groups) {
-    if (g.lists_dev) (void)hipFree(g.lists_dev);
-    for (int k = 0; k < BatchGroup::kSlots; ++k) {
-      if (g.done[k]) (void)hipEventDestroy(g.done[k]);
-      if (g.host[k]) (void)hipHostFree(g.host[k]);
+// Template shape of a member's pass launch (members of one launch share it).
+std::array<int, 5> pass_key(const tt_stream* s, int pass) {
+  const int ks = s->kstar;
+  const int ntn = s->r[ks] <= 32 ? 1 : 2;
+  if (s->compute == TT_BF16) {
+    if (pass == 1) return {1, 1, s->p1b.vec, s->p1b.waves, ntn};
+    return {1, 2, ttk::pass2b_vx(s->Pk[ks]) ? 1 : 0, s->p2b.waves, ntn};
+  }
+  if (pass == 1) return {0, 1, s->p1.vec, s->p1.waves, s->p1.ntn};
+  return {0, 2, ttk::pass2_vec(s->Pk[ks]), 0, ntn};
+}
+
+void pass_grids(const tt_stream* s, int pass, int64_t* gx, unsigned* grx) {
+  const int ks = s->kstar;
+  unsigned a = 0, b = 0;
+  if (s->compute == TT_BF16) {
+    if (pass == 1) ttk::pass1b_grids(s->p1b, &a, &b);
+    else ttk::pass2b_grids(s->p2b, &a, &b);
+  } else if (pass == 1) {
+    ttk::pass1_grids(s->p1, s->Pk[ks], &a, &b);
+  } else {
+    a = ttk::pass2_grid(s->Jk[ks]);
+  }
+  *gx = a;
+  *grx = b;
+}
+
+ttk::PassDesc pass_desc(const tt_stream* s, int pass, const void* x) {
+  const int ks = s->kstar;
+  ttk::PassDesc d{};
+  d.x = x;
+  d.w = pass == 1 ? s->B32 : s->A32;
+  d.out = pass == 1 ? s->Z : s->Y[0];
+  d.ws = pass == 1 ? s->ws : s->ws2;
+  d.flag = s->flag;
+  d.P = s->Pk[ks];
+  d.J = s->Jk[ks];
+  d.r = (int32_t)s->r[ks];
+  if (s->compute == TT_BF16) {
+    const ttk::PassBPlan& pl = pass == 1 ? s->p1b : s->p2b;
+    d.tiles = pl.tiles;
+    d.chunks = pl.chunks;
+  } else {
+    d.tiles = (int32_t)((d.P + 32 * s->p1.vec - 1) / (32 * s->p1.vec));
+    d.chunks = s->p1.chunks;
+  }
+  return d;
+}
+
+// The launch sequence of a batch (its shape does not change between pushes).
+void build_schedule(tt_batch* b) {
+  const int n = (int)b->members.size();
+  b->phases.assign(n, {});
+  for (int i = 0; i < n; ++i) {
+    const UpdatePlan& P = b->members[i]->plan[0];
+    int ph = 0;
+    auto& mp = b->phases[i];
+    for (auto& x : mp) x.segs.push_back({0, 0});
+    for (const Step& st : P.steps) {
+      if (st.kind == kStepChain) {
+        mp[ph].segs.back() = {st.first, st.count};
+      } else if (st.kind == kStepWide) {
+        mp[ph].wides.push_back(st.first);
+        mp[ph].segs.push_back({0, 0});
+      } else {
+        ++ph;
+      }
     }
   }
-  b->groups.clear();
+  b->launches.clear();
+  size_t off = 0;
+  auto add = [&](BatchLaunch&& L, size_t bytes) {
+    L.off = off;
+    off += (bytes + 255) & ~size_t(255);
+    b->launches.push_back(std::move(L));
+  };
+  for (int ph = 0; ph < 3; ++ph) {
+    size_t W = 0;
+    for (int i = 0; i < n; ++i) W = std::max(W, b->phases[i][ph].wides.size());
+    for (size_t w = 0; w <= W; ++w) {
+      bool any = false;
+      for (int i = 0; i < n; ++i) {
+        const auto& mp = b->phases[i][ph];
+        any = any || (w < mp.segs.size() && mp.segs[w].second > 0);
+      }
+      if (any) {
+        BatchLaunch L;
+        L.kind = kBlChain;
+        L.phase = ph;
+        L.slot = (int)w;
+        for (int i = 0; i < n; ++i) L.members.push_back(i);
+        add(std::move(L), sizeof(ttk::ChainSeg) * n);
+      }
+      if (w < W) {
+        BatchLaunch L;
+        L.kind = kBlWide;
+        L.phase = ph;
+        L.slot = (int)w;
+        for (int i = 0; i < n; ++i) {
+          const auto& mp = b->phases[i][ph];
+          if (w < mp.wides.size()) {
+            L.members.push_back(i);
+            const ttk::ChainOp& o = b->members[i]->plan[0].ops[mp.wides[w]];
+            L.gx = std::max(L.gx, ttk::gemm64_blocks(o.m, o.n, o.k));
+          }
+        }
+        const size_t k = L.members.size();
+        add(std::move(L), sizeof(ttk::ChainOp*) * k);
+      }
+    }
+    if (ph < 2) {
+      const int pass = ph + 1;
+      std::vector<std::array<int, 5>> keys;
+      std::vector<std::vector<int>> groups;
+      for (int i = 0; i < n; ++i) {
+        const auto key = pass_key(b->members[i], pass);
+        size_t g = 0;
+        while (g < keys.size() && keys[g] != key) ++g;
+        if (g == keys.size()) {
+          keys.push_back(key);
+          groups.emplace_back();
+        }
+        groups[g].push_back(i);
+      }
+      for (auto& grp : groups) {
+        BatchLaunch L;
+        L.kind = pass == 1 ? kBlPass1 : kBlPass2;
+        L.members = grp;
+        L.rep = grp[0];
+        for (int i : grp) {
+          int64_t gx;
+          unsigned grx;
+          pass_grids(b->members[i], pass, &gx, &grx);
+          L.gx = std::max(L.gx, gx);
+          L.grx = std::max(L.grx, grx);
+        }
+        const size_t k = L.members.size();
+        add(std::move(L), sizeof(ttk::PassDesc) * k);
+      }
+    }
+  }
+  b->bytes = off;
+}
+
+void batch_release(tt_batch* b) {
+  if (b->dev) (void)hipFree(b->dev);
+  b->dev = nullptr;
+  for (int k = 0; k < kBatchSlots; ++k) {
+    if (b->done[k]) (void)hipEventDestroy(b->done[k]);
+    if (b->host[k]) (void)hipHostFree(b->host[k]);
+    b->done[k] = nullptr;
+    b->host[k] = nullptr;
+  }
 }
 
 }  // namespace
@@ -548,6 +708,7 @@ extern "C" {
 
 tt_status tt_batch_create(tt_stream* const* streams, int32_t n, void* hip_stream, tt_batch** out) {
   if (!streams || !out || n < 1) return fail(TT_ERR_INVALID_ARG, "null argument or n < 1");
+  if (n > 65535) return fail(TT_ERR_INVALID_ARG, "at most 65535 streams per batch");
   *out = nullptr;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return fail(TT_ERR_DEVICE, "hipGetDevice failed");
@@ -565,43 +726,31 @@ tt_status tt_batch_create(tt_stream* const* streams, int32_t n, void* hip_stream
   b->stream = static_cast<hipStream_t>(hip_stream);
   b->members.assign(streams, streams + n);
   b->rejected_seen.resize(n);
+  std::vector<int> reps;
   for (int i = 0; i < n; ++i) {
-    bool placed = false;
-    for (BatchGroup& g : b->groups)
-      if (same_structure(b->members[g.idx[0]], b->members[i])) {
-        g.idx.push_back(i);
-        placed = true;
-        break;
-      }
-    if (!placed) {
-      b->groups.emplace_back();
-      b->groups.back().idx.push_back(i);
-    }
+    bool seen = false;
+    for (int j : reps) seen = seen || same_structure(b->members[j], b->members[i]);
+    if (!seen) reps.push_back(i);
     b->rejected_seen[i] = b->members[i]->rejected_seen;
   }
-  for (BatchGroup& g : b->groups) {
-    const size_t k = g.idx.size();
-    g.bytes = k * (sizeof(ttk::ChainOp*) + 2 * sizeof(ttk::PassPtrs));
-    void* d = nullptr;
-    if (hipMalloc(&d, g.bytes) != hipSuccess) {
+  b->n_groups = (int)reps.size();
+  build_schedule(b);
+  void* d = nullptr;
+  if (hipMalloc(&d, b->bytes) != hipSuccess) {
+    delete b;
+    return fail(TT_ERR_OOM, "batch descriptor allocation failed");
+  }
+  b->dev = static_cast<char*>(d);
+  for (int q = 0; q < kBatchSlots; ++q) {
+    void* h = nullptr;
+    if (hipHostMalloc(&h, b->bytes, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&b->done[q], hipEventDisableTiming) != hipSuccess) {
+      if (h) (void)hipHostFree(h);
       batch_release(b);
       delete b;
-      return fail(TT_ERR_OOM, "batch descriptor allocation failed");
+      return fail(TT_ERR_OOM, "batch staging allocation failed");
     }
-    g.lists_dev = static_cast<ttk::ChainOp**>(d);
-    g.p1_dev = reinterpret_cast<ttk::PassPtrs*>(static_cast<char*>(d) + k * sizeof(ttk::ChainOp*));
-    g.p2_dev = g.p1_dev + k;
-    for (int q = 0; q < BatchGroup::kSlots; ++q) {
-      void* h = nullptr;
-      if (hipHostMalloc(&h, g.bytes, hipHostMallocDefault) != hipSuccess ||
-          hipEventCreateWithFlags(&g.done[q], hipEventDisableTiming) != hipSuccess) {
-        if (h) (void)hipHostFree(h);
-        batch_release(b);
-        delete b;
-        return fail(TT_ERR_OOM, "batch staging allocation failed");
-      }
-      g.host[q] = static_cast<char*>(h);
-    }
+    b->host[q] = static_cast<char*>(h);
   }
   *out = b;
   return TT_OK;
@@ -610,35 +759,70 @@ tt_status tt_batch_create(tt_stream* const* streams, int32_t n, void* hip_stream
 tt_status tt_batch_push(tt_batch* b, const void* const* slices, tt_dtype dtype) {
   if (!batch_valid(b) || !slices) return fail(TT_ERR_INVALID_ARG, "invalid batch or null slices");
   if (dtype != TT_F64 && dtype != TT_F32 && dtype != TT_BF16) return fail(TT_ERR_INVALID_ARG, "bad dtype");
-  for (size_t i = 0; i < b->members.size(); ++i)
+  const int n = (int)b->members.size();
+  for (int i = 0; i < n; ++i)
     if (!slices[i]) return fail(TT_ERR_INVALID_ARG, "null slice");
-  for (BatchGroup& g : b->groups) {
-    const int k = (int)g.idx.size();
-    const int q = g.next;
-    g.next = (g.next + 1) % BatchGroup::kSlots;
-    if (g.used[q]) TT_HIP(hipEventSynchronize(g.done[q]));
-    char* h = g.host[q];
-    ttk::ChainOp** lists = reinterpret_cast<ttk::ChainOp**>(h);
-    ttk::PassPtrs* p1 = reinterpret_cast<ttk::PassPtrs*>(h + k * sizeof(ttk::ChainOp*));
-    ttk::PassPtrs* p2 = p1 + k;
-    for (int i = 0; i < k; ++i) {
-      tt_stream* s = b->members[g.idx[i]];
-      lists[i] = s->plan[s->cur].dev;
-      p1[i] = ttk::PassPtrs{slices[g.idx[i]], s->B32, s->Z, s->ws, s->flag};
-      p2[i] = ttk::PassPtrs{slices[g.idx[i]], s->A32, s->Y[0], s->ws2, s->flag};
+  // descriptors of this push into a free pinned slot, then one upload
+  const int q = b->next;
+  b->next = (b->next + 1) % kBatchSlots;
+  if (b->used[q]) TT_HIP(hipEventSynchronize(b->done[q]));
+  char* h = b->host[q];
+  for (const BatchLaunch& L : b->launches) {
+    char* p = h + L.off;
+    if (L.kind == kBlChain) {
+      ttk::ChainSeg* sg = reinterpret_cast<ttk::ChainSeg*>(p);
+      for (int i = 0; i < n; ++i) {
+        const tt_stream* s = b->members[i];
+        const auto& mp = b->phases[i][L.phase];
+        const auto seg = L.slot < (int)mp.segs.size() ? mp.segs[L.slot] : std::pair<int, int>{0, 0};
+        sg[i] = ttk::ChainSeg{s->plan[s->cur].dev + seg.first, seg.second, 0};
+      }
+    } else if (L.kind == kBlWide) {
+      ttk::ChainOp** op = reinterpret_cast<ttk::ChainOp**>(p);
+      for (size_t k = 0; k < L.members.size(); ++k) {
+        const int i = L.members[k];
+        const tt_stream* s = b->members[i];
+        op[k] = s->plan[s->cur].dev + b->phases[i][L.phase].wides[L.slot];
+      }
+    } else {
+      const int pass = L.kind == kBlPass1 ? 1 : 2;
+      ttk::PassDesc* pd = reinterpret_cast<ttk::PassDesc*>(p);
+      for (size_t k = 0; k < L.members.size(); ++k)
+        pd[k] = pass_desc(b->members[L.members[k]], pass, slices[L.members[k]]);
     }
-    TT_HIP(hipMemcpyAsync(g.lists_dev, h, g.bytes, hipMemcpyHostToDevice, b->stream));
-    TT_HIP(hipEventRecord(g.done[q], b->stream));
-    g.used[q] = true;
-    tt_stream* s0 = b->members[g.idx[0]];
-    tt_status st = run_steps(b->stream, s0, s0->plan[s0->cur], g.lists_dev, k, nullptr, dtype, g.p1_dev, g.p2_dev,
-                             nullptr);
-    if (st != TT_OK) return st;
-    for (int i = 0; i < k; ++i) {
-      tt_stream* s = b->members[g.idx[i]];
-      s->cur ^= 1;
-      s->pushes++;
+  }
+  TT_HIP(hipMemcpyAsync(b->dev, h, b->bytes, hipMemcpyHostToDevice, b->stream));
+  TT_HIP(hipEventRecord(b->done[q], b->stream));
+  b->used[q] = true;
+  for (const BatchLaunch& L : b->launches) {
+    char* p = b->dev + L.off;
+    const int k = (int)L.members.size();
+    if (L.kind == kBlChain) {
+      TT_HIP(ttk::chain_run(b->stream, reinterpret_cast<const ttk::ChainSeg*>(p), n));
+    } else if (L.kind == kBlWide) {
+      TT_HIP(ttk::gemm64_ops(b->stream, reinterpret_cast<const ttk::ChainOp* const*>(p), k, L.gx));
+    } else {
+      const tt_stream* s = b->members[L.rep];
+      const int ks = s->kstar;
+      ttk::PassLaunch bl{reinterpret_cast<const ttk::PassDesc*>(p), k, (unsigned)L.gx, L.grx};
+      const int64_t P = s->Pk[ks], J = s->Jk[ks];
+      const int r = (int)s->r[ks];
+      if (L.kind == kBlPass1) {
+        if (s->compute == TT_BF16)
+          TT_HIP(ttk::pass1_bf16(b->stream, nullptr, dtype, s->p1b, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
+        else
+          TT_HIP(ttk::pass1(b->stream, nullptr, dtype, s->p1, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
+      } else {
+        if (s->compute == TT_BF16)
+          TT_HIP(ttk::pass2_bf16(b->stream, nullptr, dtype, s->p2b, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
+        else
+          TT_HIP(ttk::pass2(b->stream, nullptr, dtype, P, J, r, nullptr, nullptr, nullptr, &bl));
+      }
     }
+  }
+  for (tt_stream* s : b->members) {
+    s->cur ^= 1;
+    s->pushes++;
   }
   return TT_OK;
 }
@@ -663,7 +847,7 @@ tt_status tt_batch_synchronize(tt_batch* b, int32_t* rejected) {
 tt_status tt_batch_info(const tt_batch* b, int32_t* n_streams, int32_t* n_groups) {
   if (!batch_valid(b)) return fail(TT_ERR_INVALID_ARG, "invalid batch");
   if (n_streams) *n_streams = (int32_t)b->members.size();
-  if (n_groups) *n_groups = (int32_t)b->groups.size();
+  if (n_groups) *n_groups = (int32_t)b->n_groups;
   return TT_OK;
 }
 
@@ -846,16 +1030,25 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
     UpdatePlan& P = s->plan[par];
     for (const ttk::ChainOp& op : P.ops)
       if (!ttk::chain_op_supported(op)) return bail(TT_ERR_UNSUPPORTED, "a core re-orthogonalisation exceeds 256 columns");
-    P.dev = static_cast<ttk::ChainOp*>(dev_alloc(s, sizeof(ttk::ChainOp) * P.ops.size()));
-    if (!P.dev) return bail(TT_ERR_OOM, "plan allocation failed");
-    TT_HIP_BAIL(hipMemcpyAsync(P.dev, P.ops.data(), sizeof(ttk::ChainOp) * P.ops.size(), hipMemcpyHostToDevice,
-                               s->stream));
-  }
-  {
-    ttk::ChainOp* lists[2] = {s->plan[0].dev, s->plan[1].dev};
-    s->plist = static_cast<ttk::ChainOp**>(dev_alloc(s, sizeof(lists)));
-    if (!s->plist) return bail(TT_ERR_OOM, "plan allocation failed");
-    TT_HIP_BAIL(hipMemcpy(s->plist, lists, sizeof(lists), hipMemcpyHostToDevice));
+    // one device block: ops, then a segment per step, then a pointer per op
+    const size_t nops = P.ops.size(), nsteps = P.steps.size();
+    const size_t b_ops = sizeof(ttk::ChainOp) * nops, b_segs = sizeof(ttk::ChainSeg) * nsteps;
+    char* blk = static_cast<char*>(dev_alloc(s, b_ops + b_segs + sizeof(ttk::ChainOp*) * nops));
+    if (!blk) return bail(TT_ERR_OOM, "plan allocation failed");
+    P.dev = reinterpret_cast<ttk::ChainOp*>(blk);
+    P.segs = reinterpret_cast<ttk::ChainSeg*>(blk + b_ops);
+    P.opptr = reinterpret_cast<ttk::ChainOp**>(blk + b_ops + b_segs);
+    std::vector<char> host(b_ops + b_segs + sizeof(ttk::ChainOp*) * nops);
+    std::memcpy(host.data(), P.ops.data(), b_ops);
+    for (size_t i = 0; i < nsteps; ++i) {
+      ttk::ChainSeg sg{P.dev + P.steps[i].first, P.steps[i].kind == kStepChain ? P.steps[i].count : 0, 0};
+      std::memcpy(host.data() + b_ops + i * sizeof(sg), &sg, sizeof(sg));
+    }
+    for (size_t i = 0; i < nops; ++i) {
+      ttk::ChainOp* q = P.dev + i;
+      std::memcpy(host.data() + b_ops + b_segs + i * sizeof(q), &q, sizeof(q));
+    }
+    TT_HIP_BAIL(hipMemcpy(blk, host.data(), host.size(), hipMemcpyHostToDevice));
   }
   if (s->flags & TT_FLAG_PROFILE_OPS) {
     s->trace_len = (int64_t)std::max(s->plan[0].ops.size(), s->plan[1].ops.size());

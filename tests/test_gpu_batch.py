@@ -121,3 +121,56 @@ def test_nonfinite_slice_is_rejected_for_its_member_only():
         assert _states_equal(a, b)
     assert [s.time() for s in streams] == [2, 1, 2]
     batch.close()
+
+
+def _mixed_members(n, seed, T, max_elems=60000):
+    """Streams of uneven order (3-5), mode sizes and ranks ({4,8,16,32},
+    clamped to feasibility), low rank plus noise; every third member uses
+    BF16 contractions."""
+    from paper_2606_31061_amd.binding import tt_clamp_ranks
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    while len(out) < n:
+        order = int(rng.integers(3, 6))
+        hi = {3: 200, 4: 40, 5: 16}[order]
+        modes = tuple(int(v) for v in rng.integers(4, hi + 1, order - 1))
+        if int(np.prod(modes)) > max_elems:
+            continue
+        rank = int(rng.choice([4, 8, 16, 32]))
+        ranks = tuple(int(v) for v in tt_clamp_ranks(modes, [rank] * len(modes)))
+        q = len(out)
+        st = exact_tt_stream(modes, ranks, ranks, T, seed + 10 * q, seed + 10 * q + 1, sigma=1e-2)
+        out.append((st, "bf16" if q % 3 == 2 else "f32"))
+    return out
+
+
+def test_heterogeneous_batch_is_bitwise_equal_to_solo_runs():
+    torch = torch_cuda()
+    from paper_2606_31061_amd import TTBatch, TTStream
+    T = 3
+    members = _mixed_members(10, 4100, T)
+    say("heterogeneous batch of 10 streams, orders 3-5, f32 and bf16 contractions: "
+        + "; ".join(f"{st.modes} r{st.ranks} {c}" for st, c in members))
+    solo = [TTStream(st.modes, st.ranks, init=st.init(), compute=c) for st, c in members]
+    batched = [TTStream(st.modes, st.ranks, init=st.init(), compute=c) for st, c in members]
+    batch = TTBatch(batched)
+    assert batch.info()["streams"] == 10
+    dev = [[to_device_slice(torch, X.astype(np.float32)) for X in st.frames(1, T)] for st, _ in members]
+    for t in range(T):
+        for s, xs in zip(solo, dev):
+            s.push(xs[t])
+        batch.push([xs[t] for xs in dev])
+    assert batch.synchronize() == [0] * 10
+    for s in solo:
+        s.synchronize()
+    for a, b in zip(solo, batched):
+        assert _states_equal(a, b)
+    # the FP32 members follow the oracle
+    for (st, c), s in zip(members, batched):
+        if c != "f32":
+            continue
+        xs = [X.astype(np.float32).astype(np.float64) for X in st.frames(1, T)]
+        init = st.init()
+        ref = ttals.run_stream(xs, init[0], init[1], keep_M=True)
+        assert rel(s.reconstruct(), ref.infos[-1].M, np.linalg.norm(xs[-1])) <= M_TOL
+    batch.close()
