@@ -64,6 +64,97 @@ def time_passes_in_update(stream, pool, steps):
     return {"pass1": float(np.mean(t1)), "pass2": float(np.mean(t2))}
 
 
+def batched_section(torch, n_streams, rounds, warmup, compute, tune):
+    """The batched workload: n_streams streams of order 3-5 with uneven mode
+    sizes and ranks, advanced together (one TTBatch push = one update of
+    every stream) with graph replay, against the same streams pushed one by
+    one through the single-stream path."""
+    from paper_2606_31061_amd import TTBatch, TTStream, binding
+    from ttgen import config_c4_streams
+    specs = config_c4_streams(n_streams, 1004, T=2, clamp=binding.tt_clamp_ranks, max_elems=1 << 21)
+    orders = sorted(len(sp.modes) + 1 for sp in specs)
+    elems = [sp.n_elems for sp in specs]
+    log(f"batched workload: {n_streams} streams, orders {orders[0]}-{orders[-1]}, slices {min(elems)}-{max(elems)} "
+        f"elements ({sum(elems) / 1e6:.1f} M per round)")
+    side = torch.cuda.Stream()
+    out = {}
+    with torch.cuda.stream(side):
+        frames = [[torch.from_numpy(np.ascontiguousarray(X.reshape(-1, order="F"))).cuda() for X in sp.frames(1, 2)]
+                  for sp in specs]
+        if compute == "bf16":
+            frames = [[x.to(torch.bfloat16) for x in f] for f in frames]
+        bytes_round = 0
+        for sp in specs:
+            members = TTStream(sp.modes, sp.ranks, init=sp.init(), compute=compute, autotune=tune)
+            k = members.info()["split_point"]
+            members.close()
+            P, J, r = int(np.prod(sp.modes[:k])), int(np.prod(sp.modes[k:])), sp.ranks[k - 1]
+            b1, b2 = pass_bytes(P, J, r, 2 if compute == "bf16" else 4)
+            bytes_round += b1 + b2
+
+        def run(batch_graph, solo):
+            streams = [TTStream(sp.modes, sp.ranks, init=sp.init(), compute=compute, autotune=tune) for sp in specs]
+            b = None if solo else TTBatch(streams, graph=batch_graph)
+
+            def one(i):
+                if solo:
+                    for st, f in zip(streams, frames):
+                        st.push(f[i % 2])
+                else:
+                    b.push([f[i % 2] for f in frames])
+
+            def sync():
+                if solo:
+                    for st in streams:
+                        st.synchronize()
+                else:
+                    b.synchronize()
+            for i in range(warmup):
+                one(i)
+            sync()
+            side.synchronize()
+            t0 = time.perf_counter()
+            for i in range(rounds):
+                one(i)
+            sync()
+            side.synchronize()
+            el = time.perf_counter() - t0
+            lat = []
+            for i in range(max(rounds, 20)):
+                ts = time.perf_counter()
+                one(i)
+                sync()
+                lat.append((time.perf_counter() - ts) * 1e3)
+            if b is not None:
+                b.close()
+            for st in streams:
+                st.close()
+            return n_streams * rounds / el, el * 1e3 / rounds, lat
+
+        g_rate, g_ms, g_lat = run(True, False)
+        log(f"batched (graph): {g_rate:.0f} updates/s, {g_ms:.3f} ms per round of {n_streams}")
+        e_rate, e_ms, _ = run(False, False)
+        log(f"batched (eager launches): {e_rate:.0f} updates/s")
+        s_rate, s_ms, s_lat = run(False, True)
+        log(f"single-stream path, streams one after another: {s_rate:.0f} updates/s")
+    out = {
+        "workload": f"c4_{n_streams}_streams_order3-5_modes16-256_ranks4-32_max2M",
+        "streams": n_streams,
+        "rounds": rounds,
+        "updates_per_s": g_rate,
+        "ms_per_round": g_ms,
+        "latency_ms_per_round": {"p50": float(np.percentile(g_lat, 50)), "p99": float(np.percentile(g_lat, 99))},
+        "eager_updates_per_s": e_rate,
+        "single_stream_updates_per_s": s_rate,
+        "single_stream_latency_ms_per_round": {"p50": float(np.percentile(s_lat, 50)),
+                                               "p99": float(np.percentile(s_lat, 99))},
+        "speedup_vs_single_stream": g_rate / s_rate,
+        "pass_bytes_per_round": bytes_round,
+        "pass_hbm_gbs_aggregate": bytes_round / (g_ms * 1e-3) / 1e9,
+    }
+    return out
+
+
 def cpu_baseline(spec, seconds_budget: float):
     """The FP64 oracle as it stands, timed on the host on a bounded sample."""
     from oracle import ttals
@@ -99,6 +190,9 @@ def main():
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--compute", default="f32", choices=["f32", "bf16"],
                     help="contraction precision; bf16 also stores the slices as BF16")
+    ap.add_argument("--batch", type=int, default=64,
+                    help="streams in the batched measurement (0: skip it)")
+    ap.add_argument("--batch-rounds", type=int, default=20)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default pass launch shapes instead of tuning them for the workload")
     ap.add_argument("--profile-ops", action="store_true",
@@ -175,6 +269,10 @@ def main():
     dom = "pass1" if kt["pass1"] >= kt["pass2"] else "pass2"
     achieved = gbs1 if dom == "pass1" else gbs2
 
+    batched = None
+    if args.batch > 0:
+        batched = batched_section(torch, args.batch, args.batch_rounds, 3, args.compute, tune)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
@@ -210,6 +308,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None},
         "slice_kernels": {"pass1_us": kt["pass1"] * 1e3, "pass1_gbs": gbs1, "pass1_bytes": b1,
                           "pass2_us": kt["pass2"] * 1e3, "pass2_gbs": gbs2, "pass2_bytes": b2},
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -1,16 +1,17 @@
 /*
  * tt_batch.h - many streams advanced together on one GPU.
  *
- * Each stream's update (Algorithm 1) is a fixed sequence of steps: chain
- * steps run by one workgroup, whole-GPU products, and the two slice passes.
- * Streams created with the same mode sizes, TT-ranks and split point have
- * identical step sequences; a batch groups such streams and launches every
- * step once for the whole group (the chain steps with one workgroup per
- * stream, the other kernels with a stream index in the grid).  Every stream
- * is computed exactly as when pushed alone (same kernels, same arithmetic,
- * same order), so its results are bitwise the same.  Streams of different
- * shapes form separate groups, launched one after the other on the batch's
- * HIP stream.
+ * Each stream's update (Algorithm 1's loop body) is a fixed sequence of
+ * steps: chain steps run by one workgroup, whole-GPU products, and the two
+ * slice passes (Eq. 5 evaluated at the split point, Section 4.2).  A batch
+ * cuts every member's sequence at the two passes into three phases and runs
+ * slot w of every member's phase in one launch (chain segment w with one
+ * workgroup per member, then product w of the members that have one); each
+ * pass runs as one launch per kernel template shape over the members of that
+ * shape.  Members may differ in order, mode sizes, ranks, split point and
+ * contraction precision.  Every member is computed exactly as when pushed
+ * alone (same kernels, launch shapes and arithmetic order), so its results
+ * are bitwise the same.
  *
  * All streams must live on the current device, were created with the
  * batch's hip_stream, and must outlive the batch.  Calls are stream-ordered
@@ -43,7 +44,15 @@ tt_status tt_batch_push(tt_batch* b, const void* const* slices, tt_dtype dtype);
  * Returns TT_ERR_NONFINITE if any member rejected a slice, else TT_OK. */
 tt_status tt_batch_synchronize(tt_batch* b, int32_t* rejected);
 
-/* Number of members and of shape groups. */
+/* Replays each push from a captured HIP graph (enable != 0): the first push
+ * through each of the batch's eight descriptor slots captures the push's
+ * descriptor upload and launches into a graph; later pushes rewrite the
+ * slot's descriptors and launch the graph.  Results are bitwise those of the
+ * eager path.  Needs a batch created on a non-default hip_stream
+ * (TT_ERR_UNSUPPORTED otherwise).  Errors: INVALID_ARG, DEVICE. */
+tt_status tt_batch_use_graph(tt_batch* b, int32_t enable);
+
+/* Number of members and of distinct update structures among them. */
 tt_status tt_batch_info(const tt_batch* b, int32_t* n_streams, int32_t* n_groups);
 
 tt_status tt_batch_destroy(tt_batch* b);

@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
         "tt_batch_push": (c_int, [sv, POINTER(c_void_p), c_int]),
         "tt_batch_synchronize": (c_int, [sv, POINTER(c_int32)]),
         "tt_batch_info": (c_int, [sv, POINTER(c_int32), POINTER(c_int32)]),
+        "tt_batch_use_graph": (c_int, [sv, c_int32]),
         "tt_batch_destroy": (c_int, [sv]),
         "tt_kernel_pass1": (c_int, [sv, c_int, c_int64, c_int64, c_int32, sv, sv, sv, sv, sv]),
         "tt_kernel_pass1_workspace": (c_size_t, [c_int64, c_int64, c_int32]),
@@ -398,11 +399,12 @@ def tt_kernel_qr(M, Q, R, workspace, hip_stream: int = 0) -> int:
 
 class TTBatch:
     """Streams advanced together (include/tt_batch.h): each push runs one
-    update of every member, every step of the update launched once per group
-    of same-shape members.  Members must share the HIP stream they were
-    created with and must outlive the batch."""
+    update of every member with launches shared by all members, whatever their
+    shapes.  Members must share the HIP stream they were created with and must
+    outlive the batch.  graph=True replays pushes from captured HIP graphs
+    (the members' stream must not be the default stream)."""
 
-    def __init__(self, streams):
+    def __init__(self, streams, graph: bool = False):
         self._lib = load_library()
         self.streams = list(streams)
         n = len(self.streams)
@@ -410,6 +412,8 @@ class TTBatch:
         sp = self.streams[0].hip_stream
         self._h = c_void_p()
         _check(self._lib.tt_batch_create(handles, n, c_void_p(sp or None), byref(self._h)), "tt_batch_create")
+        if graph:
+            _check(self._lib.tt_batch_use_graph(self._h, 1), "tt_batch_use_graph")
 
     def push(self, slices) -> None:
         """slices: one contiguous CUDA tensor per member, all of one dtype."""

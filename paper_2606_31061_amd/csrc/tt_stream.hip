@@ -516,6 +516,9 @@ struct tt_batch {
   char* host[kBatchSlots] = {};
   hipEvent_t done[kBatchSlots] = {};
   bool used[kBatchSlots] = {};
+  hipGraphExec_t graph[kBatchSlots] = {};  // per slot, when graph replay is on
+  tt_dtype graph_dtype[kBatchSlots] = {};   // slice type the slot's graph was captured for
+  bool use_graph = false;
   int next = 0;
   std::vector<int> rejected_seen;
 };
@@ -691,7 +694,15 @@ void build_schedule(tt_batch* b) {
   b->bytes = off;
 }
 
+void batch_drop_graphs(tt_batch* b) {
+  for (hipGraphExec_t& g : b->graph) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
+}
+
 void batch_release(tt_batch* b) {
+  batch_drop_graphs(b);
   if (b->dev) (void)hipFree(b->dev);
   b->dev = nullptr;
   for (int k = 0; k < kBatchSlots; ++k) {
@@ -700,6 +711,40 @@ void batch_release(tt_batch* b) {
     b->done[k] = nullptr;
     b->host[k] = nullptr;
   }
+}
+
+// Enqueues one push on the batch's stream: the descriptor upload from host
+// slot h, then every launch.
+tt_status enqueue_push(tt_batch* b, const char* h, tt_dtype dtype) {
+  const int n = (int)b->members.size();
+  TT_HIP(hipMemcpyAsync(b->dev, h, b->bytes, hipMemcpyHostToDevice, b->stream));
+  for (const BatchLaunch& L : b->launches) {
+    char* p = b->dev + L.off;
+    const int k = (int)L.members.size();
+    if (L.kind == kBlChain) {
+      TT_HIP(ttk::chain_run(b->stream, reinterpret_cast<const ttk::ChainSeg*>(p), n));
+    } else if (L.kind == kBlWide) {
+      TT_HIP(ttk::gemm64_ops(b->stream, reinterpret_cast<const ttk::ChainOp* const*>(p), k, L.gx));
+    } else {
+      const tt_stream* s = b->members[L.rep];
+      const int ks = s->kstar;
+      ttk::PassLaunch bl{reinterpret_cast<const ttk::PassDesc*>(p), k, (unsigned)L.gx, L.grx};
+      const int64_t P = s->Pk[ks], J = s->Jk[ks];
+      const int r = (int)s->r[ks];
+      if (L.kind == kBlPass1) {
+        if (s->compute == TT_BF16)
+          TT_HIP(ttk::pass1_bf16(b->stream, nullptr, dtype, s->p1b, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
+        else
+          TT_HIP(ttk::pass1(b->stream, nullptr, dtype, s->p1, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
+      } else {
+        if (s->compute == TT_BF16)
+          TT_HIP(ttk::pass2_bf16(b->stream, nullptr, dtype, s->p2b, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
+        else
+          TT_HIP(ttk::pass2(b->stream, nullptr, dtype, P, J, r, nullptr, nullptr, nullptr, &bl));
+      }
+    }
+  }
+  return TT_OK;
 }
 
 }  // namespace
@@ -791,35 +836,33 @@ tt_status tt_batch_push(tt_batch* b, const void* const* slices, tt_dtype dtype) 
         pd[k] = pass_desc(b->members[L.members[k]], pass, slices[L.members[k]]);
     }
   }
-  TT_HIP(hipMemcpyAsync(b->dev, h, b->bytes, hipMemcpyHostToDevice, b->stream));
+  if (b->use_graph && b->graph[q] && b->graph_dtype[q] != dtype) {  // kernels depend on the slice type
+    (void)hipGraphExecDestroy(b->graph[q]);
+    b->graph[q] = nullptr;
+  }
+  if (b->use_graph && !b->graph[q]) {
+    hipGraph_t g = nullptr;
+    TT_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    const tt_status st = enqueue_push(b, h, dtype);
+    const hipError_t e = hipStreamEndCapture(b->stream, &g);
+    if (st != TT_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return st;
+    }
+    TT_HIP(e);
+    const hipError_t ei = hipGraphInstantiate(&b->graph[q], g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    TT_HIP(ei);
+    b->graph_dtype[q] = dtype;
+  }
+  if (b->use_graph) {
+    TT_HIP(hipGraphLaunch(b->graph[q], b->stream));
+  } else {
+    const tt_status st = enqueue_push(b, h, dtype);
+    if (st != TT_OK) return st;
+  }
   TT_HIP(hipEventRecord(b->done[q], b->stream));
   b->used[q] = true;
-  for (const BatchLaunch& L : b->launches) {
-    char* p = b->dev + L.off;
-    const int k = (int)L.members.size();
-    if (L.kind == kBlChain) {
-      TT_HIP(ttk::chain_run(b->stream, reinterpret_cast<const ttk::ChainSeg*>(p), n));
-    } else if (L.kind == kBlWide) {
-      TT_HIP(ttk::gemm64_ops(b->stream, reinterpret_cast<const ttk::ChainOp* const*>(p), k, L.gx));
-    } else {
-      const tt_stream* s = b->members[L.rep];
-      const int ks = s->kstar;
-      ttk::PassLaunch bl{reinterpret_cast<const ttk::PassDesc*>(p), k, (unsigned)L.gx, L.grx};
-      const int64_t P = s->Pk[ks], J = s->Jk[ks];
-      const int r = (int)s->r[ks];
-      if (L.kind == kBlPass1) {
-        if (s->compute == TT_BF16)
-          TT_HIP(ttk::pass1_bf16(b->stream, nullptr, dtype, s->p1b, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
-        else
-          TT_HIP(ttk::pass1(b->stream, nullptr, dtype, s->p1, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
-      } else {
-        if (s->compute == TT_BF16)
-          TT_HIP(ttk::pass2_bf16(b->stream, nullptr, dtype, s->p2b, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
-        else
-          TT_HIP(ttk::pass2(b->stream, nullptr, dtype, P, J, r, nullptr, nullptr, nullptr, &bl));
-      }
-    }
-  }
   for (tt_stream* s : b->members) {
     s->cur ^= 1;
     s->pushes++;
@@ -842,6 +885,16 @@ tt_status tt_batch_synchronize(tt_batch* b, int32_t* rejected) {
     s->rejected_seen = rej;
   }
   return any ? fail(TT_ERR_NONFINITE, "a slice contained NaN/Inf; its stream's update was discarded") : TT_OK;
+}
+
+tt_status tt_batch_use_graph(tt_batch* b, int32_t enable) {
+  if (!batch_valid(b)) return fail(TT_ERR_INVALID_ARG, "invalid batch");
+  if (enable && b->stream == nullptr)
+    return fail(TT_ERR_UNSUPPORTED, "graph replay needs a batch on a non-default HIP stream");
+  TT_HIP(hipStreamSynchronize(b->stream));
+  if (!enable) batch_drop_graphs(b);
+  b->use_graph = enable != 0;
+  return TT_OK;
 }
 
 tt_status tt_batch_info(const tt_batch* b, int32_t* n_streams, int32_t* n_groups) {

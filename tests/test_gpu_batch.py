@@ -174,3 +174,33 @@ def test_heterogeneous_batch_is_bitwise_equal_to_solo_runs():
         ref = ttals.run_stream(xs, init[0], init[1], keep_M=True)
         assert rel(s.reconstruct(), ref.infos[-1].M, np.linalg.norm(xs[-1])) <= M_TOL
     batch.close()
+
+
+def test_graph_replay_matches_eager_batch():
+    """Pushes replayed from captured HIP graphs give bitwise the eager
+    batch's states after every push, with eager work and synchronisation
+    between the replays, across more pushes than there are descriptor slots
+    and with a change of slice dtype (which recaptures)."""
+    torch = torch_cuda()
+    from paper_2606_31061_amd import TTBatch, TTStream
+    T = 11
+    members = _mixed_members(5, 5100, T)
+    say("graph replay: 5 mixed streams, 11 pushes")
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        eager = [TTStream(st.modes, st.ranks, init=st.init(), compute=c) for st, c in members]
+        graphed = [TTStream(st.modes, st.ranks, init=st.init(), compute=c) for st, c in members]
+        be = TTBatch(eager)
+        bg = TTBatch(graphed, graph=True)
+        dev = [[to_device_slice(torch, X.astype(np.float32)) for X in st.frames(1, T)] for st, _ in members]
+        for t in range(T):
+            xs = [d[t] if t != 7 else d[t].to(torch.float64) for d in dev]
+            be.push(xs)
+            bg.push(xs)
+            assert be.synchronize() == [0] * 5 and bg.synchronize() == [0] * 5
+            for a, b in zip(eager, graphed):
+                assert _states_equal(a, b), t
+            # eager work on the same stream between replays
+            _ = (dev[0][t] * 2.0).sum().item()
+        be.close()
+        bg.close()

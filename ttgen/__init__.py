@@ -16,6 +16,7 @@ from .streams import (  # noqa: F401
     config_c2,
     config_c3,
     config_c4_specs,
+    config_c4_streams,
     init_cores,
     flatten_cores,
     exact_tt_stream,

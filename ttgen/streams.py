@@ -31,16 +31,18 @@ def tt_full(cores: Sequence[np.ndarray], h: np.ndarray | None = None) -> np.ndar
     generators to synthesise slices; the result has shape (I_1, ..., I_m).
     """
     modes = [c.shape[1] for c in cores]
+    cores = list(cores)
+    if h is not None:  # close the last bond first: the last core becomes (r, I_m, 1)
+        c = cores[-1]
+        cores[-1] = (c.reshape(-1, c.shape[2], order="F") @ np.asarray(h, dtype=np.float64)).reshape(
+            c.shape[0], c.shape[1], 1, order="F")
     acc = np.ones((1, 1))  # (prod I so far) x r
     for c in cores:
         r0, n, r1 = c.shape
-        acc = (acc @ c.reshape(r0, n * r1, order="F")).reshape(-1, r1, order="F")
-    if h is None:
-        assert acc.shape[1] == 1
-        vec = acc[:, 0]
-    else:
-        vec = acc @ np.asarray(h, dtype=acc.dtype)
-    return vec.reshape(modes, order="F")
+        # Fortran-ordered product, so the reshape below is a view, not a copy
+        acc = np.asfortranarray(acc @ c.reshape(r0, n * r1, order="F")).reshape(-1, r1, order="F")
+    assert acc.shape[1] == 1
+    return acc[:, 0].reshape(modes, order="F")
 
 
 def init_cores(modes: Sequence[int], ranks: Sequence[int], seed: int):
@@ -100,9 +102,19 @@ def _walk(rng, h0, T, step):
     return hs
 
 
+def _tt_sq_norm(cores, h) -> float:
+    """||TT(cores) x_last h||_F^2 by the left-to-right Gram recursion."""
+    W = np.ones((1, 1))
+    for c in cores:
+        r0, n, r1 = c.shape
+        W = sum(c[:, i, :].T @ W @ c[:, i, :] for i in range(n))
+    h = np.asarray(h, dtype=np.float64)
+    return float(h @ W @ h)
+
+
 def exact_tt_stream(modes, true_ranks, model_ranks, T, data_seed, init_seed,
                     sigma=0.0, walk_step=0.05, dtype=np.float64, decay=None,
-                    name="exact_tt"):
+                    name="exact_tt", noise_rel=None):
     """Exact TT-rank stream: X_t = TT(C_1..C_m) x_last h_t + sigma * noise.
 
     C_k are i.i.d. N(0,1) of shape (q_{k-1}, I_k, q_k) with q = true_ranks;
@@ -119,6 +131,8 @@ def exact_tt_stream(modes, true_ranks, model_ranks, T, data_seed, init_seed,
         cores.append(c)
     hs = _walk(rng, rng.standard_normal(q[-1]), T, walk_step)
     noise_seed = int(rng.integers(0, 2**62))
+    if noise_rel is not None:  # noise_rel times the RMS of the first slice's signal
+        sigma = noise_rel * np.sqrt(_tt_sq_norm(cores, hs[1]) / float(np.prod(modes)))
 
     def frame(t):
         x = tt_full(cores, hs[t])
@@ -260,4 +274,28 @@ def config_c4_specs(seed: int = 1004, n_streams: int = 64):
         modes = tuple(int(v) for v in rng.integers(16, 257, order - 1))
         rank = int(rng.choice([4, 8, 16, 32]))
         specs.append({"stream": s, "modes": modes, "rank": rank})
+    return specs
+
+
+def config_c4_streams(n_streams: int = 64, seed: int = 1004, T: int = 300, max_elems: int = 1 << 22,
+                      clamp=None, noise_rel: float = 1e-2) -> List[StreamSpec]:
+    """The batched workload: streams of order 3-5 (slices of order 2-4), each
+    slice mode U{16..256}, one rank drawn from {4, 8, 16, 32} per stream and
+    clamped to feasibility by `clamp(modes, ranks)`, low TT-rank plus Gaussian
+    noise of noise_rel times the signal's RMS.  Shapes whose slice exceeds
+    max_elems entries are drawn again, so a round of slices fits a bounded
+    amount of device memory."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    specs: List[StreamSpec] = []
+    while len(specs) < n_streams:
+        order = int(rng.integers(3, 6))
+        modes = tuple(int(v) for v in rng.integers(16, 257, order - 1))
+        rank = int(rng.choice([4, 8, 16, 32]))
+        if int(np.prod(modes)) > max_elems:
+            continue
+        ranks = tuple(int(v) for v in (clamp(modes, [rank] * len(modes)) if clamp else [rank] * len(modes)))
+        q = len(specs)
+        ds, is_ = seed * 1000 + 2 * q, seed * 1000 + 2 * q + 1
+        specs.append(exact_tt_stream(modes, ranks, ranks, T, ds, is_, noise_rel=noise_rel,
+                                     dtype=np.float32, name=f"c4_{q}_order{order}"))
     return specs
