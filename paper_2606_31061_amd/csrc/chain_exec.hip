@@ -99,7 +99,7 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // Workgroup sum (fixed order: reproducible); every thread gets the total.
-__device__ double block_sum(double v, double* red) {
+__device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
@@ -111,7 +111,7 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
-__device__ double block_max(double v, double* red) {
+__device__ __forceinline__ double block_max(double v, double* red) {
   v = wave_max(v);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   __syncthreads();
@@ -242,7 +242,7 @@ __device__ __forceinline__ void mma_dispatch(const View& A, const View& B, const
 // every output element of the i < M, j < N range.  Ends with a barrier.
 // Only for plans without k split (used for small outputs in LDS).
 template <class Store>
-__device__ void finish_direct(const Plan& p, int M, int N, const v4d* acc, Store store) {
+__device__ __forceinline__ void finish_direct(const Plan& p, int M, int N, const v4d* acc, Store store) {
   const int lane = tix() & 63;
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
@@ -269,7 +269,7 @@ __device__ void finish_direct(const Plan& p, int M, int N, const v4d* acc, Store
 // adding the k groups in order, so that consecutive threads store to
 // consecutive addresses.  Ends with a barrier.
 template <class Store>
-__device__ void finish_lds(const Plan& p, int M, int N, const v4d* acc, double* buf, bool ifast, Store store) {
+__device__ __forceinline__ void finish_lds(const Plan& p, int M, int N, const v4d* acc, double* buf, bool ifast, Store store) {
   const int lane = tix() & 63;
   if (p.ks == 1) {
 #pragma unroll
@@ -316,7 +316,7 @@ __device__ void finish_lds(const Plan& p, int M, int N, const v4d* acc, double* 
 // C = A B with both operands already in LDS (zero-padded views), nks
 // k-steps, at most 64 output blocks; no k split.  Ends with a barrier.
 template <class Store>
-__device__ void gemm_lds(int M, int N, int nks, const View& A, const View& B, Store store) {
+__device__ __forceinline__ void gemm_lds(int M, int N, int nks, const View& A, const View& B, Store store) {
   const int w = tix() >> 6;
   const int nbm = (M + 15) >> 4, nbn = (N + 15) >> 4;
   const Plan p = wave_plan(nbm, nbm * nbn, nks, w, false);
@@ -344,7 +344,7 @@ struct Gemm {
 // into LDS at dst[i * drs + j * dcs], zero outside i < r_valid, j < c_valid.
 // The walk follows the smaller source stride so that the loads coalesce,
 // with eight loads in flight per thread.
-__device__ void stage(int dst, int drs, int dcs, int rows, int cols, const double* src, int64_t rs, int64_t cs,
+__device__ __forceinline__ void stage(int dst, int drs, int dcs, int rows, int cols, const double* src, int64_t rs, int64_t cs,
                       int r_valid, int c_valid) {
   constexpr int U = 8;  // loads in flight per thread
   const int total = rows * cols;
@@ -380,7 +380,7 @@ __device__ void stage(int dst, int drs, int dcs, int rows, int cols, const doubl
 // C = A B from global operands.  The output is cut into tiles of at most
 // 64 blocks; for each tile the needed rows of A and columns of B go through
 // LDS one k-chunk at a time.
-__device__ void wg_gemm(const Gemm& g) {
+__device__ __forceinline__ void wg_gemm(const Gemm& g) {
   const int M = (int)g.M, N = (int)g.N, K = (int)g.K;
   if (M <= 0 || N <= 0) {
     __syncthreads();
@@ -540,7 +540,7 @@ struct Qr {
 // have been built (the rank is then exhausted: without pivoting the
 // independent columns may be anywhere, so this counts reflectors, not
 // columns).
-__device__ void hh_factor(double* A, int m, int n, int lda, double thr, int rho, bool need_r, double* tau,
+__device__ __forceinline__ void hh_factor(double* A, int m, int n, int lda, double thr, int rho, bool need_r, double* tau,
                           double* red) {
   const int tid = tix(), lane = tid & 63, wid = tid >> 6;
   int built = 0;
@@ -597,7 +597,7 @@ __device__ void hh_factor(double* A, int m, int n, int lda, double thr, int rho,
 // (backward accumulation) and flips column j when sgn[j] < 0.  Columns with
 // the identity reflector (tau = 0) hold no reflector data, so they all become
 // unit vectors in one pass; each proper reflector then costs two barriers.
-__device__ void hh_form_q(double* A, int m, int n, int lda, const double* tau, const double* sgn) {
+__device__ __forceinline__ void hh_form_q(double* A, int m, int n, int lda, const double* tau, const double* sgn) {
   const int tid = tix(), lane = tid & 63, wid = tid >> 6;
   for (int j = 0; j < n; ++j)
     if (tau[j] == 0.0) {
@@ -639,7 +639,7 @@ __device__ void hh_form_q(double* A, int m, int n, int lda, const double* tau, c
 
 // Householder QR of q.M, already copied into A (column-major, leading
 // dimension lda; LDS or the scratch buffer).
-__device__ void householder_qr(const Qr& q, double* A, int lda) {
+__device__ __forceinline__ void householder_qr(const Qr& q, double* A, int lda) {
   double* tau = s_lds + kLdsTau;
   double* sgn = s_lds + kLdsSgn;
   double* red = s_lds + kLdsRed;
@@ -711,7 +711,7 @@ __device__ __forceinline__ void stripe_gram(const double (&f)[8][2], bool live, 
 // block index) feed Q = M R^-1.  Only the 32 x 32 Gram matrices and
 // triangular factors go through LDS, plus one transposition of Q1.  Returns
 // false, with nothing written, when a pivot test fails.
-__device__ bool cholqr2_reg(const Qr& q) {
+__device__ __forceinline__ bool cholqr2_reg(const Qr& q) {
   const int tid = tix(), lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int m = q.m, n = q.n;
@@ -859,9 +859,217 @@ __device__ bool cholqr2_reg(const Qr& q) {
   return true;
 }
 
-__device__ void wg_qr(const Qr& q) {
+// Gram contributions of one 32-row stripe held as row fragments (see
+// stripe_gram), added to the wave's accumulators.
+__device__ __forceinline__ void gram_acc(const double (&f)[8][2], v4d& g00, v4d& g10, v4d& g11) {
+#pragma unroll
+  for (int s = 0; s < 8; ++s) {
+    g00 = __builtin_amdgcn_mfma_f64_16x16x4f64(f[s][0], f[s][0], g00, 0, 0, 0);
+    g10 = __builtin_amdgcn_mfma_f64_16x16x4f64(f[s][1], f[s][0], g10, 0, 0, 0);
+    g11 = __builtin_amdgcn_mfma_f64_16x16x4f64(f[s][1], f[s][1], g11, 0, 0, 0);
+  }
+}
+
+// The waves' Gram accumulators added in wave order into W (32 x 32, mirrored).
+__device__ __forceinline__ void gram_reduce(const v4d& g00, const v4d& g10, const v4d& g11, double* part,
+                                            double* W) {
+  const int tid = tix(), lane = tid & 63, w = tid >> 6;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    part[(3 * w + 0) * 256 + 64 * v + lane] = g00[v];
+    part[(3 * w + 1) * 256 + 64 * v + lane] = g10[v];
+    part[(3 * w + 2) * 256 + 64 * v + lane] = g11[v];
+  }
+  __syncthreads();
+  if (tid < 768) {
+    const int blk = tid >> 8, e = tid & 255, v = e >> 6, l = e & 63;
+    const int bi = blk == 0 ? 0 : 1, bj = blk == 2 ? 1 : 0;
+    double sum = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < kCW; ++ww) sum += part[(3 * ww + blk) * 256 + e];
+    const int i = 16 * bi + 4 * v + (l >> 4), j = 16 * bj + (l & 15);
+    W[i + 32 * j] = sum;
+    if (bi != bj) W[j + 32 * i] = sum;
+  }
+  __syncthreads();
+}
+
+// Product of a 32-row stripe (column fragments g: g[t][kc] is the element
+// (16 t + l % 16, 4 kc + l / 16)) with the upper-triangular Ri (LDS, leading
+// dimension 33); result in row-fragment order (see cholqr2_reg).
+__device__ __forceinline__ void stripe_times_upper(const double (&g)[2][8], const double* Ri, double (&f)[8][2]) {
+  const int lane = tix() & 63, li = lane & 15, lk = lane >> 4;
+  v4d acc[2][2];
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) acc[t][cb] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kc = 0; kc < 8; ++kc) {
+    const double b1 = Ri[(4 * kc + lk) + 33 * (16 + li)];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[t][kc], b1, acc[t][1], 0, 0, 0);
+    if (kc < 4) {
+      const double b0 = Ri[(4 * kc + lk) + 33 * li];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[t][kc], b0, acc[t][0], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) f[4 * t + v][cb] = acc[t][cb][v];
+}
+
+// CholeskyQR2 of a tall m x n matrix (m > 512, n <= 32), streamed in
+// 512-row stripes (wave w takes rows 32 w .. 32 w + 31 of each stripe):
+//   A: W = M^T M,                   R1 = chol(W), Ri = R1^-1
+//   B: Q1 = M Ri into aux,          W = Q1^T Q1, R2 = chol(W) (first order
+//                                   when W is within kFirstOrder of I)
+//   C: Q = Q1 R2^-1,                R = R2 R1.
+// Q1 goes to the op's scratch, so M (which Q may alias) is intact until
+// pass C; returns false, with Q and R untouched, when a pivot test fails.
+__device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
+  const int tid = tix(), lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int m = q.m, n = q.n;
+  const int nst = (m + kQrRows - 1) / kQrRows;
+  double* part = s_lds + kLdsMs;
+  double* W = s_lds + kLdsW;
+  double* R1 = s_lds + kLdsR1;
+  double* Ri = s_lds + kLdsRi;
+  double* rowbuf = s_lds + kLdsRow;
+  double* red = s_lds + kLdsRed;
+  int* flag = reinterpret_cast<int*>(s_lds + kLdsFlag);
+  double* Q1 = q.aux;  // m x n column-major
+
+  auto load_rows = [&](const double* A, int64_t ars, int64_t acs, int st, double (&f)[8][2]) {
+    const int r0 = kQrRows * st + 32 * w;
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        const int row = r0 + 4 * s + lk, col = 16 * cb + li;
+        f[s][cb] = (row < m && col < n) ? A[row * ars + col * acs] : 0.0;
+      }
+  };
+  auto load_cols = [&](const double* A, int64_t ars, int64_t acs, int st, double (&g)[2][8]) {
+    const int r0 = kQrRows * st + 32 * w;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int kc = 0; kc < 8; ++kc) {
+        const int row = r0 + 16 * t + li, col = 4 * kc + lk;
+        g[t][kc] = (row < m && col < n) ? A[row * ars + col * acs] : 0.0;
+      }
+  };
+  auto pad_identity = [&]() {
+    const int i = tid & 31, j = tid >> 5;
+    if (i >= n || j >= n) W[i + 32 * j] = (i == j) ? 1.0 : 0.0;
+  };
+
+  // pass A
+  {
+    v4d g00 = {0.0, 0.0, 0.0, 0.0}, g10 = g00, g11 = g00;
+    double fa[8][2];
+#pragma unroll 1
+    for (int st = 0; st < nst; ++st) {
+      load_rows(q.M, q.mrs, q.mcs, st, fa);
+      gram_acc(fa, g00, g10, g11);
+    }
+    __syncthreads();
+    gram_reduce(g00, g10, g11, part, W);
+  }
+  pad_identity();
+  __syncthreads();
+  double fro2 = 0.0;
+  for (int i = 0; i < n; ++i) fro2 += W[i * 33];
+  if (tid < 64) {
+    const bool ok = chol_inv32<1>(W, R1, Ri, rowbuf, kCholRel * kCholRel * fro2, n);
+    if (tid == 0) flag[0] = ok ? 1 : 0;
+  }
+  __syncthreads();
+  if (!flag[0]) return false;
+
+  // pass B
+  {
+    v4d h00 = {0.0, 0.0, 0.0, 0.0}, h10 = h00, h11 = h00;
+    double ga[2][8], f[8][2];
+    auto finish = [&](const double (&g)[2][8], int st) {
+      stripe_times_upper(g, Ri, f);
+      gram_acc(f, h00, h10, h11);
+      const int r0 = kQrRows * st + 32 * w;
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          const int row = r0 + 4 * s + lk, col = 16 * cb + li;
+          if (row < m && col < n) Q1[row + (int64_t)m * col] = f[s][cb];
+        }
+    };
+#pragma unroll 1
+    for (int st = 0; st < nst; ++st) {
+      load_cols(q.M, q.mrs, q.mcs, st, ga);
+      finish(ga, st);
+    }
+    __syncthreads();  // Ri is read above and rewritten below; Q1 complete
+    gram_reduce(h00, h10, h11, part, W);
+  }
+  {
+    const int i = tid & 31, j = tid >> 5;
+    const double e = (i < n && j < n) ? W[i + 32 * j] - (i == j ? 1.0 : 0.0) : 0.0;
+    const double emax = block_max(fabs(e), red);
+    if (emax <= kFirstOrder) {
+      const double u = (i < j) ? e : (i == j ? 0.5 * e : 0.0);
+      W[i + 32 * j] = (i == j ? 1.0 : 0.0) + u;
+      Ri[i + 33 * j] = (i == j ? 1.0 : 0.0) - u;
+      __syncthreads();
+    } else {
+      pad_identity();
+      __syncthreads();
+      if (tid < 64) {
+        const bool ok = chol_inv32<2>(W, W, Ri, rowbuf, 0.25, n);
+        if (tid == 0) flag[0] = ok ? 1 : 0;
+      }
+      __syncthreads();
+      if (!flag[0]) return false;
+    }
+  }
+
+  // pass C
+  {
+    double ga[2][8], f[8][2];
+    auto finish = [&](const double (&g)[2][8], int st) {
+      stripe_times_upper(g, Ri, f);
+      const int r0 = kQrRows * st + 32 * w;
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          const int row = r0 + 4 * s + lk, col = 16 * cb + li;
+          if (row < m && col < n) q.Q[row * q.qrs + col * q.qcs] = f[s][cb];
+        }
+    };
+#pragma unroll 1
+    for (int st = 0; st < nst; ++st) {
+      load_cols(Q1, 1, m, st, ga);
+      finish(ga, st);
+    }
+  }
+  if (q.R) {
+    const View R2v{kLdsW, 1, 32}, R1v{kLdsR1, 1, 32};
+    gemm_lds(n, n, 8, R2v, R1v, [&](int ii, int jj, double v) { q.R[ii + n * jj] = v; });
+  }
+  __syncthreads();
+  return true;
+}
+
+__device__ __forceinline__ void wg_qr(const Qr& q) {
   const int m = q.m, n = q.n;
   if (q.rho >= n && m <= kQrRows && n <= 32 && cholqr2_reg(q)) return;
+  if (q.rho >= n && m > kQrRows && n <= 32 && q.aux && cholqr2_tall(q)) return;
   if (m <= kQrRows && n <= 32) {
     // Householder in LDS
     const int mp = round16(m);

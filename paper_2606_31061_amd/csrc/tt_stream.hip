@@ -39,9 +39,13 @@ namespace {
 constexpr uint64_t kMagic = 0x54545354524d3031ULL;  // "TTSTRM01"
 constexpr uint64_t kDead = 0xdeadbeefdeadbeefULL;
 constexpr double kQrTol = 64.0 * 2.220446049250313e-16;
-// A contraction of at least this many multiply-adds is launched over the whole
+// A contraction of at least kWideFma multiply-adds, or a deep one (depth at
+// least kWideDepth and kWideDeepFma multiply-adds: a long dot product per
+// output, bound by one workgroup's load latency), is launched over the whole
 // GPU instead of being run by the chain workgroup.
 constexpr double kWideFma = 1.0e6;
+constexpr int64_t kWideDepth = 2048;
+constexpr double kWideDeepFma = 6.5e4;
 
 enum StepKind { kStepChain = 0, kStepWide = 1, kStepPass1 = 2, kStepPass2 = 3 };
 struct Step {
@@ -271,7 +275,8 @@ void plan_gemm(UpdatePlan& p, int64_t M, int64_t N, int64_t K, const double* A, 
   op.crs = crs;
   op.ccs = ccs;
   op.c32 = C32;
-  if ((double)M * (double)N * (double)K >= kWideFma) {
+  const double fma = (double)M * (double)N * (double)K;
+  if (fma >= kWideFma || (K >= kWideDepth && fma >= kWideDeepFma)) {
     p.ops.push_back(op);
     p.steps.push_back({kStepWide, (int)p.ops.size() - 1, 1});
   } else {

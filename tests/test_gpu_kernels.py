@@ -99,7 +99,8 @@ def test_passes_flag_nonfinite_slices():
 
 
 QR_CASES = [(8, 8, None), (72, 32, None), (480, 32, None), (512, 32, None), (96, 32, 1), (480, 32, 3),
-            (32, 32, 1), (5120, 16, None), (5120, 16, 3), (1, 1, None), (300, 7, None), (16, 16, 0)]
+            (32, 32, 1), (5120, 16, None), (5120, 16, 3), (1, 1, None), (300, 7, None), (16, 16, 0),
+            (513, 32, None), (7328, 32, None), (2049, 33, None), (4096, 32, 5), (1000, 1, None)]
 
 
 @pytest.mark.parametrize("m,n,rank", QR_CASES)
@@ -136,3 +137,27 @@ def test_qr_matches_oracle(m, n, rank):
         k = max(rank, 0)
         if k:
             assert np.linalg.norm(Q[:, :k] @ Q[:, :k].T @ M - M) <= 1e-11 * nrm
+
+
+@pytest.mark.parametrize("m,n,cond", [(3000, 32, 1e3), (3000, 32, 1e10), (700, 20, 1e10)])
+def test_tall_qr_in_place_and_ill_conditioned(m, n, cond):
+    """Tall matrices, Q overwriting M: a well-conditioned one takes the
+    streamed CholeskyQR2, an ill-conditioned one fails its pivot test and
+    falls back to Householder; both give an orthonormal Q and M = Q R."""
+    torch = torch_cuda()
+    from paper_2606_31061_amd import binding
+    say(f"tall qr in place m={m} n={n} cond={cond:g}")
+    rng = _rng(m + n)
+    U, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    V, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    M = (U * np.logspace(0, -np.log10(cond), n)) @ V.T
+    Md = torch.from_numpy(M.T.copy()).cuda()
+    Rd = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    wk = torch.empty(m * n, dtype=torch.float64, device="cuda")
+    assert binding.tt_kernel_qr(Md, Md, Rd, wk) == 0
+    torch.cuda.synchronize()
+    Q = Md.cpu().numpy().T
+    R = Rd.cpu().numpy().T
+    assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= 1e-12
+    assert np.linalg.norm(Q @ R - M) <= 1e-12 * np.linalg.norm(M)
+    assert np.all(np.diag(R) >= 0)
