@@ -155,6 +155,79 @@ def batched_section(torch, n_streams, rounds, warmup, compute, tune):
     return out
 
 
+def serving_section(torch, spec, n_streams, rate_hz, duration, compute, tune, max_wave, lanes, budget_slices):
+    """Serving: n_streams streams of the config-3 shape with Poisson arrivals at
+    rate_hz each (seeded exponential gaps) for `duration` seconds, served with
+    continuous batching (TTServer) under an HBM budget of budget_slices slices;
+    then the same arrival trace for a quarter of the time through one-at-a-time
+    single-stream serving.  Slices come from a pool of resident frames."""
+    from paper_2606_31061_amd import TTServer, TTStream
+    from ttgen import init_cores
+    pool_n = 8
+    frames = []
+    for t in range(1, pool_n + 1):
+        x = torch.from_numpy(np.ascontiguousarray(spec.frame(t).reshape(-1, order="F"))).cuda()
+        frames.append(x.to(torch.bfloat16) if compute == "bf16" else x)
+    torch.cuda.synchronize()
+    slice_bytes = frames[0].numel() * frames[0].element_size()
+    rng = np.random.Generator(np.random.PCG64(1005))
+
+    def trace(dur):
+        arr = []
+        for q in range(n_streams):
+            t = rng.exponential(1.0 / rate_hz)
+            while t < dur:
+                arr.append((t, q))
+                t += rng.exponential(1.0 / rate_hz)
+        arr.sort()
+        return arr
+
+    def run(arrivals, mw, ln, budget):
+        streams = [TTStream(spec.modes, spec.ranks, init=init_cores(spec.modes, spec.ranks, 5000 + q),
+                            compute=compute, autotune=tune) for q in range(n_streams)]
+        sv = TTServer(max_wave=mw, lanes=ln, hbm_budget=budget)
+        ids = [sv.add(st) for st in streams]
+        for q in range(n_streams):  # warm-up: one update per stream
+            sv.submit(ids[q], frames[q % pool_n], tag=1 << 40)
+        sv.drain()
+        sv.take()
+        w0 = sv.stats()["waves"]
+        t0 = time.perf_counter()
+        for k, (ta, q) in enumerate(arrivals):
+            while time.perf_counter() - t0 < ta:
+                sv.poll()
+            sv.submit(ids[q], frames[k % pool_n], tag=k)
+            sv.poll()
+        sv.drain()
+        el = time.perf_counter() - t0
+        res = sv.take()
+        st = sv.stats()
+        sv.close()
+        for x in streams:
+            x.close()
+        lat = np.array([r[1] for r in res]) * 1e3
+        waves = st["waves"] - w0
+        return {"requests": len(res), "elapsed_s": el, "updates_per_s": len(res) / el,
+                "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99))},
+                "waves": waves, "mean_wave": len(res) / max(waves, 1), "peak_admitted_bytes": st["peak_bytes"]}
+
+    budget = budget_slices * slice_bytes
+    arr = trace(duration)
+    log(f"serving: {n_streams} streams x {rate_hz} Hz for {duration} s = {len(arr)} requests; "
+        f"max_wave {max_wave}, lanes {lanes}, HBM budget {budget / 1e6:.0f} MB ({budget_slices} slices)")
+    cont = run(arr, max_wave, lanes, budget)
+    log(f"continuous batching: {cont['updates_per_s']:.0f} updates/s, p50 {cont['latency_ms']['p50']:.2f} ms "
+        f"p99 {cont['latency_ms']['p99']:.2f} ms, mean wave {cont['mean_wave']:.1f}")
+    short = [a for a in arr if a[0] < duration / 4]
+    single = run(short, 1, 1, 0)
+    log(f"single-stream serving ({len(short)} requests): {single['updates_per_s']:.0f} updates/s, "
+        f"p50 {single['latency_ms']['p50']:.2f} ms p99 {single['latency_ms']['p99']:.2f} ms")
+    return {"workload": f"c5_{n_streams}_streams_c3_shape_poisson_{rate_hz:g}hz",
+            "offered_updates_per_s": n_streams * rate_hz, "duration_s": duration,
+            "max_wave": max_wave, "lanes": lanes, "hbm_budget_bytes": budget,
+            "continuous_batching": cont, "single_stream": single}
+
+
 def cpu_baseline(spec, seconds_budget: float):
     """The FP64 oracle as it stands, timed on the host on a bounded sample."""
     from oracle import ttals
@@ -193,6 +266,10 @@ def main():
     ap.add_argument("--batch", type=int, default=64,
                     help="streams in the batched measurement (0: skip it)")
     ap.add_argument("--batch-rounds", type=int, default=20)
+    ap.add_argument("--serve-streams", type=int, default=256,
+                    help="streams in the serving measurement (0: skip it)")
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--serve-rate", type=float, default=30.0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default pass launch shapes instead of tuning them for the workload")
     ap.add_argument("--profile-ops", action="store_true",
@@ -273,6 +350,11 @@ def main():
     if args.batch > 0:
         batched = batched_section(torch, args.batch, args.batch_rounds, 3, args.compute, tune)
 
+    serving = None
+    if args.serve_streams > 0:
+        serving = serving_section(torch, spec, args.serve_streams, args.serve_rate, args.serve_seconds, args.compute,
+                                  tune, max_wave=32, lanes=2, budget_slices=24)
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
@@ -309,6 +391,7 @@ def main():
         "slice_kernels": {"pass1_us": kt["pass1"] * 1e3, "pass1_gbs": gbs1, "pass1_bytes": b1,
                           "pass2_us": kt["pass2"] * 1e3, "pass2_gbs": gbs2, "pass2_bytes": b2},
         "batched": batched,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -1,14 +1,15 @@
 """MI355X (gfx950) Online TT-ALS: per-slice streaming Tensor-Train updates.
 
 The product is the HIP shared library lib/libttstream.so with the C ABI in
-include/tt_stream.h (batches of streams in include/tt_batch.h, the kernel
-entry points in include/tt_kernels.h);
+include/tt_stream.h (batches of streams in include/tt_batch.h, serving in
+include/tt_server.h, the kernel entry points in include/tt_kernels.h);
 this package only builds it (build.py) and binds it (binding.py).
 """
 
 from .binding import (  # noqa: F401
     TTStream,
     TTBatch,
+    TTServer,
     TTError,
     load_library,
     tt_clamp_ranks,

@@ -64,6 +64,10 @@ class tt_stream_config(Structure):
 _lib = None
 
 
+class tt_server_config(Structure):
+    _fields_ = [("max_wave", c_int32), ("lanes", c_int32), ("hbm_budget", c_uint64)]
+
+
 def load_library(path: str = LIB_PATH):
     """Load libttstream.so (raises if it is missing: build it first)."""
     global _lib
@@ -96,6 +100,16 @@ def load_library(path: str = LIB_PATH):
         "tt_batch_synchronize": (c_int, [sv, POINTER(c_int32)]),
         "tt_batch_info": (c_int, [sv, POINTER(c_int32), POINTER(c_int32)]),
         "tt_batch_use_graph": (c_int, [sv, c_int32]),
+        "tt_server_create": (c_int, [POINTER(tt_server_config), POINTER(c_void_p)]),
+        "tt_server_add": (c_int, [sv, sv, POINTER(c_int32)]),
+        "tt_server_submit": (c_int, [sv, c_int32, sv, c_int, c_uint64]),
+        "tt_server_poll": (c_int, [sv, POINTER(c_int32)]),
+        "tt_server_drain": (c_int, [sv]),
+        "tt_server_take": (c_int, [sv, c_int64, POINTER(c_uint64), POINTER(c_double), POINTER(c_int32),
+                                   POINTER(c_int64)]),
+        "tt_server_stats": (c_int, [sv, POINTER(c_int64), POINTER(c_int64), POINTER(c_int64), POINTER(c_int64),
+                                    POINTER(c_uint64)]),
+        "tt_server_destroy": (c_int, [sv]),
         "tt_batch_destroy": (c_int, [sv]),
         "tt_kernel_pass1": (c_int, [sv, c_int, c_int64, c_int64, c_int32, sv, sv, sv, sv, sv]),
         "tt_kernel_pass1_workspace": (c_size_t, [c_int64, c_int64, c_int32]),
@@ -441,6 +455,70 @@ class TTBatch:
     def close(self) -> None:
         if self._h is not None and self._h.value:
             _check(self._lib.tt_batch_destroy(self._h), "tt_batch_destroy")
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class TTServer:
+    """Continuous-batching server over registered streams (include/tt_server.h).
+
+    Requests are submitted as they arrive; poll() retires finished waves,
+    admits queued requests (per-stream order, wave size, HBM budget) and
+    launches the next wave on a free lane.  Registered streams must not be
+    pushed directly."""
+
+    def __init__(self, max_wave: int = 32, lanes: int = 2, hbm_budget: int = 0):
+        self._lib = load_library()
+        cfg = tt_server_config(max_wave, lanes, hbm_budget)
+        self._h = c_void_p()
+        _check(self._lib.tt_server_create(byref(cfg), byref(self._h)), "tt_server_create")
+        self.streams = []
+
+    def add(self, stream) -> int:
+        i = c_int32()
+        _check(self._lib.tt_server_add(self._h, stream._h, byref(i)), "tt_server_add")
+        self.streams.append(stream)
+        return i.value
+
+    def submit(self, sid: int, x, tag: int) -> None:
+        if not x.is_cuda or not x.is_contiguous() or x.numel() != self.streams[sid].n:
+            raise ValueError("device slices must be contiguous CUDA tensors with N elements")
+        _check(self._lib.tt_server_submit(self._h, sid, c_void_p(x.data_ptr()), _dtype_code_torch(x), tag),
+               "tt_server_submit")
+
+    def poll(self) -> int:
+        d = c_int32()
+        _check(self._lib.tt_server_poll(self._h, byref(d)), "tt_server_poll")
+        return d.value
+
+    def drain(self) -> None:
+        _check(self._lib.tt_server_drain(self._h), "tt_server_drain")
+
+    def take(self, cap: int = 1 << 16):
+        """[(tag, latency_s, rejected)] of the requests retired since the last call."""
+        tags = (c_uint64 * cap)()
+        lat = (c_double * cap)()
+        rej = (c_int32 * cap)()
+        n = c_int64()
+        _check(self._lib.tt_server_take(self._h, cap, tags, lat, rej, byref(n)), "tt_server_take")
+        return [(int(tags[i]), float(lat[i]), int(rej[i])) for i in range(n.value)]
+
+    def stats(self):
+        w, r, q, f = c_int64(), c_int64(), c_int64(), c_int64()
+        pb = c_uint64()
+        _check(self._lib.tt_server_stats(self._h, byref(w), byref(r), byref(q), byref(f), byref(pb)),
+               "tt_server_stats")
+        return {"waves": w.value, "retired": r.value, "queued": q.value, "in_flight": f.value,
+                "peak_bytes": pb.value}
+
+    def close(self) -> None:
+        if self._h is not None and self._h.value:
+            _check(self._lib.tt_server_destroy(self._h), "tt_server_destroy")
             self._h = None
 
     def __del__(self):

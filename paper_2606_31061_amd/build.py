@@ -17,7 +17,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "lib")
 LIBNAME = "libttstream.so"
-SOURCES = ["tt_stream.hip", "kernels_abi.hip", "chain_kernels.hip", "chain_exec.hip", "pass_kernels.hip", "pass_bf16.hip", "autotune.hip"]
+SOURCES = ["tt_stream.hip", "kernels_abi.hip", "chain_kernels.hip", "chain_exec.hip", "pass_kernels.hip", "pass_bf16.hip", "autotune.hip", "batch.hip"]
 ARCH = os.environ.get("TT_OFFLOAD_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

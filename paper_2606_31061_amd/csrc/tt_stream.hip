@@ -18,8 +18,7 @@
 // enqueueing.  Small steps are grouped into operation lists run by one
 // workgroup (chain_exec.hip); large contractions and the passes are launches
 // of their own.  Nothing is read back to the host during a push.
-#include "tt_internal.h"
-#include "tt_batch.h"
+#include "stream_internal.h"
 
 #include <algorithm>
 #include <cmath>
@@ -34,9 +33,15 @@ namespace ttk {
 hipError_t pass_setup();
 }  // namespace ttk
 
+using ttk::Step;
+using ttk::UpdatePlan;
+using ttk::kStepChain;
+using ttk::kStepWide;
+using ttk::kStepPass1;
+using ttk::kStepPass2;
+
 namespace {
 
-constexpr uint64_t kMagic = 0x54545354524d3031ULL;  // "TTSTRM01"
 constexpr uint64_t kDead = 0xdeadbeefdeadbeefULL;
 constexpr double kQrTol = 64.0 * 2.220446049250313e-16;
 // A contraction of at least kWideFma multiply-adds, or a deep one (depth at
@@ -46,20 +51,6 @@ constexpr double kQrTol = 64.0 * 2.220446049250313e-16;
 constexpr double kWideFma = 1.0e6;
 constexpr int64_t kWideDepth = 2048;
 constexpr double kWideDeepFma = 6.5e4;
-
-enum StepKind { kStepChain = 0, kStepWide = 1, kStepPass1 = 2, kStepPass2 = 3 };
-struct Step {
-  int kind;
-  int first;
-  int count;
-};
-struct UpdatePlan {
-  std::vector<ttk::ChainOp> ops;
-  std::vector<Step> steps;
-  ttk::ChainOp* dev = nullptr;     // the ops on the device
-  ttk::ChainSeg* segs = nullptr;   // segs[i]: step i's operations (device; chain steps)
-  ttk::ChainOp** opptr = nullptr;  // opptr[i] = dev + i (device)
-};
 
 thread_local std::string g_last_error = "no error";
 
@@ -109,70 +100,10 @@ void normal_fill(std::vector<double>& v, uint64_t seed) {
 
 tt_status ttk::set_error(tt_status st, const char* msg) { return fail(st, msg); }
 
-struct tt_stream {
-  uint64_t magic = kMagic;
-  int m = 0;
-  std::vector<int64_t> I;    // I[1..m] (I[0] unused)
-  std::vector<int64_t> r;    // r[0..m], r[0] = 1
-  std::vector<int64_t> Pk;   // Pk[k] = I_1..I_k, Pk[0] = 1
-  std::vector<int64_t> Jk;   // Jk[k] = I_{k+1}..I_m, Jk[m] = 1
-  std::vector<int64_t> coff; // offset of G_k in a state buffer; coff[m+1] = offset of g
-  int64_t N = 0, cores_len = 0, state_len = 0;
-  int kstar = 1;
-  tt_dtype compute = TT_F32;
-  uint32_t flags = 0;
-  hipStream_t stream = nullptr;
-  int device = 0;
-  tt_allocator alloc{};
-  bool has_alloc = false;
-  size_t lds_limit = 65536;
-  size_t device_bytes = 0;
-  std::vector<void*> owned;
-
-  double* state[2] = {nullptr, nullptr};
-  int cur = 0;               // state[cur] is the committed state
-  UpdatePlan plan[2];        // plan[p] reads state[p], writes state[p ^ 1]
-  double* work = nullptr;
-  double* Rbuf = nullptr;
-  int64_t* trace = nullptr;  // 2 stamps per chain op (TT_FLAG_PROFILE_OPS)
-  int64_t trace_len = 0;
-  int traced_plan = -1;      // plan of the last traced push
-  int wall_khz = 100000;
-  std::vector<double*> B;    // B[k] for k = kstar..m-1
-  float* B32 = nullptr;
-  double* Z = nullptr;
-  std::vector<double*> Zk;   // Zk[k] for k = 1..kstar-1
-  std::vector<double*> A;    // A[k] for k = 3..kstar+1
-  float* A32 = nullptr;
-  double* Gt = nullptr;
-  double* Y[2] = {nullptr, nullptr};
-  double* qrwork = nullptr;
-  float* ws = nullptr;       // pass 1 workspace
-  float* ws2 = nullptr;      // pass 2 workspace (BF16 contractions only)
-  int* flag = nullptr;
-  int* rejected = nullptr;
-  int64_t* tdev = nullptr;
-  double* hist = nullptr;
-  int64_t hist_cap = 0;
-  double* recon[2] = {nullptr, nullptr};
-  void* stage = nullptr;
-  size_t stage_bytes = 0;
-  ttk::Pass1Plan p1;
-  ttk::PassBPlan p1b, p2b;   // BF16 contractions
-  int rejected_seen = 0;
-  int64_t pushes = 0;
-  hipEvent_t ev0 = nullptr, ev1 = nullptr, evcopy = nullptr;
-  hipEvent_t evpass[4] = {};  // around pass 1 and pass 2 (TT_FLAG_PROFILE_OPS)
-  bool timed = false;
-
-  double* g_of(double* st) const { return st + coff[m + 1]; }
-  double* G_of(double* st, int k) const { return st + coff[k]; }
-  double* master() const { return state[cur]; }
-};
 
 namespace {
 
-bool valid(const tt_stream* s) { return s != nullptr && s->magic == kMagic; }
+bool valid(const tt_stream* s) { return ttk::stream_valid(s); }
 
 void* dev_alloc(tt_stream* s, size_t bytes) {
   if (bytes == 0) bytes = 256;
@@ -481,443 +412,7 @@ tt_status run_plan(tt_stream* s, const void* X, tt_dtype xdt) {
 
 }  // namespace
 
-// A batch runs one update of every member with launches shared by all
-// members, whatever their shapes: the update's steps are cut at the two slice
-// passes into three phases; inside a phase each member alternates chain
-// segments and whole-GPU products, and slot w of every member runs in one
-// launch (chain segment w on one workgroup per member, then product w of the
-// members that have one).  Each pass runs as one launch per kernel template
-// shape, over the members of that shape.  Every member computes exactly what
-// it computes alone: the same operations, kernels and launch shapes.
-enum BatchLaunchKind { kBlChain = 0, kBlWide = 1, kBlPass1 = 2, kBlPass2 = 3 };
-struct BatchLaunch {
-  int kind = 0;
-  int phase = 0, slot = 0;       // chain/wide: phase and slot
-  std::vector<int> members;      // participating members (batch order)
-  size_t off = 0;                // descriptor offset in the upload
-  int64_t gx = 0;                // wide: grid.x; passes: main grid.x
-  unsigned grx = 0;              // passes: reduction grid.x
-  int rep = -1;                  // passes: a member whose plan gives the template shape
-};
-// Per member and phase: chain segments (first, count) and, between them,
-// whole-GPU product op indices (segments = products + 1).
-struct MemberPhase {
-  std::vector<std::pair<int, int>> segs;
-  std::vector<int> wides;
-};
-
-constexpr uint64_t kBatchMagic = 0x54544241544348ULL;  // "TTBATCH"
-constexpr int kBatchSlots = 8;
-
-struct tt_batch {
-  uint64_t magic = kBatchMagic;
-  hipStream_t stream = nullptr;
-  std::vector<tt_stream*> members;
-  std::vector<std::array<MemberPhase, 3>> phases;
-  std::vector<BatchLaunch> launches;
-  int n_groups = 0;              // distinct update structures (informational)
-  size_t bytes = 0;              // descriptor upload per push
-  char* dev = nullptr;
-  char* host[kBatchSlots] = {};
-  hipEvent_t done[kBatchSlots] = {};
-  bool used[kBatchSlots] = {};
-  hipGraphExec_t graph[kBatchSlots] = {};  // per slot, when graph replay is on
-  tt_dtype graph_dtype[kBatchSlots] = {};   // slice type the slot's graph was captured for
-  bool use_graph = false;
-  int next = 0;
-  std::vector<int> rejected_seen;
-};
-
-namespace {
-
-bool batch_valid(const tt_batch* b) { return b != nullptr && b->magic == kBatchMagic; }
-
-// Same update structure: shapes, split point, precision, pass plans and ops.
-bool same_structure(const tt_stream* a, const tt_stream* b) {
-  if (a->m != b->m || a->kstar != b->kstar || a->I != b->I || a->r != b->r || a->compute != b->compute) return false;
-  const auto same1 = [](const ttk::Pass1Plan& x, const ttk::Pass1Plan& y) {
-    return x.vec == y.vec && x.ntn == y.ntn && x.waves == y.waves && x.chunks == y.chunks;
-  };
-  const auto sameb = [](const ttk::PassBPlan& x, const ttk::PassBPlan& y) {
-    return x.vec == y.vec && x.ntn == y.ntn && x.waves == y.waves && x.chunks == y.chunks;
-  };
-  if (!same1(a->p1, b->p1) || !sameb(a->p1b, b->p1b) || !sameb(a->p2b, b->p2b)) return false;
-  const UpdatePlan &pa = a->plan[0], &pb = b->plan[0];
-  if (pa.ops.size() != pb.ops.size() || pa.steps.size() != pb.steps.size()) return false;
-  for (size_t i = 0; i < pa.steps.size(); ++i)
-    if (pa.steps[i].kind != pb.steps[i].kind || pa.steps[i].first != pb.steps[i].first ||
-        pa.steps[i].count != pb.steps[i].count)
-      return false;
-  for (size_t i = 0; i < pa.ops.size(); ++i) {
-    const ttk::ChainOp &x = pa.ops[i], &y = pb.ops[i];
-    if (x.type != y.type || x.m != y.m || x.n != y.n || x.k != y.k || x.rho != y.rho) return false;
-  }
-  return true;
-}
-
-// Template shape of a member's pass launch (members of one launch share it).
-std::array<int, 5> pass_key(const tt_stream* s, int pass) {
-  const int ks = s->kstar;
-  const int ntn = s->r[ks] <= 32 ? 1 : 2;
-  if (s->compute == TT_BF16) {
-    if (pass == 1) return {1, 1, s->p1b.vec, s->p1b.waves, ntn};
-    return {1, 2, ttk::pass2b_vx(s->Pk[ks]) ? 1 : 0, s->p2b.waves, ntn};
-  }
-  if (pass == 1) return {0, 1, s->p1.vec, s->p1.waves, s->p1.ntn};
-  return {0, 2, ttk::pass2_vec(s->Pk[ks]), 0, ntn};
-}
-
-void pass_grids(const tt_stream* s, int pass, int64_t* gx, unsigned* grx) {
-  const int ks = s->kstar;
-  unsigned a = 0, b = 0;
-  if (s->compute == TT_BF16) {
-    if (pass == 1) ttk::pass1b_grids(s->p1b, &a, &b);
-    else ttk::pass2b_grids(s->p2b, &a, &b);
-  } else if (pass == 1) {
-    ttk::pass1_grids(s->p1, s->Pk[ks], &a, &b);
-  } else {
-    a = ttk::pass2_grid(s->Jk[ks]);
-  }
-  *gx = a;
-  *grx = b;
-}
-
-ttk::PassDesc pass_desc(const tt_stream* s, int pass, const void* x) {
-  const int ks = s->kstar;
-  ttk::PassDesc d{};
-  d.x = x;
-  d.w = pass == 1 ? s->B32 : s->A32;
-  d.out = pass == 1 ? s->Z : s->Y[0];
-  d.ws = pass == 1 ? s->ws : s->ws2;
-  d.flag = s->flag;
-  d.P = s->Pk[ks];
-  d.J = s->Jk[ks];
-  d.r = (int32_t)s->r[ks];
-  if (s->compute == TT_BF16) {
-    const ttk::PassBPlan& pl = pass == 1 ? s->p1b : s->p2b;
-    d.tiles = pl.tiles;
-    d.chunks = pl.chunks;
-  } else {
-    d.tiles = (int32_t)((d.P + 32 * s->p1.vec - 1) / (32 * s->p1.vec));
-    d.chunks = s->p1.chunks;
-  }
-  return d;
-}
-
-// The launch sequence of a batch (its shape does not change between pushes).
-void build_schedule(tt_batch* b) {
-  const int n = (int)b->members.size();
-  b->phases.assign(n, {});
-  for (int i = 0; i < n; ++i) {
-    const UpdatePlan& P = b->members[i]->plan[0];
-    int ph = 0;
-    auto& mp = b->phases[i];
-    for (auto& x : mp) x.segs.push_back({0, 0});
-    for (const Step& st : P.steps) {
-      if (st.kind == kStepChain) {
-        mp[ph].segs.back() = {st.first, st.count};
-      } else if (st.kind == kStepWide) {
-        mp[ph].wides.push_back(st.first);
-        mp[ph].segs.push_back({0, 0});
-      } else {
-        ++ph;
-      }
-    }
-  }
-  b->launches.clear();
-  size_t off = 0;
-  auto add = [&](BatchLaunch&& L, size_t bytes) {
-    L.off = off;
-    off += (bytes + 255) & ~size_t(255);
-    b->launches.push_back(std::move(L));
-  };
-  for (int ph = 0; ph < 3; ++ph) {
-    size_t W = 0;
-    for (int i = 0; i < n; ++i) W = std::max(W, b->phases[i][ph].wides.size());
-    for (size_t w = 0; w <= W; ++w) {
-      bool any = false;
-      for (int i = 0; i < n; ++i) {
-        const auto& mp = b->phases[i][ph];
-        any = any || (w < mp.segs.size() && mp.segs[w].second > 0);
-      }
-      if (any) {
-        BatchLaunch L;
-        L.kind = kBlChain;
-        L.phase = ph;
-        L.slot = (int)w;
-        for (int i = 0; i < n; ++i) L.members.push_back(i);
-        add(std::move(L), sizeof(ttk::ChainSeg) * n);
-      }
-      if (w < W) {
-        BatchLaunch L;
-        L.kind = kBlWide;
-        L.phase = ph;
-        L.slot = (int)w;
-        for (int i = 0; i < n; ++i) {
-          const auto& mp = b->phases[i][ph];
-          if (w < mp.wides.size()) {
-            L.members.push_back(i);
-            const ttk::ChainOp& o = b->members[i]->plan[0].ops[mp.wides[w]];
-            L.gx = std::max(L.gx, ttk::gemm64_blocks(o.m, o.n, o.k));
-          }
-        }
-        const size_t k = L.members.size();
-        add(std::move(L), sizeof(ttk::ChainOp*) * k);
-      }
-    }
-    if (ph < 2) {
-      const int pass = ph + 1;
-      std::vector<std::array<int, 5>> keys;
-      std::vector<std::vector<int>> groups;
-      for (int i = 0; i < n; ++i) {
-        const auto key = pass_key(b->members[i], pass);
-        size_t g = 0;
-        while (g < keys.size() && keys[g] != key) ++g;
-        if (g == keys.size()) {
-          keys.push_back(key);
-          groups.emplace_back();
-        }
-        groups[g].push_back(i);
-      }
-      for (auto& grp : groups) {
-        BatchLaunch L;
-        L.kind = pass == 1 ? kBlPass1 : kBlPass2;
-        L.members = grp;
-        L.rep = grp[0];
-        for (int i : grp) {
-          int64_t gx;
-          unsigned grx;
-          pass_grids(b->members[i], pass, &gx, &grx);
-          L.gx = std::max(L.gx, gx);
-          L.grx = std::max(L.grx, grx);
-        }
-        const size_t k = L.members.size();
-        add(std::move(L), sizeof(ttk::PassDesc) * k);
-      }
-    }
-  }
-  b->bytes = off;
-}
-
-void batch_drop_graphs(tt_batch* b) {
-  for (hipGraphExec_t& g : b->graph) {
-    if (g) (void)hipGraphExecDestroy(g);
-    g = nullptr;
-  }
-}
-
-void batch_release(tt_batch* b) {
-  batch_drop_graphs(b);
-  if (b->dev) (void)hipFree(b->dev);
-  b->dev = nullptr;
-  for (int k = 0; k < kBatchSlots; ++k) {
-    if (b->done[k]) (void)hipEventDestroy(b->done[k]);
-    if (b->host[k]) (void)hipHostFree(b->host[k]);
-    b->done[k] = nullptr;
-    b->host[k] = nullptr;
-  }
-}
-
-// Enqueues one push on the batch's stream: the descriptor upload from host
-// slot h, then every launch.
-tt_status enqueue_push(tt_batch* b, const char* h, tt_dtype dtype) {
-  const int n = (int)b->members.size();
-  TT_HIP(hipMemcpyAsync(b->dev, h, b->bytes, hipMemcpyHostToDevice, b->stream));
-  for (const BatchLaunch& L : b->launches) {
-    char* p = b->dev + L.off;
-    const int k = (int)L.members.size();
-    if (L.kind == kBlChain) {
-      TT_HIP(ttk::chain_run(b->stream, reinterpret_cast<const ttk::ChainSeg*>(p), n));
-    } else if (L.kind == kBlWide) {
-      TT_HIP(ttk::gemm64_ops(b->stream, reinterpret_cast<const ttk::ChainOp* const*>(p), k, L.gx));
-    } else {
-      const tt_stream* s = b->members[L.rep];
-      const int ks = s->kstar;
-      ttk::PassLaunch bl{reinterpret_cast<const ttk::PassDesc*>(p), k, (unsigned)L.gx, L.grx};
-      const int64_t P = s->Pk[ks], J = s->Jk[ks];
-      const int r = (int)s->r[ks];
-      if (L.kind == kBlPass1) {
-        if (s->compute == TT_BF16)
-          TT_HIP(ttk::pass1_bf16(b->stream, nullptr, dtype, s->p1b, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
-        else
-          TT_HIP(ttk::pass1(b->stream, nullptr, dtype, s->p1, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
-      } else {
-        if (s->compute == TT_BF16)
-          TT_HIP(ttk::pass2_bf16(b->stream, nullptr, dtype, s->p2b, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
-        else
-          TT_HIP(ttk::pass2(b->stream, nullptr, dtype, P, J, r, nullptr, nullptr, nullptr, &bl));
-      }
-    }
-  }
-  return TT_OK;
-}
-
-}  // namespace
-
 extern "C" {
-
-tt_status tt_batch_create(tt_stream* const* streams, int32_t n, void* hip_stream, tt_batch** out) {
-  if (!streams || !out || n < 1) return fail(TT_ERR_INVALID_ARG, "null argument or n < 1");
-  if (n > 65535) return fail(TT_ERR_INVALID_ARG, "at most 65535 streams per batch");
-  *out = nullptr;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return fail(TT_ERR_DEVICE, "hipGetDevice failed");
-  for (int i = 0; i < n; ++i) {
-    const tt_stream* s = streams[i];
-    if (!valid(s)) return fail(TT_ERR_INVALID_ARG, "invalid stream handle");
-    if (s->device != dev) return fail(TT_ERR_INVALID_ARG, "stream lives on another device");
-    if (s->stream != static_cast<hipStream_t>(hip_stream)) return fail(TT_ERR_INVALID_ARG, "stream uses another HIP stream");
-    if (s->trace) return fail(TT_ERR_INVALID_ARG, "streams with TT_FLAG_PROFILE_OPS cannot be batched");
-    for (int j = 0; j < i; ++j)
-      if (streams[j] == s) return fail(TT_ERR_INVALID_ARG, "duplicate stream");
-  }
-  tt_batch* b = new (std::nothrow) tt_batch();
-  if (!b) return fail(TT_ERR_OOM, "host allocation failed");
-  b->stream = static_cast<hipStream_t>(hip_stream);
-  b->members.assign(streams, streams + n);
-  b->rejected_seen.resize(n);
-  std::vector<int> reps;
-  for (int i = 0; i < n; ++i) {
-    bool seen = false;
-    for (int j : reps) seen = seen || same_structure(b->members[j], b->members[i]);
-    if (!seen) reps.push_back(i);
-    b->rejected_seen[i] = b->members[i]->rejected_seen;
-  }
-  b->n_groups = (int)reps.size();
-  build_schedule(b);
-  void* d = nullptr;
-  if (hipMalloc(&d, b->bytes) != hipSuccess) {
-    delete b;
-    return fail(TT_ERR_OOM, "batch descriptor allocation failed");
-  }
-  b->dev = static_cast<char*>(d);
-  for (int q = 0; q < kBatchSlots; ++q) {
-    void* h = nullptr;
-    if (hipHostMalloc(&h, b->bytes, hipHostMallocDefault) != hipSuccess ||
-        hipEventCreateWithFlags(&b->done[q], hipEventDisableTiming) != hipSuccess) {
-      if (h) (void)hipHostFree(h);
-      batch_release(b);
-      delete b;
-      return fail(TT_ERR_OOM, "batch staging allocation failed");
-    }
-    b->host[q] = static_cast<char*>(h);
-  }
-  *out = b;
-  return TT_OK;
-}
-
-tt_status tt_batch_push(tt_batch* b, const void* const* slices, tt_dtype dtype) {
-  if (!batch_valid(b) || !slices) return fail(TT_ERR_INVALID_ARG, "invalid batch or null slices");
-  if (dtype != TT_F64 && dtype != TT_F32 && dtype != TT_BF16) return fail(TT_ERR_INVALID_ARG, "bad dtype");
-  const int n = (int)b->members.size();
-  for (int i = 0; i < n; ++i)
-    if (!slices[i]) return fail(TT_ERR_INVALID_ARG, "null slice");
-  // descriptors of this push into a free pinned slot, then one upload
-  const int q = b->next;
-  b->next = (b->next + 1) % kBatchSlots;
-  if (b->used[q]) TT_HIP(hipEventSynchronize(b->done[q]));
-  char* h = b->host[q];
-  for (const BatchLaunch& L : b->launches) {
-    char* p = h + L.off;
-    if (L.kind == kBlChain) {
-      ttk::ChainSeg* sg = reinterpret_cast<ttk::ChainSeg*>(p);
-      for (int i = 0; i < n; ++i) {
-        const tt_stream* s = b->members[i];
-        const auto& mp = b->phases[i][L.phase];
-        const auto seg = L.slot < (int)mp.segs.size() ? mp.segs[L.slot] : std::pair<int, int>{0, 0};
-        sg[i] = ttk::ChainSeg{s->plan[s->cur].dev + seg.first, seg.second, 0};
-      }
-    } else if (L.kind == kBlWide) {
-      ttk::ChainOp** op = reinterpret_cast<ttk::ChainOp**>(p);
-      for (size_t k = 0; k < L.members.size(); ++k) {
-        const int i = L.members[k];
-        const tt_stream* s = b->members[i];
-        op[k] = s->plan[s->cur].dev + b->phases[i][L.phase].wides[L.slot];
-      }
-    } else {
-      const int pass = L.kind == kBlPass1 ? 1 : 2;
-      ttk::PassDesc* pd = reinterpret_cast<ttk::PassDesc*>(p);
-      for (size_t k = 0; k < L.members.size(); ++k)
-        pd[k] = pass_desc(b->members[L.members[k]], pass, slices[L.members[k]]);
-    }
-  }
-  if (b->use_graph && b->graph[q] && b->graph_dtype[q] != dtype) {  // kernels depend on the slice type
-    (void)hipGraphExecDestroy(b->graph[q]);
-    b->graph[q] = nullptr;
-  }
-  if (b->use_graph && !b->graph[q]) {
-    hipGraph_t g = nullptr;
-    TT_HIP(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    const tt_status st = enqueue_push(b, h, dtype);
-    const hipError_t e = hipStreamEndCapture(b->stream, &g);
-    if (st != TT_OK) {
-      if (g) (void)hipGraphDestroy(g);
-      return st;
-    }
-    TT_HIP(e);
-    const hipError_t ei = hipGraphInstantiate(&b->graph[q], g, nullptr, nullptr, 0);
-    (void)hipGraphDestroy(g);
-    TT_HIP(ei);
-    b->graph_dtype[q] = dtype;
-  }
-  if (b->use_graph) {
-    TT_HIP(hipGraphLaunch(b->graph[q], b->stream));
-  } else {
-    const tt_status st = enqueue_push(b, h, dtype);
-    if (st != TT_OK) return st;
-  }
-  TT_HIP(hipEventRecord(b->done[q], b->stream));
-  b->used[q] = true;
-  for (tt_stream* s : b->members) {
-    s->cur ^= 1;
-    s->pushes++;
-  }
-  return TT_OK;
-}
-
-tt_status tt_batch_synchronize(tt_batch* b, int32_t* rejected) {
-  if (!batch_valid(b)) return fail(TT_ERR_INVALID_ARG, "invalid batch");
-  TT_HIP(hipStreamSynchronize(b->stream));
-  bool any = false;
-  for (size_t i = 0; i < b->members.size(); ++i) {
-    tt_stream* s = b->members[i];
-    int rej = 0;
-    TT_HIP(hipMemcpy(&rej, s->rejected, sizeof(int), hipMemcpyDeviceToHost));
-    const int fresh = rej - b->rejected_seen[i];
-    if (rejected) rejected[i] = fresh;
-    if (fresh > 0) any = true;
-    b->rejected_seen[i] = rej;
-    s->rejected_seen = rej;
-  }
-  return any ? fail(TT_ERR_NONFINITE, "a slice contained NaN/Inf; its stream's update was discarded") : TT_OK;
-}
-
-tt_status tt_batch_use_graph(tt_batch* b, int32_t enable) {
-  if (!batch_valid(b)) return fail(TT_ERR_INVALID_ARG, "invalid batch");
-  if (enable && b->stream == nullptr)
-    return fail(TT_ERR_UNSUPPORTED, "graph replay needs a batch on a non-default HIP stream");
-  TT_HIP(hipStreamSynchronize(b->stream));
-  if (!enable) batch_drop_graphs(b);
-  b->use_graph = enable != 0;
-  return TT_OK;
-}
-
-tt_status tt_batch_info(const tt_batch* b, int32_t* n_streams, int32_t* n_groups) {
-  if (!batch_valid(b)) return fail(TT_ERR_INVALID_ARG, "invalid batch");
-  if (n_streams) *n_streams = (int32_t)b->members.size();
-  if (n_groups) *n_groups = (int32_t)b->n_groups;
-  return TT_OK;
-}
-
-tt_status tt_batch_destroy(tt_batch* b) {
-  if (!batch_valid(b)) return fail(TT_ERR_INVALID_ARG, "invalid batch");
-  (void)hipStreamSynchronize(b->stream);
-  batch_release(b);
-  b->magic = kDead;
-  delete b;
-  return TT_OK;
-}
-
 
 const char* tt_last_error_string(void) { return g_last_error.c_str(); }
 

@@ -97,6 +97,21 @@ def test_null_handles_are_rejected():
     assert lib.tt_batch_synchronize(None, None) == binding.TT_ERR_INVALID_ARG
     assert lib.tt_batch_info(None, None, None) == binding.TT_ERR_INVALID_ARG
     assert lib.tt_batch_destroy(None) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_batch_use_graph(None, 1) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_server_create(None, None) == binding.TT_ERR_INVALID_ARG
+    bad = binding.tt_server_config(0, 1, 0)
+    h = ctypes.c_void_p()
+    assert lib.tt_server_create(ctypes.byref(bad), ctypes.byref(h)) == binding.TT_ERR_INVALID_ARG
+    bad = binding.tt_server_config(4, 9, 0)
+    assert lib.tt_server_create(ctypes.byref(bad), ctypes.byref(h)) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_server_add(None, None, None) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_server_submit(None, 0, None, 1, 0) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_server_poll(None, None) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_server_drain(None) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_server_take(None, 0, None, None, None, None) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_server_stats(None, None, None, None, None, None) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_server_destroy(None) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_stream_pass_profile(None, None, None) == binding.TT_ERR_INVALID_ARG
     assert lib.tt_kernel_pass1_workspace(0, 1, 1) == 0
 
 
