@@ -34,12 +34,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def make_workload(name: str):
+def make_workload(name: str, pool=None):
     from ttgen import config_c2, config_c3
     if name == "c3":
-        return config_c3(T=500), 24
+        return config_c3(T=500), pool or 24
     if name == "c2":
-        return config_c2(T=1000), 64
+        return config_c2(T=1000), pool or 64
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -272,6 +272,10 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=30.0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default pass launch shapes instead of tuning them for the workload")
+    ap.add_argument("--pool", type=int, default=0,
+                    help="distinct resident frames cycled (default: more than the Infinity Cache holds)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one plain 256 MiB device copy (the counter calibration kernel)")
     ap.add_argument("--profile-ops", action="store_true",
                     help="also print the per-operation times of the update's chain (stderr)")
     args = ap.parse_args()
@@ -285,7 +289,7 @@ def main():
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
-    spec, pool_n = make_workload(args.workload)
+    spec, pool_n = make_workload(args.workload, args.pool or None)
     log(f"workload {spec.name}: modes {spec.modes} ranks {spec.ranks}; generating {pool_n} frames")
     pool = []
     for t in range(1, pool_n + 1):
@@ -319,8 +323,10 @@ def main():
     log(f"timed {args.steps} steps in {elapsed:.4f} s")
 
     # per-slice latency: push to committed state, one slice at a time
-    lat = []
+    lat = [float("nan")]
     for i in range(args.latency_steps):
+        if i == 0:
+            lat = []
         ts = time.perf_counter()
         s.push(pool[i % pool_n])
         s.synchronize()
@@ -345,6 +351,15 @@ def main():
     log(f"pass1 {kt['pass1']*1e3:.1f} us {gbs1:.0f} GB/s; pass2 {kt['pass2']*1e3:.1f} us {gbs2:.0f} GB/s")
     dom = "pass1" if kt["pass1"] >= kt["pass2"] else "pass2"
     achieved = gbs1 if dom == "pass1" else gbs2
+
+    if args.copy_calibration:
+        # a plain copy of known size: rocprofv3's FETCH_SIZE / WRITE_SIZE of this
+        # kernel calibrate the counters (bytes counted per byte moved)
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 268435456 bytes read, 268435456 bytes written")
 
     batched = None
     if args.batch > 0:

@@ -90,7 +90,15 @@ typedef struct {
 
 /* Flags. */
 #define TT_FLAG_SYNC_PUSH 0x1u   /* push waits for its update and reports NONFINITE */
-#define TT_FLAG_NO_ORTHO 0x2u    /* ablation: skip the LQ sweep and the QR steps    */
+/* TT_FLAG_NO_ORTHO: the "w/o Ortho" ablation of Section 5 (the LQ/QR
+ * orthogonalisation steps removed).  No normalisation of g, no LQ sweep, no
+ * QR: each local problem is solved exactly through the Gram matrices of the
+ * non-orthonormal interfaces, G~_k = (A_k^T A_k)^-1 A_k^T X B_k^T
+ * (B_k B_k^T)^-1 and G_k <- G~_k, and g = (A^T A)^-1 A^T vec(X); each Gram
+ * system S is solved as (S + 1e-12 tr(S)/r I)^-1 (it is singular where the
+ * interface has fewer columns than rows).  A non-positive Cholesky pivot
+ * rejects the update like a non-finite slice.  TT-ranks <= 32. */
+#define TT_FLAG_NO_ORTHO 0x2u
 #define TT_FLAG_PROFILE_OPS 0x4u /* time every chain operation (tt_stream_op_profile) */
 /* TT_FLAG_AUTOTUNE: at create, time candidate launch shapes of the two slice
  * passes for this stream's shape and precision (once per process and shape,

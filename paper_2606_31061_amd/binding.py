@@ -218,7 +218,8 @@ class TTStream:
 
     def __init__(self, modes, ranks, init=None, *, seed: int = 0, stream=None, keep_history: bool = False,
                  history_capacity: int = 0, split_point: int = 0, sync_push: bool = False,
-                 profile_ops: bool = False, compute: str = "f32", autotune: bool = False):
+                 profile_ops: bool = False, compute: str = "f32", autotune: bool = False,
+                 no_ortho: bool = False):
         self.modes = tuple(int(v) for v in modes)
         self.ranks = tuple(int(v) for v in ranks)
         self.n = int(np.prod(self.modes))
@@ -236,7 +237,8 @@ class TTStream:
                                    split_point=split_point, compute={"f32": TT_F32, "bf16": TT_BF16}[compute],
                                    flags=(TT_FLAG_SYNC_PUSH if sync_push else 0)
                                    | (TT_FLAG_PROFILE_OPS if profile_ops else 0)
-                                   | (TT_FLAG_AUTOTUNE if autotune else 0))
+                                   | (TT_FLAG_AUTOTUNE if autotune else 0)
+                                   | (TT_FLAG_NO_ORTHO if no_ortho else 0))
         self._lib = load_library()
 
     @staticmethod

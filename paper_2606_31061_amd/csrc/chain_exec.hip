@@ -1117,6 +1117,31 @@ __device__ __forceinline__ void exec_op(const ChainOp& op) {
       __syncthreads();
       break;
     }
+    case kOpSpdInv: {
+      // W = S + shift I (identity beyond m), R^-1 by chol_inv32, S^-1 = R^-1 R^-T
+      const int n = (int)op.m;
+      double* W = s_lds + kLdsW;
+      int* flag = reinterpret_cast<int*>(s_lds + kLdsFlag);
+      double tr = 0.0;
+      for (int i = 0; i < n; ++i) tr += op.a[i * op.ars + i * op.acs];
+      const double shift = op.tol * tr / n;
+      {
+        const int i = tid & 31, j = tid >> 5;
+        W[i + 32 * j] = (i < n && j < n) ? op.a[i * op.ars + j * op.acs] + (i == j ? shift : 0.0)
+                                         : (i == j ? 1.0 : 0.0);
+      }
+      __syncthreads();
+      if (tid < 64) {
+        const bool ok = chol_inv32<2>(s_lds + kLdsW, s_lds + kLdsR1, s_lds + kLdsRi, s_lds + kLdsRow, 0.0, n);
+        if (tid == 0) flag[0] = ok ? 1 : 0;
+      }
+      __syncthreads();
+      if (!flag[0] && tid == 0) *op.flag = 1;
+      const View Riv{kLdsRi, 1, 33}, RiTv{kLdsRi, 33, 1};
+      gemm_lds(n, n, 8, Riv, RiTv, [&](int ii, int jj, double v) { op.c[ii + n * jj] = v; });
+      __syncthreads();
+      break;
+    }
     case kOpCopy:
       for (int64_t e = tid; e < op.m; e += kCT) {
         const double x = op.a[e];
@@ -1191,6 +1216,7 @@ hipError_t chain_setup(size_t lds_limit) {
 }
 
 bool chain_op_supported(const ChainOp& op) {
+  if (op.type == kOpSpdInv) return op.m >= 1 && op.m <= 32;
   if (op.type == kOpQr) return op.n >= 1 && op.m >= op.n && op.n <= kMaxHouseholderCols && op.m <= INT32_MAX;
   if (op.type == kOpGemm) return op.m <= INT32_MAX && op.n <= INT32_MAX && op.k <= INT32_MAX;
   return true;

@@ -72,6 +72,13 @@ struct tt_stream {
   double* Gt = nullptr;
   double* Y[2] = {nullptr, nullptr};
   double* qrwork = nullptr;
+  // the "w/o Ortho" ablation: GB[k] = B_k B_k^T and GBi[k] = (B_k B_k^T)^+
+  // (k = 1..m), a J x J Gram matrix and its inverse, scratch, and G~ R_k
+  std::vector<double*> GB, GBi;
+  double* gram_j = nullptr;
+  double* gram_ji = nullptr;
+  double* gram_tmp = nullptr;
+  double* gram_g = nullptr;
   float* ws = nullptr;       // pass 1 workspace
   float* ws2 = nullptr;      // pass 2 workspace (BF16 contractions only)
   int* flag = nullptr;

@@ -40,7 +40,10 @@ constexpr int kChainThreads = 1024;
 //   kOpCommit if *flag == 0: hist row (t mod hist_cap) = a (m values), t += 1;
 //             else c = b (k doubles, restoring the old state), *rejected += 1;
 //             then *flag = 0.
-enum : int32_t { kOpGemm = 1, kOpQr = 2, kOpNormG = 3, kOpCopy = 4, kOpCommit = 5 };
+//   kOpSpdInv c = (S + tol tr(S)/m I)^-1 for the symmetric m x m matrix a
+//             (strides ars, acs; m <= 32), c column-major with leading
+//             dimension m; a non-positive Cholesky pivot sets *flag = 1.
+enum : int32_t { kOpGemm = 1, kOpQr = 2, kOpNormG = 3, kOpCopy = 4, kOpCommit = 5, kOpSpdInv = 6 };
 struct ChainOp {
   int32_t type = 0;
   int32_t rho = 0;

@@ -245,6 +245,149 @@ void plan_copy(UpdatePlan& p, const double* src, double* dst, float* dst32, int6
   plan_chain(p, op);
 }
 
+// S^-1 of the symmetric positive definite m x m matrix S into Sinv.
+void plan_spd_inv(UpdatePlan& p, const tt_stream* s, int64_t m, const double* S, double* Sinv) {
+  ttk::ChainOp op;
+  op.type = ttk::kOpSpdInv;
+  op.m = m;
+  op.a = S;
+  op.ars = 1;
+  op.acs = m;
+  op.c = Sinv;
+  op.tol = 0.0;
+  op.flag = s->flag;
+  plan_chain(p, op);
+}
+
+// The "w/o Ortho" ablation (TT_FLAG_NO_ORTHO): the update without the
+// right-orthogonalisation (no normalisation of g, no LQ sweep).  The right
+// interfaces B_k built from the current cores are then not orthonormal, and
+// the exact local solution needs their Gram matrix:
+//   G~_k = A_k^T X B_k^T R_k,  R_k = (B_k B_k^T)^+,
+// R_k = (B_k B_k^T)^-1 when r_k <= J_k, else B_k (B_k^T B_k)^-2 B_k^T (B_k of
+// full column rank; always the case at k = m, B_m = g).  The forward sweep's
+// QR and everything after it are as in build_plan.  For k < k* the Gram
+// matrix comes from the recursion B_k B_k^T = sum_i G_{k+1}(:,i,:)
+// (B_{k+1} B_{k+1}^T) G_{k+1}(:,i,:)^T and needs r_k <= J_k.
+void build_plan_noortho(tt_stream* s, int par) {
+  UpdatePlan& P = s->plan[par];
+  P.ops.clear();
+  P.steps.clear();
+  double* master = s->state[par];
+  double* fresh = s->state[par ^ 1];
+  double* tmp = s->gram_tmp;
+  const int m = s->m, ks = s->kstar;
+  const auto& I = s->I;
+  const auto& r = s->r;
+  const auto& Pk = s->Pk;
+  const auto& Jk = s->Jk;
+  auto Bk = [&](int k) -> double* { return k == m ? s->g_of(master) : s->B[k]; };
+
+  // right interfaces B_{m-1} .. B_{k*} from the current cores
+  for (int j = m - 1; j >= ks; --j) {
+    const int64_t rj = r[j] * I[j + 1];
+    plan_gemm(P, rj, Jk[j + 1], r[j + 1], s->G_of(master, j + 1), 1, rj, Bk(j + 1), 1, r[j + 1], s->B[j], 1, rj,
+              j == ks ? s->B32 : nullptr);
+  }
+  if (ks == m) plan_copy(P, s->g_of(master), nullptr, s->B32, r[m]);
+  // R_k for k >= k* from the explicit interfaces
+  for (int k = m; k >= ks; --k) {
+    const double* Bm = Bk(k);
+    const int64_t rk = r[k], J = Jk[k];
+    if (rk <= J) {
+      plan_gemm(P, rk, rk, J, Bm, 1, rk, Bm, rk, 1, s->GB[k], 1, rk, nullptr);
+      plan_spd_inv(P, s, rk, s->GB[k], s->GBi[k]);
+    } else {
+      // (B B^T)^+ = B H H B^T with H = (B^T B)^-1 (J x J)
+      plan_gemm(P, J, J, rk, Bm, rk, 1, Bm, 1, rk, s->gram_j, 1, J, nullptr);
+      plan_spd_inv(P, s, J, s->gram_j, s->gram_ji);
+      plan_gemm(P, rk, J, J, Bm, 1, rk, s->gram_ji, 1, J, tmp, 1, rk, nullptr);
+      plan_gemm(P, rk, J, J, tmp, 1, rk, s->gram_ji, 1, J, tmp + rk * J, 1, rk, nullptr);
+      plan_gemm(P, rk, rk, J, tmp + rk * J, 1, rk, Bm, rk, 1, s->GBi[k], 1, rk, nullptr);
+    }
+  }
+  // R_k for k < k* by the Gram recursion from B_{k*} B_{k*}^T
+  if (ks > 1) {
+    if (r[ks] > Jk[ks]) plan_gemm(P, r[ks], r[ks], Jk[ks], Bk(ks), 1, r[ks], Bk(ks), r[ks], 1, s->GB[ks], 1, r[ks],
+                                  nullptr);
+    for (int k = ks - 1; k >= 1; --k) {
+      const int64_t rows = r[k] * I[k + 1];
+      const double* G = s->G_of(master, k + 1);
+      plan_gemm(P, rows, r[k + 1], r[k + 1], G, 1, rows, s->GB[k + 1], 1, r[k + 1], tmp, 1, rows, nullptr);
+      plan_gemm(P, r[k], r[k], I[k + 1] * r[k + 1], tmp, 1, r[k], G, r[k], 1, s->GB[k], 1, r[k], nullptr);
+      plan_spd_inv(P, s, r[k], s->GB[k], s->GBi[k]);
+    }
+  }
+
+  P.steps.push_back({kStepPass1, 0, 0});
+
+  auto Zof = [&](int k) -> double* { return k == ks ? s->Z : s->Zk[k]; };
+  for (int k = ks - 1; k >= 1; --k) {
+    const int64_t Kd = I[k + 1] * r[k + 1];
+    plan_gemm(P, Pk[k], r[k], Kd, Zof(k + 1), 1, Pk[k], s->G_of(master, k + 1), r[k], 1, Zof(k), 1, Pk[k],
+              nullptr);
+  }
+  // G~ R_k (rows x n) into gram_g, then the thin QR into the fresh core
+  auto solve_qr = [&](int k, const double* src) {
+    const int64_t rows = r[k - 1] * I[k];
+    const int64_t n = r[k];
+    plan_gemm(P, rows, n, n, src, 1, rows, s->GBi[k], 1, n, s->gram_g, 1, rows, nullptr);
+    double* Gnew = s->G_of(fresh, k);
+    plan_qr(P, s, rows, n, (int)std::min<int64_t>(n, Jk[k]), s->gram_g, 1, rows, Gnew, 1, rows, nullptr);
+    return Gnew;
+  };
+  for (int k = 1; k <= ks; ++k) {
+    const double* Gt;
+    if (k == 1) {
+      Gt = Zof(1);
+    } else {
+      const double* Ak = (k == 2) ? s->G_of(fresh, 1) : s->A[k];
+      plan_gemm(P, r[k - 1], I[k] * r[k], Pk[k - 1], Ak, Pk[k - 1], 1, Zof(k), 1, Pk[k - 1], s->Gt, 1, r[k - 1],
+                nullptr);
+      Gt = s->Gt;
+    }
+    double* Gnew = solve_qr(k, Gt);
+    if (k >= 2) {
+      const double* Ak = (k == 2) ? s->G_of(fresh, 1) : s->A[k];
+      double* Anext = (k == ks) ? nullptr : s->A[k + 1];
+      plan_gemm(P, Pk[k - 1], I[k] * r[k], r[k - 1], Ak, 1, Pk[k - 1], Gnew, 1, r[k - 1], Anext, 1, Pk[k - 1],
+                k == ks ? s->A32 : nullptr);
+    } else if (ks == 1) {
+      plan_copy(P, Gnew, nullptr, s->A32, Pk[1] * r[1]);
+    }
+  }
+
+  P.steps.push_back({kStepPass2, 0, 0});
+
+  int cur = 0;
+  for (int k = ks + 1; k <= m; ++k) {
+    const int64_t rows = r[k - 1] * I[k];
+    const int64_t n = r[k];
+    plan_gemm(P, rows, n, Jk[k], s->Y[cur], 1, rows, Bk(k), r[k], 1, s->Gt, 1, rows, nullptr);
+    double* Gnew = solve_qr(k, s->Gt);
+    double* dst = (k == m) ? s->g_of(fresh) : s->Y[cur ^ 1];
+    plan_gemm(P, n, Jk[k], rows, Gnew, rows, 1, s->Y[cur], 1, rows, dst, 1, n, nullptr);
+    cur ^= 1;
+  }
+  if (ks == m) plan_copy(P, s->Y[0], s->g_of(fresh), nullptr, r[m]);
+
+  {
+    ttk::ChainOp op;
+    op.type = ttk::kOpCommit;
+    op.a = s->g_of(fresh);
+    op.m = r[m];
+    op.b = master;
+    op.c = fresh;
+    op.k = s->state_len;
+    op.flag = s->flag;
+    op.rejected = s->rejected;
+    op.tdev = s->tdev;
+    op.hist = s->hist;
+    op.hist_cap = s->hist_cap;
+    plan_chain(P, op);
+  }
+}
+
 // The update that reads state[par] and writes state[par ^ 1].
 void build_plan(tt_stream* s, int par) {
   UpdatePlan& P = s->plan[par];
@@ -441,7 +584,7 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
         return fail(TT_ERR_RANK, "infeasible TT-ranks: need r_k <= r_{k-1} I_k and r_{k-1} <= I_k r_k");
   }
   if (cfg->compute != TT_F32 && cfg->compute != TT_BF16) return fail(TT_ERR_INVALID_ARG, "compute must be F32/BF16");
-  if (cfg->flags & ~(TT_FLAG_SYNC_PUSH | TT_FLAG_PROFILE_OPS | TT_FLAG_AUTOTUNE))
+  if (cfg->flags & ~(TT_FLAG_SYNC_PUSH | TT_FLAG_PROFILE_OPS | TT_FLAG_AUTOTUNE | TT_FLAG_NO_ORTHO))
     return fail(TT_ERR_UNSUPPORTED, "unsupported flags");
   if (cfg->split_point < 0 || cfg->split_point > m) return fail(TT_ERR_INVALID_ARG, "split_point out of range");
 
@@ -480,6 +623,13 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
     delete s;
     return fail(TT_ERR_UNSUPPORTED, "rank at the split point must be <= 64");
   }
+  if (s->flags & TT_FLAG_NO_ORTHO)
+    for (int k = 1; k <= m; ++k)
+      if (s->r[k] > 32 || (k < s->kstar && s->r[k] > s->Jk[k])) {
+        delete s;
+        return fail(TT_ERR_UNSUPPORTED,
+                    "TT_FLAG_NO_ORTHO needs TT-ranks <= 32 and r_k <= I_{k+1}..I_m below the split point");
+      }
 
   auto bail = [&](tt_status code, const std::string& msg) {
     release(s);
@@ -547,6 +697,18 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
   s->Y[0] = D(ymax);
   s->Y[1] = D(ymax);
   s->qrwork = D(qrmax);
+  if (s->flags & TT_FLAG_NO_ORTHO) {  // Gram matrices of the ablation
+    s->GB.assign(m_ + 1, nullptr);
+    s->GBi.assign(m_ + 1, nullptr);
+    for (int k = 1; k <= m_; ++k) {
+      s->GB[k] = D(r[k] * r[k]);
+      s->GBi[k] = D(r[k] * r[k]);
+    }
+    s->gram_j = D(32 * 32);
+    s->gram_ji = D(32 * 32);
+    s->gram_tmp = D(std::max<int64_t>(qrmax, 2 * 32 * 32));
+    s->gram_g = D(gtmax);
+  }
   s->ws = bf16 ? static_cast<float*>(dev_alloc(s, s->p1b.ws_bytes)) : F(s->p1.ws_floats);
   if (bf16) s->ws2 = static_cast<float*>(dev_alloc(s, s->p2b.ws_bytes));
   if (bf16 && (!s->ws || !s->ws2)) ok = false;
@@ -579,7 +741,8 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
                              s->stream));
   s->cur = 0;
   for (int par = 0; par < 2; ++par) {
-    build_plan(s, par);
+    if (s->flags & TT_FLAG_NO_ORTHO) build_plan_noortho(s, par);
+    else build_plan(s, par);
     UpdatePlan& P = s->plan[par];
     for (const ttk::ChainOp& op : P.ops)
       if (!ttk::chain_op_supported(op)) return bail(TT_ERR_UNSUPPORTED, "a core re-orthogonalisation exceeds 256 columns");
