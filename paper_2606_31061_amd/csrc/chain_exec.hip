@@ -80,6 +80,23 @@ __device__ __forceinline__ int tix() {
   return t;
 }
 
+// fn(i, j) for every (i, j) of an m x n index space (m >= 1), the workgroup's
+// threads walking i fastest.  The indices advance incrementally, so there is no
+// integer division per element.
+template <class Fn>
+__device__ __forceinline__ void for_each_ij(int m, int n, Fn fn) {
+  const int tid = tix(), di = kCT % m, dj = kCT / m;
+  for (int i = tid % m, j = tid / m; j < n;) {
+    fn(i, j);
+    i += di;
+    j += dj;
+    if (i >= m) {
+      i -= m;
+      ++j;
+    }
+  }
+}
+
 __device__ __forceinline__ double read_lane(double x, int lane) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
   const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
@@ -455,8 +472,9 @@ __device__ __forceinline__ double rsqrt_pos(double d) {
 // that it ends as R^-T.  Step j scales row j by 1/sqrt(pivot) and removes
 // R(j,:)^T R(j,:) from the rows below.  The steps go in blocks of four: inside
 // a block the few entries needed come from single lanes, and the rows below
-// receive the block's four updates at once from an LDS broadcast, so there
-// are eight LDS round trips instead of thirty-two.  Only pivots of the first
+// receive the block's four updates at once, the entries of row i read from
+// lane i into scalar registers (v_readlane), so no step waits on memory
+// (rowbuf is not used).  Only pivots of the first
 // n columns are tested against thr2.  Writes R (zeros below the diagonal,
 // leading dimension 32) and R^-1 (leading dimension 33); R may alias W.
 // NEWTON = 1 leaves the pivots' square roots good to about 1e-10 relative,
@@ -488,26 +506,16 @@ __device__ __forceinline__ bool chol_inv32(const double* W, double* R, double* R
 #pragma unroll
       for (int i = j + 1; i < jb + 4; ++i) v[i] = fma(-read_lane(v[j], i), v[j], v[i]);
     }
-    if (jb + 4 < 32) {
-      double* mine = rowbuf + 4 * lane;
-      mine[0] = v[jb];
-      mine[1] = v[jb + 1];
-      mine[2] = v[jb + 2];
-      mine[3] = v[jb + 3];
-      __builtin_amdgcn_wave_barrier();
+    // rows below the block: R(jb..jb+3, i) lives in lane i; it reaches every
+    // lane through scalar registers (no memory round trip on the chain)
 #pragma unroll
-      for (int i0 = jb + 4; i0 < 32; i0 += 4) {
-#pragma unroll
-        for (int i = i0; i < i0 + 4; ++i) {
-          const double* r = rowbuf + 4 * i;  // R(jb..jb+3, i), written by lane i
-          v[i] = fma(-r[0], v[jb], v[i]);
-          v[i] = fma(-r[1], v[jb + 1], v[i]);
-          v[i] = fma(-r[2], v[jb + 2], v[i]);
-          v[i] = fma(-r[3], v[jb + 3], v[i]);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-      }
-      __builtin_amdgcn_wave_barrier();
+    for (int i = jb + 4; i < 32; ++i) {
+      const double r0 = read_lane(v[jb], i), r1 = read_lane(v[jb + 1], i);
+      const double r2 = read_lane(v[jb + 2], i), r3 = read_lane(v[jb + 3], i);
+      v[i] = fma(-r0, v[jb], v[i]);
+      v[i] = fma(-r1, v[jb + 1], v[i]);
+      v[i] = fma(-r2, v[jb + 2], v[i]);
+      v[i] = fma(-r3, v[jb + 3], v[i]);
     }
   }
 #pragma unroll
@@ -655,17 +663,11 @@ __device__ __forceinline__ void householder_qr(const Qr& q, double* A, int lda) 
   for (int j = tid; j < n; j += kCT) sgn[j] = (tau[j] != 0.0 && A[j + (int64_t)j * lda] < 0.0) ? -1.0 : 1.0;
   __syncthreads();
   if (q.R) {
-    for (int e = tid; e < n * n; e += kCT) {
-      const int i = e % n, j = e / n;
-      q.R[e] = (i <= j) ? sgn[i] * A[i + (int64_t)j * lda] : 0.0;
-    }
+    for_each_ij(n, n, [&](int i, int j) { q.R[i + n * j] = (i <= j) ? sgn[i] * A[i + (int64_t)j * lda] : 0.0; });
   }
   __syncthreads();
   hh_form_q(A, m, n, lda, tau, sgn);
-  for (int64_t e = tid; e < (int64_t)m * n; e += kCT) {
-    const int i = (int)(e % m), j = (int)(e / m);
-    q.Q[i * q.qrs + j * q.qcs] = A[i + (int64_t)j * lda];
-  }
+  for_each_ij(m, n, [&](int i, int j) { q.Q[i * q.qrs + j * q.qcs] = A[i + (int64_t)j * lda]; });
   __syncthreads();
 }
 
@@ -845,10 +847,19 @@ __device__ __forceinline__ bool cholqr2_reg(const Qr& q) {
 #pragma unroll
         for (int v = 0; v < 4; ++v) part[(r0 + 16 * t + 4 * v + lk) + ldq * (16 * cb + li)] = acc[t][cb][v];
     __syncthreads();
+    // the threads walk Q along its contiguous index (f) and step the indices
+    // incrementally: no integer division per element
     const bool ifast = q.qrs <= q.qcs;
-    for (int e = tid; e < m * n; e += kCT) {
-      const int row = ifast ? e % m : e / n, col = ifast ? e / m : e % n;
+    const int nf = ifast ? m : n, ns = ifast ? n : m, df = kCT % nf, ds = kCT / nf;
+    for (int f = tid % nf, sl = tid / nf; sl < ns;) {
+      const int row = ifast ? f : sl, col = ifast ? sl : f;
       q.Q[row * q.qrs + col * q.qcs] = part[row + ldq * col];
+      f += df;
+      sl += ds;
+      if (f >= nf) {
+        f -= nf;
+        ++sl;
+      }
     }
   }
   if (q.R) {
@@ -1081,11 +1092,7 @@ __device__ __forceinline__ void wg_qr(const Qr& q) {
     return;
   }
   // larger matrices: Householder in the device scratch buffer
-  const int tid = tix();
-  for (int64_t e = tid; e < (int64_t)m * n; e += kCT) {
-    const int i = (int)(e % m), j = (int)(e / m);
-    q.aux[e] = q.M[i * q.mrs + j * q.mcs];
-  }
+  for_each_ij(m, n, [&](int i, int j) { q.aux[i + (int64_t)m * j] = q.M[i * q.mrs + j * q.mcs]; });
   __syncthreads();
   householder_qr(q, q.aux, m);
 }
