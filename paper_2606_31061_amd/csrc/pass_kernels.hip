@@ -18,18 +18,24 @@ namespace {
 typedef float floatx16 __attribute__((ext_vector_type(16)));
 
 // ---------------------------------------------------------------- loads
+typedef float f2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+template <typename T>
+__device__ __forceinline__ const TT_GLOBAL_AS T* gptr(const T* p) {
+  return (const TT_GLOBAL_AS T*)p;
+}
+
 // VEC consecutive elements of X converted to FP32 (streamed: non-temporal).
 template <typename T, int VEC>
 struct Ld;
 template <>
 struct Ld<float, 1> {
-  static __device__ __forceinline__ void get(const float* p, float* o) { o[0] = __builtin_nontemporal_load(p); }
+  static __device__ __forceinline__ void get(const float* p, float* o) { o[0] = __builtin_nontemporal_load(gptr(p)); }
 };
 template <>
 struct Ld<float, 2> {
   static __device__ __forceinline__ void get(const float* p, float* o) {
-    typedef float f2 __attribute__((ext_vector_type(2)));
-    const f2 v = __builtin_nontemporal_load(reinterpret_cast<const f2*>(p));
+    const f2 v = __builtin_nontemporal_load(gptr(reinterpret_cast<const f2*>(p)));
     o[0] = v.x;
     o[1] = v.y;
   }
@@ -37,8 +43,7 @@ struct Ld<float, 2> {
 template <>
 struct Ld<float, 4> {
   static __device__ __forceinline__ void get(const float* p, float* o) {
-    typedef float f4 __attribute__((ext_vector_type(4)));
-    const f4 v = __builtin_nontemporal_load(reinterpret_cast<const f4*>(p));
+    const f4 v = __builtin_nontemporal_load(gptr(reinterpret_cast<const f4*>(p)));
     o[0] = v.x;
     o[1] = v.y;
     o[2] = v.z;
@@ -49,7 +54,7 @@ template <int VEC>
 struct Ld<double, VEC> {
   static __device__ __forceinline__ void get(const double* p, float* o) {
 #pragma unroll
-    for (int s = 0; s < VEC; ++s) o[s] = (float)__builtin_nontemporal_load(p + s);
+    for (int s = 0; s < VEC; ++s) o[s] = (float)__builtin_nontemporal_load(gptr(p + s));
   }
 };
 template <int VEC>
@@ -57,7 +62,7 @@ struct Ld<__hip_bfloat16, VEC> {
   static __device__ __forceinline__ void get(const __hip_bfloat16* p, float* o) {
     const unsigned short* q = reinterpret_cast<const unsigned short*>(p);
 #pragma unroll
-    for (int s = 0; s < VEC; ++s) o[s] = __uint_as_float(((unsigned)__builtin_nontemporal_load(q + s)) << 16);
+    for (int s = 0; s < VEC; ++s) o[s] = __uint_as_float(((unsigned)__builtin_nontemporal_load(gptr(q + s))) << 16);
   }
 };
 
@@ -69,17 +74,17 @@ template <int VEC>
 struct LdC<float, VEC> {
   static __device__ __forceinline__ void get(const float* p, float* o) {
     if constexpr (VEC == 4) {
-      const float4 v = *reinterpret_cast<const float4*>(p);
+      const f4 v = *gptr(reinterpret_cast<const f4*>(p));
       o[0] = v.x;
       o[1] = v.y;
       o[2] = v.z;
       o[3] = v.w;
     } else if constexpr (VEC == 2) {
-      const float2 v = *reinterpret_cast<const float2*>(p);
+      const f2 v = *gptr(reinterpret_cast<const f2*>(p));
       o[0] = v.x;
       o[1] = v.y;
     } else {
-      o[0] = *p;
+      o[0] = *gptr(p);
     }
   }
 };
@@ -87,7 +92,7 @@ template <int VEC>
 struct LdC<double, VEC> {
   static __device__ __forceinline__ void get(const double* p, float* o) {
 #pragma unroll
-    for (int s = 0; s < VEC; ++s) o[s] = (float)p[s];
+    for (int s = 0; s < VEC; ++s) o[s] = (float)*gptr(p + s);
   }
 };
 template <int VEC>
@@ -95,7 +100,7 @@ struct LdC<__hip_bfloat16, VEC> {
   static __device__ __forceinline__ void get(const __hip_bfloat16* p, float* o) {
     const unsigned short* q = reinterpret_cast<const unsigned short*>(p);
 #pragma unroll
-    for (int s = 0; s < VEC; ++s) o[s] = __uint_as_float(((unsigned)q[s]) << 16);
+    for (int s = 0; s < VEC; ++s) o[s] = __uint_as_float(((unsigned)*gptr(q + s)) << 16);
   }
 };
 
@@ -173,16 +178,13 @@ __global__ void __launch_bounds__(NW * 64) k_pass1(const T* __restrict__ X, int6
   // load batches themselves never wait on their data: the next batch stays
   // in flight while the current one is multiplied.
   const int64_t prow_c = rowok ? prow : P - VEC;
-  const float rmask = rowok ? 1.f : 0.f;
   const int64_t j_first = 2 * (pb + w) + half;
   const int64_t jend = (2 * pe < J) ? 2 * pe : J;
   int acol_c[NTN];
-  float amask[NTN];
 #pragma unroll
   for (int t = 0; t < NTN; ++t) {
     const int a = acol + 32 * t;
     acol_c[t] = a < r ? a : r - 1;
-    amask[t] = a < r ? 1.f : 0.f;
   }
   const int64_t xstep = 2 * (int64_t)NW * P;   // one column pair per wave step
   const int64_t bstep = 2 * (int64_t)NW * r;
@@ -193,29 +195,37 @@ __global__ void __launch_bounds__(NW * 64) k_pass1(const T* __restrict__ X, int6
   const int64_t nsteps = (pe > pb + w) ? (pe - (pb + w) + NW - 1) / NW : 0;
 
   float xa0[U][VEC], bb0[U][NTN], xa1[U][VEC], bb1[U][NTN];
+  // Interface values first (they come from L2), then the slice vectors, so
+  // the MFMAs of column pair u wait only for the loads up to pair u.
   auto load = [&](float (&xa)[U][VEC], float (&bb)[U][NTN], int64_t i0) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const float* b = bp + (i0 + u) * bstep;
+      b = b < blast ? b : blast;
+#pragma unroll
+      for (int t = 0; t < NTN; ++t) bb[u][t] = *gptr(b + acol_c[t]);
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const T* x = xp + (i0 + u) * xstep;
       x = x < xlast ? x : xlast;
       LdC<T, VEC>::get(x, xa[u]);
-      const float* b = bp + (i0 + u) * bstep;
-      b = b < blast ? b : blast;
-#pragma unroll
-      for (int t = 0; t < NTN; ++t) bb[u][t] = b[acol_c[t]];
     }
   };
+  // Rows past P and ranks past r only reach outputs that are never stored; a
+  // column past the chunk is zeroed on the interface operand, so the slice
+  // values enter the MFMAs as loaded (no per-element select to wait for).
   auto compute = [&](const float (&xa)[U][VEC], const float (&bb)[U][NTN], int64_t i0) {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int64_t j = j_first + (i0 + u) * 2 * NW;
-      const float m = (j < jend) ? rmask : 0.f;
+      const bool live = j_first + (i0 + u) * 2 * NW < jend;
 #pragma unroll
       for (int t = 0; t < NTN; ++t) {
-        const float b = bb[u][t] * amask[t];
+        const float b = live ? bb[u][t] : 0.f;
 #pragma unroll
-        for (int s = 0; s < VEC; ++s) acc[t][s] = mfma32(xa[u][s] * m, b, acc[t][s]);
+        for (int s = 0; s < VEC; ++s) acc[t][s] = mfma32(xa[u][s], b, acc[t][s]);
       }
+      __builtin_amdgcn_sched_barrier(0);
     }
   };
   // Branch-free steady state: loads past the wave's last step read the
@@ -261,7 +271,14 @@ __global__ void __launch_bounds__(NW * 64) k_pass1(const T* __restrict__ X, int6
   }
 }
 
-// Z(row, col) = sum over chunks of the partial tiles (FP64, chunk order).
+// Z(row, col) = sum over chunks of the partial tiles, in FP64.  A block
+// covers kRedElems tile elements; its thread (element e, group g) adds the
+// chunks g, g + kRedGroups, ... in order, with all of its loads in flight at
+// once, and the kRedGroups sums are then added in group order, so the result
+// does not depend on the launch (every member of a batch sums the same way).
+constexpr int kRedGroups = 4;
+constexpr int kRedElems = 256 / kRedGroups;
+
 template <int VEC, int NTN>
 __global__ void __launch_bounds__(256) k_pass1_reduce(const float* __restrict__ part, int chunks, int64_t P, int r,
                                                       double* __restrict__ Z, int* __restrict__ flag,
@@ -276,26 +293,35 @@ __global__ void __launch_bounds__(256) k_pass1_reduce(const float* __restrict__ 
     r = pp.r;
   }
   constexpr int TILEF = NTN * VEC * 1024;
-  const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int64_t tp = g / TILEF;
-  const int e = (int)(g % TILEF);
+  __shared__ double red[256];
+  const int el = threadIdx.x % kRedElems, g = threadIdx.x / kRedElems;
+  const int64_t eg = (int64_t)blockIdx.x * kRedElems + el;
+  const int64_t tp = eg / TILEF;
+  const int e = (int)(eg % TILEF);
   const int64_t ntiles = (P + 32 * VEC - 1) / (32 * VEC);
-  if (tp >= ntiles) return;
+  double sum = 0.0;
+  if (tp < ntiles) {
+    const float* p = part + tp * chunks * TILEF + e;
+    for (int c0 = g; c0 < chunks; c0 += 8 * kRedGroups) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int cc = c0 + u * kRedGroups;
+        v[u] = cc < chunks ? *gptr(p + (int64_t)cc * TILEF) : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) sum += (double)v[u];
+    }
+  }
+  red[threadIdx.x] = sum;
+  __syncthreads();
+  if (g != 0 || tp >= ntiles) return;
+#pragma unroll
+  for (int gg = 1; gg < kRedGroups; ++gg) sum += red[gg * kRedElems + el];
   const int t = e / (VEC * 1024), s = (e / 1024) % VEC, v = (e / 64) % 16, ln = e % 64;
   const int64_t row = tp * 32 * VEC + (int64_t)VEC * mfma_row(ln, v) + s;
   const int col = (ln & 31) + 32 * t;
   if (row >= P || col >= r) return;
-  double sum = 0.0;
-  const float* p = part + tp * chunks * TILEF + e;
-  int cc = 0;
-  for (; cc + 8 <= chunks; cc += 8) {  // eight loads in flight, summed in chunk order
-    float v[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = p[(int64_t)(cc + u) * TILEF];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) sum += (double)v[u];
-  }
-  for (; cc < chunks; ++cc) sum += (double)p[(int64_t)cc * TILEF];
   Z[row + P * (int64_t)col] = sum;
   if (!isfinite(sum)) atomicOr(flag, 1);
 }
@@ -402,7 +428,7 @@ __global__ void __launch_bounds__(kPass2Waves * 64) k_pass2(const T* __restrict_
         const int ac = a < r ? a : r - 1;
         if (VEC == 4) {
           const int64_t pc = pbase < P - 3 ? pbase : P - 4;
-          const float4 q = *reinterpret_cast<const float4*>(A + pc + P * (int64_t)ac);
+          const f4 q = *gptr(reinterpret_cast<const f4*>(A + pc + P * (int64_t)ac));
           av[k][t][0] = q.x;
           av[k][t][1] = q.y;
           av[k][t][2] = q.z;
@@ -411,7 +437,7 @@ __global__ void __launch_bounds__(kPass2Waves * 64) k_pass2(const T* __restrict_
 #pragma unroll
           for (int s = 0; s < 4; ++s) {
             const int64_t p = pbase + s;
-            av[k][t][s] = A[(p < P ? p : P - 1) + P * (int64_t)ac];
+            av[k][t][s] = *gptr(A + (p < P ? p : P - 1) + P * (int64_t)ac);
           }
         }
       }
@@ -480,7 +506,7 @@ hipError_t launch_p1(hipStream_t st, const T* X, int64_t P, int64_t J, int r, co
   constexpr int TILEF = NTN * VEC * 1024;
   const int64_t threads = (int64_t)tiles * TILEF;
   const unsigned gx = bl ? bl->gx : (unsigned)(tiles * groups * 8);
-  const unsigned grx = bl ? bl->grx : (unsigned)((threads + 255) / 256);
+  const unsigned grx = bl ? bl->grx : (unsigned)((threads + kRedElems - 1) / kRedElems);
   const unsigned nb = bl ? (unsigned)bl->n : 1u;
   const PassDesc* d = bl ? bl->desc : nullptr;
   hipLaunchKernelGGL((k_pass1<T, VEC, NW, NTN>), dim3(gx, nb), dim3(NW * 64), 0, st, X, P, J, r, B, ws, tiles, chunks,
@@ -572,7 +598,7 @@ Pass1Plan finish_plan(Pass1Plan pl, int64_t P) {
 void pass1_grids(const Pass1Plan& pl, int64_t P, unsigned* gx, unsigned* grx) {
   const int tiles = (int)((P + 32 * pl.vec - 1) / (32 * pl.vec));
   *gx = (unsigned)(tiles * ((pl.chunks + 7) / 8) * 8);
-  *grx = (unsigned)(((int64_t)tiles * pl.ntn * pl.vec * 1024 + 255) / 256);
+  *grx = (unsigned)(((int64_t)tiles * pl.ntn * pl.vec * 1024 + kRedElems - 1) / kRedElems);
 }
 
 unsigned pass2_grid(int64_t J) { return (unsigned)((J + 31) / 32); }

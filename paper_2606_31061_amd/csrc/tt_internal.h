@@ -21,6 +21,15 @@ tt_status set_error(tt_status st, const char* msg);
 #else
 #define TT_CONSTANT_AS
 #endif
+// Device memory reached through a pointer that the compiler cannot trace to a
+// kernel argument (batch descriptors): loads through the global address space
+// are plain vector-memory loads, where a generic pointer would give flat loads
+// that also count against the LDS wait counter and force coarser waits.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define TT_GLOBAL_AS __attribute__((address_space(1)))
+#else
+#define TT_GLOBAL_AS
+#endif
 
 // Threads of the workgroup that runs the chain operation lists.
 constexpr int kChainThreads = 1024;
