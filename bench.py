@@ -52,16 +52,39 @@ def pass_bytes(P, J, r, xbytes=4):
 
 
 def time_passes_in_update(stream, pool, steps):
-    """Average device time of the two slice passes inside the update: HIP
-    events recorded on the update's stream around each pass (the stream was
-    created with profile_ops)."""
-    t1, t2 = [], []
+    """Average device times (ms) of the two slice passes inside the update:
+    HIP events recorded on the update's stream around each pass and after its
+    contraction kernel (the stream was created with profile_ops)."""
+    acc = {}
     for i in range(steps):
         stream.push(pool[i % len(pool)])
-        a, b = stream.pass_profile()
-        t1.append(a)
-        t2.append(b)
-    return {"pass1": float(np.mean(t1)), "pass2": float(np.mean(t2))}
+        for key, ms in stream.pass_profile().items():
+            acc.setdefault(key, []).append(ms)
+    return {key: float(np.mean(v)) for key, v in acc.items()}
+
+
+# rocprofv3 HBM counters of the contraction kernels (FETCH_SIZE and WRITE_SIZE
+# per dispatch, scaled by the same counters on a copy kernel of known size),
+# stored with a hash of the kernel source they were taken on.
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "slice_pass_traffic.json")
+KERNEL_SOURCES = {"f32": "paper_2606_31061_amd/csrc/pass_kernels.hip", "bf16": "paper_2606_31061_amd/csrc/pass_bf16.hip"}
+
+
+def measured_traffic(workload, compute, kernel):
+    """HBM bytes per launch of `kernel` from the stored counters, or None when
+    there are none for this workload or the kernel source changed since."""
+    import hashlib
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(os.path.join(ROOT, KERNEL_SOURCES[compute]), "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError, KeyError):
+        return None
+    k = rec.get("kernels", {}).get(kernel)
+    if rec.get("workload") != workload or rec.get("compute") != compute or not k or k.get("source_sha256") != digest:
+        return None
+    return float(k["fetch_bytes"] + k["write_bytes"])
 
 
 def batched_section(torch, n_streams, rounds, warmup, compute, tune):
@@ -251,6 +274,46 @@ def cpu_baseline(spec, seconds_budget: float):
                       f"{t_used:.1f} s of CPU work"}
 
 
+def write_traffic(fetch_db, write_db, workload, compute):
+    """Writes TRAFFIC_FILE from two rocprofv3 --pmc databases of a bench run
+    with --copy-calibration (one with FETCH_SIZE, one with WRITE_SIZE).  Each
+    counter is scaled by bytes moved / counter value of the 256 MiB copy, and
+    averaged over the last ten dispatches of each contraction kernel (those
+    of the tuned plan, after the tuner's trial launches)."""
+    import hashlib
+    import re
+    import sqlite3
+
+    def read(db, counter):
+        con = sqlite3.connect(db)
+        rows = con.execute("select dispatch_id, kernel_name, value from counters_collection where counter_name = ? "
+                           "order by dispatch_id", (counter,)).fetchall()
+        con.close()
+        return rows
+
+    copy_bytes = 256 << 20
+    out = {"workload": workload, "compute": compute, "kernels": {}}
+    for counter, db, key in (("FETCH_SIZE", fetch_db, "fetch_bytes"), ("WRITE_SIZE", write_db, "write_bytes")):
+        rows = read(db, counter)
+        copies = [v for _, k, v in rows if "copyBuffer" in k and v * 1024 > copy_bytes / 4]
+        if not copies:
+            raise SystemExit(f"{db}: no copy calibration dispatch (run the bench with --copy-calibration)")
+        scale = copy_bytes / (max(copies) * 1024.0)
+        out[key.replace("_bytes", "_scale")] = scale
+        with open(os.path.join(ROOT, KERNEL_SOURCES[compute]), "rb") as f:
+            digest = hashlib.sha256(f.read()).hexdigest()
+        for kern in (["k_pass1b", "k_pass2b"] if compute == "bf16" else ["k_pass1", "k_pass2"]):
+            vals = [v for _, k, v in rows if re.search(r"\b" + kern + "<", k)][-10:]
+            if not vals:
+                raise SystemExit(f"{db}: no {kern} dispatches")
+            rec = out["kernels"].setdefault(kern, {"source_sha256": digest, "dispatches": len(vals)})
+            rec[key] = float(np.mean(vals)) * 1024.0 * scale
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -278,7 +341,14 @@ def main():
                     help="also run one plain 256 MiB device copy (the counter calibration kernel)")
     ap.add_argument("--profile-ops", action="store_true",
                     help="also print the per-operation times of the update's chain (stderr)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DB", "WRITE_DB"),
+                    help="host only: store the contraction kernels' HBM traffic from two rocprofv3 --pmc databases "
+                         "(FETCH_SIZE, WRITE_SIZE) of a --copy-calibration run, then exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        spec, _ = make_workload(args.workload, None)
+        write_traffic(args.traffic_from[0], args.traffic_from[1], spec.name, args.compute)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU only: every stream's update runs on a single device and this build "
               "has no multi-GPU path; run with --gpus 1.", file=sys.stderr)
@@ -338,6 +408,9 @@ def main():
     # the passes inside the update, and optionally the chain's operations
     sp = TTStream(spec.modes, spec.ranks, init=(cores, g), profile_ops=True, compute=args.compute, autotune=tune)
     kt = time_passes_in_update(sp, pool, args.kernel_reps)
+    # the pass kernels alone, launched back to back over the resident frames
+    # (HIP events around the whole run on the stream that launches them)
+    kb = sp.time_passes(pool, reps=args.kernel_reps)
     if args.profile_ops:
         prof = sp.op_profile()
         tot = sum(p[2] for p in prof)
@@ -346,11 +419,18 @@ def main():
             log(f"  op {i:3d} {kind:6s} m={dims[0]:6d} n={dims[1]:6d} k={dims[2]:6d} {us:9.2f} us")
     sp.close()
     b1, b2 = pass_bytes(P, J, r, 2 if args.compute == "bf16" else 4)
-    gbs1 = b1 / (kt["pass1"] * 1e-3) / 1e9
-    gbs2 = b2 / (kt["pass2"] * 1e-3) / 1e9
-    log(f"pass1 {kt['pass1']*1e3:.1f} us {gbs1:.0f} GB/s; pass2 {kt['pass2']*1e3:.1f} us {gbs2:.0f} GB/s")
-    dom = "pass1" if kt["pass1"] >= kt["pass2"] else "pass2"
-    achieved = gbs1 if dom == "pass1" else gbs2
+    gb = {key: (b1 if key.startswith("pass1") else b2) / (ms * 1e-3) / 1e9 for key, ms in kt.items()}
+    log(f"in the update (events around each pass): pass1 {kt['pass1']*1e3:.1f} us (contraction kernel "
+        f"{kt['pass1_kernel']*1e3:.1f} us), pass2 {kt['pass2']*1e3:.1f} us (contraction kernel "
+        f"{kt['pass2_kernel']*1e3:.1f} us)")
+    log(f"back to back: pass1 contraction {kb['pass1_kernel']:.2f} us + reduction {kb['pass1_reduce']:.2f} us; "
+        f"pass2 contraction {kb['pass2_kernel']:.2f} us + reduction {kb['pass2_reduce']:.2f} us")
+    # the dominant kernel: the slower of the two contraction kernels
+    dom = "pass1" if kb["pass1_kernel"] >= kb["pass2_kernel"] else "pass2"
+    kname = ("k_pass1" if dom == "pass1" else "k_pass2") + ("b" if args.compute == "bf16" else "")
+    dom_bytes = b1 if dom == "pass1" else b2
+    achieved = dom_bytes / (kb[dom + "_kernel"] * 1e-6) / 1e9
+    traffic = measured_traffic(spec.name, args.compute, kname)
 
     if args.copy_calibration:
         # a plain copy of known size: rocprofv3's FETCH_SIZE / WRITE_SIZE of this
@@ -401,10 +481,15 @@ def main():
         },
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "device_last": dev_ms},
-        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
-        "slice_kernels": {"pass1_us": kt["pass1"] * 1e3, "pass1_gbs": gbs1, "pass1_bytes": b1,
-                          "pass2_us": kt["pass2"] * 1e3, "pass2_gbs": gbs2, "pass2_bytes": b2},
+        "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": dom_bytes,
+                     "kernel_us": kb[dom + "_kernel"]},
+        "slice_kernels": {"pass1_bytes": b1, "pass2_bytes": b2,
+                          "back_to_back_us": kb,
+                          "back_to_back_gbs": {"pass1_kernel": b1 / (kb["pass1_kernel"] * 1e-6) / 1e9,
+                                               "pass2_kernel": b2 / (kb["pass2_kernel"] * 1e-6) / 1e9},
+                          "in_update_us": {key: ms * 1e3 for key, ms in kt.items()},
+                          "in_update_gbs": gb},
         "batched": batched,
         "serving": serving,
         "cpu_baseline": cpu,

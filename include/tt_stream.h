@@ -184,12 +184,30 @@ tt_status tt_stream_last_push_ms(tt_stream* s, float* ms);
 tt_status tt_stream_op_profile(tt_stream* s, int64_t cap, int32_t* kinds, int64_t* dims, double* us,
                                int64_t* count);
 
-/* Device times of the two slice passes of the last push (HIP events recorded
- * on the handle's stream around each pass's launches; pass 1 includes its
- * partial-tile reduction), for a stream created with TT_FLAG_PROFILE_OPS.
- * Waits for the handle's work.  Errors: INVALID_ARG (null), STATE (flag not
- * set or no push yet). */
-tt_status tt_stream_pass_profile(tt_stream* s, float* pass1_ms, float* pass2_ms);
+/* Device times in milliseconds of the two slice passes of the last push, for
+ * a stream created with TT_FLAG_PROFILE_OPS, from HIP events recorded on the
+ * handle's stream: ms[0] pass 1's contraction kernel alone, ms[1] the whole
+ * of pass 1 (with its partial-tile reduction), ms[2] and ms[3] the same for
+ * pass 2 (equal when the pass is a single kernel).  ms: caller array of 4
+ * floats.  Waits for the handle's work.  Errors: INVALID_ARG (null), STATE
+ * (flag not set or no push yet). */
+tt_status tt_stream_pass_profile(tt_stream* s, float* ms);
+
+/* Average device time per launch, in microseconds, of the handle's slice-pass
+ * kernels (the contractions of Section 4.2 at the split point, with the
+ * interfaces of the last update): each kernel is launched `reps` times back
+ * to back on the handle's stream between two HIP events, after one untimed
+ * launch, launch i reading slices[i % nslices] (several resident slices keep
+ * the reads out of the caches).  us[0] pass 1's contraction kernel, us[1] its
+ * partial-tile reduction, us[2] pass 2's contraction kernel, us[3] its
+ * reduction (about 0 when the pass has none).  slices: nslices device
+ * pointers, layout and dtype as for tt_stream_push_slice.  The passes'
+ * outputs are per-update scratch and the state is not changed; waits for the
+ * handle's work.  us: caller array of 4 floats.  Errors: INVALID_ARG (null,
+ * nslices < 1, bad dtype, reps outside 1..100000), STATE (no push yet),
+ * DEVICE. */
+tt_status tt_stream_time_passes(tt_stream* s, const void* const* slices, int32_t nslices, tt_dtype dtype,
+                                int32_t reps, float* us);
 
 /* Description of the calling thread's last error (never NULL). */
 const char* tt_last_error_string(void);

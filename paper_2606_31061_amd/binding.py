@@ -92,7 +92,8 @@ def load_library(path: str = LIB_PATH):
         "tt_stream_last_push_ms": (c_int, [sv, POINTER(c_float)]),
         "tt_stream_op_profile": (c_int, [sv, c_int64, POINTER(c_int32), POINTER(c_int64), POINTER(c_double),
                                          POINTER(c_int64)]),
-        "tt_stream_pass_profile": (c_int, [sv, POINTER(c_float), POINTER(c_float)]),
+        "tt_stream_pass_profile": (c_int, [sv, POINTER(c_float)]),
+        "tt_stream_time_passes": (c_int, [sv, POINTER(c_void_p), c_int32, c_int, c_int32, POINTER(c_float)]),
         "tt_last_error_string": (c_char_p, []),
         "tt_version": (c_char_p, []),
         "tt_batch_create": (c_int, [POINTER(c_void_p), c_int32, sv, POINTER(c_void_p)]),
@@ -343,10 +344,26 @@ class TTStream:
         return [(names.get(kinds[i], "?"), (dims[3 * i], dims[3 * i + 1], dims[3 * i + 2]), us[i]) for i in range(n)]
 
     def pass_profile(self):
-        """(pass 1 ms, pass 2 ms) of the last push (needs profile_ops=True)."""
-        a, b = c_float(), c_float()
-        _check(self._lib.tt_stream_pass_profile(self._h, byref(a), byref(b)), "tt_stream_pass_profile")
-        return a.value, b.value
+        """Device ms of the last push's slice passes (needs profile_ops=True):
+        dict with pass1_kernel, pass1, pass2_kernel, pass2 (the contraction
+        kernel alone, and the whole pass with its reduction)."""
+        ms = (c_float * 4)()
+        _check(self._lib.tt_stream_pass_profile(self._h, ms), "tt_stream_pass_profile")
+        return {"pass1_kernel": ms[0], "pass1": ms[1], "pass2_kernel": ms[2], "pass2": ms[3]}
+
+    def time_passes(self, xs, reps: int = 50):
+        """Average device us per launch of the slice-pass kernels, launched
+        reps times back to back on the device slices xs (cycled): dict with
+        pass1_kernel, pass1_reduce, pass2_kernel, pass2_reduce."""
+        xs = list(xs)
+        for x in xs:
+            if not x.is_cuda or not x.is_contiguous() or x.numel() != self.n:
+                raise ValueError("device slices must be contiguous CUDA tensors with N elements")
+        ptrs = (c_void_p * len(xs))(*[x.data_ptr() for x in xs])
+        us = (c_float * 4)()
+        _check(self._lib.tt_stream_time_passes(self._h, ptrs, len(xs), _dtype_code_torch(xs[0]), int(reps), us),
+               "tt_stream_time_passes")
+        return {"pass1_kernel": us[0], "pass1_reduce": us[1], "pass2_kernel": us[2], "pass2_reduce": us[3]}
 
     def close(self) -> None:
         if self._h is not None and self._h.value:

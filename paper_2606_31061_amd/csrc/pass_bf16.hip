@@ -491,6 +491,7 @@ __global__ void __launch_bounds__(256) k_reduceb(const float* __restrict__ ws, i
 template <int PASS, int VEC, int NTN>
 hipError_t launch_reduce(hipStream_t st, const PassBPlan& pl, int64_t P, int64_t J, int r, double* out,
                          const void* ws, int* flag, const PassLaunch* bl) {
+  if (!(pass_launch_mask() & 2)) return hipSuccess;
   if (!bl && pl.chunks == 1) return hipSuccess;
   if (bl && bl->grx == 0) return hipSuccess;  // no member splits its reduction
   constexpr int TILEF = NTN * VEC * 1024;
@@ -508,9 +509,12 @@ hipError_t launch_p1b(hipStream_t st, const T* X, const PassBPlan& pl, int64_t P
   unsigned gx, grx;
   pass1b_grids(pl, &gx, &grx);
   if (bl) gx = bl->gx;
-  hipLaunchKernelGGL((k_pass1b<T, VEC, NW, NTN>), dim3(gx, bl ? (unsigned)bl->n : 1u), dim3(NW * 64), 0, st, X, P, J,
-                     r, B, static_cast<float*>(ws), Z, flag, pl.tiles, pl.chunks, bl ? bl->desc : nullptr);
-  const hipError_t e = hipGetLastError();
+  if (pass_launch_mask() & 1)
+    hipLaunchKernelGGL((k_pass1b<T, VEC, NW, NTN>), dim3(gx, bl ? (unsigned)bl->n : 1u), dim3(NW * 64), 0, st, X, P,
+                       J, r, B, static_cast<float*>(ws), Z, flag, pl.tiles, pl.chunks, bl ? bl->desc : nullptr);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (hipEvent_t m = pass_mid_event()) e = hipEventRecord(m, st);
   if (e != hipSuccess) return e;
   return launch_reduce<1, VEC, NTN>(st, pl, P, J, r, Z, ws, flag, bl);
 }
@@ -544,7 +548,8 @@ hipError_t p2b_nw(hipStream_t st, const T* X, const PassBPlan& pl, int64_t P, in
   const PassDesc* bt = bl ? bl->desc : nullptr;
   float* w = static_cast<float*>(ws);
   const bool vx = pass2b_vx(P);
-  if (pl.ntn == 1) {
+  if (!(pass_launch_mask() & 1)) {
+  } else if (pl.ntn == 1) {
     if (vx)
       hipLaunchKernelGGL((k_pass2b<T, NW, 1, true>), grid, block, 0, st, X, P, J, r, A, w, Y, flag, pl.tiles,
                          pl.chunks, bt);
@@ -561,7 +566,9 @@ hipError_t p2b_nw(hipStream_t st, const T* X, const PassBPlan& pl, int64_t P, in
   } else {
     return hipErrorInvalidValue;
   }
-  const hipError_t e = hipGetLastError();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (hipEvent_t m = pass_mid_event()) e = hipEventRecord(m, st);
   if (e != hipSuccess) return e;
   if (pl.ntn == 1) return launch_reduce<2, 1, 1>(st, pl, P, J, r, Y, ws, flag, bl);
   return launch_reduce<2, 1, 2>(st, pl, P, J, r, Y, ws, flag, bl);

@@ -509,9 +509,16 @@ hipError_t launch_p1(hipStream_t st, const T* X, int64_t P, int64_t J, int r, co
   const unsigned grx = bl ? bl->grx : (unsigned)((threads + kRedElems - 1) / kRedElems);
   const unsigned nb = bl ? (unsigned)bl->n : 1u;
   const PassDesc* d = bl ? bl->desc : nullptr;
-  hipLaunchKernelGGL((k_pass1<T, VEC, NW, NTN>), dim3(gx, nb), dim3(NW * 64), 0, st, X, P, J, r, B, ws, tiles, chunks,
-                     d);
-  hipLaunchKernelGGL((k_pass1_reduce<VEC, NTN>), dim3(grx, nb), dim3(256), 0, st, ws, chunks, P, r, Z, flag, d);
+  const int mask = pass_launch_mask();
+  if (mask & 1)
+    hipLaunchKernelGGL((k_pass1<T, VEC, NW, NTN>), dim3(gx, nb), dim3(NW * 64), 0, st, X, P, J, r, B, ws, tiles,
+                       chunks, d);
+  if (hipEvent_t m = pass_mid_event()) {
+    const hipError_t e = hipEventRecord(m, st);
+    if (e != hipSuccess) return e;
+  }
+  if (mask & 2)
+    hipLaunchKernelGGL((k_pass1_reduce<VEC, NTN>), dim3(grx, nb), dim3(256), 0, st, ws, chunks, P, r, Z, flag, d);
   return hipGetLastError();
 }
 
@@ -545,10 +552,16 @@ hipError_t pass2_v(hipStream_t st, const T* X, int64_t P, int64_t J, int r, cons
   const dim3 grid(bl ? bl->gx : pass2_grid(J), bl ? (unsigned)bl->n : 1u);
   const PassDesc* bt = bl ? bl->desc : nullptr;
   const dim3 block(kPass2Waves * 64);
-  if (r <= 32)
+  if (!(pass_launch_mask() & 1))
+    ;
+  else if (r <= 32)
     hipLaunchKernelGGL((k_pass2<T, VEC, 1>), grid, block, lds, st, X, P, J, r, A, Y, flag, (int)slab, nchunk, bt);
   else
     hipLaunchKernelGGL((k_pass2<T, VEC, 2>), grid, block, lds, st, X, P, J, r, A, Y, flag, (int)slab, nchunk, bt);
+  if (hipEvent_t m = pass_mid_event()) {
+    const hipError_t e = hipEventRecord(m, st);
+    if (e != hipSuccess) return e;
+  }
   return hipGetLastError();
 }
 
@@ -565,6 +578,16 @@ hipError_t attr2(int lds) {
 }
 
 }  // namespace
+
+hipEvent_t& pass_mid_event() {
+  thread_local hipEvent_t ev = nullptr;
+  return ev;
+}
+
+int& pass_launch_mask() {
+  thread_local int mask = 3;
+  return mask;
+}
 
 Pass1Plan pass1_plan(int64_t P, int64_t J, int r, int cus) {
   Pass1Plan pl;

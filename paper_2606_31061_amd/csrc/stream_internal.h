@@ -94,7 +94,9 @@ struct tt_stream {
   int rejected_seen = 0;
   int64_t pushes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evcopy = nullptr;
-  hipEvent_t evpass[4] = {};  // around pass 1 and pass 2 (TT_FLAG_PROFILE_OPS)
+  // TT_FLAG_PROFILE_OPS: per pass, before it, after its contraction kernel,
+  // after its reduction (pass 1: 0, 1, 2; pass 2: 3, 4, 5)
+  hipEvent_t evpass[6] = {};
   bool timed = false;
 
   double* g_of(double* st) const { return st + coff[m + 1]; }

@@ -157,6 +157,16 @@ hipError_t pass1(hipStream_t st, const void* X, tt_dtype xdt, const Pass1Plan& p
                  const float* B, double* Z, float* ws, int* flag, const PassLaunch* bl = nullptr);
 void pass1_grids(const Pass1Plan& plan, int64_t P, unsigned* gx, unsigned* grx);
 
+// When set (not null), the pass launchers record this event on their stream
+// right after a pass's contraction kernel, before its partial-tile reduction
+// (or after the only kernel), so the contraction kernel can be timed alone.
+// Per calling thread; the runtime sets it around one pass and clears it.
+hipEvent_t& pass_mid_event();
+// Which kernels the pass launchers launch: bit 0 the contraction kernel, bit
+// 1 the partial-tile reduction (default 3).  Per calling thread; only the
+// pass timer changes it (to launch either kernel alone, back to back).
+int& pass_launch_mask();
+
 // Pass 2: Y(a,j) = sum_p A(p,a) X(p,j); A P x r FP32 column-major; Y FP64
 // r x J column-major.  Sets *flag if Y non-finite.
 hipError_t pass2(hipStream_t st, const void* X, tt_dtype xdt, int64_t P, int64_t J, int r,

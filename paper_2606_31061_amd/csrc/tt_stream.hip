@@ -508,8 +508,8 @@ void build_plan(tt_stream* s, int par) {
 }
 
 // Runs the steps of plan P of stream s with slice X.  trace (if not null)
-// receives two stamps per chain operation; pass_ev (if not null) four events
-// around the two passes.
+// receives two stamps per chain operation; pass_ev (if not null) three events
+// per pass: before it, after its contraction kernel, after its reduction.
 tt_status run_steps(hipStream_t st, const tt_stream* s, const UpdatePlan& P, const void* X, tt_dtype xdt,
                     int64_t* trace, hipEvent_t const* pass_ev = nullptr) {
   const int ks = s->kstar;
@@ -524,24 +524,32 @@ tt_status run_steps(hipStream_t st, const tt_stream* s, const UpdatePlan& P, con
         TT_HIP(ttk::gemm64_ops(st, P.opptr + step.first, 1, ttk::gemm64_blocks(o.m, o.n, o.k)));
         break;
       }
-      case kStepPass1:
+      case kStepPass1: {
         if (pass_ev) TT_HIP(hipEventRecord(pass_ev[0], st));
-        if (s->compute == TT_BF16)
-          TT_HIP(ttk::pass1_bf16(st, X, xdt, s->p1b, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->B32, s->Z, s->ws,
-                                 s->flag));
-        else
-          TT_HIP(ttk::pass1(st, X, xdt, s->p1, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->B32, s->Z, s->ws, s->flag));
-        if (pass_ev) TT_HIP(hipEventRecord(pass_ev[1], st));
-        break;
-      case kStepPass2:
+        ttk::pass_mid_event() = pass_ev ? pass_ev[1] : nullptr;
+        const hipError_t e =
+            s->compute == TT_BF16
+                ? ttk::pass1_bf16(st, X, xdt, s->p1b, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->B32, s->Z, s->ws,
+                                  s->flag)
+                : ttk::pass1(st, X, xdt, s->p1, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->B32, s->Z, s->ws, s->flag);
+        ttk::pass_mid_event() = nullptr;
+        TT_HIP(e);
         if (pass_ev) TT_HIP(hipEventRecord(pass_ev[2], st));
-        if (s->compute == TT_BF16)
-          TT_HIP(ttk::pass2_bf16(st, X, xdt, s->p2b, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->A32, s->Y[0], s->ws2,
-                                 s->flag));
-        else
-          TT_HIP(ttk::pass2(st, X, xdt, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->A32, s->Y[0], s->flag));
-        if (pass_ev) TT_HIP(hipEventRecord(pass_ev[3], st));
         break;
+      }
+      case kStepPass2: {
+        if (pass_ev) TT_HIP(hipEventRecord(pass_ev[3], st));
+        ttk::pass_mid_event() = pass_ev ? pass_ev[4] : nullptr;
+        const hipError_t e =
+            s->compute == TT_BF16
+                ? ttk::pass2_bf16(st, X, xdt, s->p2b, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->A32, s->Y[0], s->ws2,
+                                  s->flag)
+                : ttk::pass2(st, X, xdt, s->Pk[ks], s->Jk[ks], (int)s->r[ks], s->A32, s->Y[0], s->flag);
+        ttk::pass_mid_event() = nullptr;
+        TT_HIP(e);
+        if (pass_ev) TT_HIP(hipEventRecord(pass_ev[5], st));
+        break;
+      }
       default:
         return fail(TT_ERR_DEVICE, "corrupt update plan");
     }
@@ -960,14 +968,64 @@ tt_status tt_stream_op_profile(tt_stream* s, int64_t cap, int32_t* kinds, int64_
   return TT_OK;
 }
 
-tt_status tt_stream_pass_profile(tt_stream* s, float* pass1_ms, float* pass2_ms) {
-  if (!valid(s) || !pass1_ms || !pass2_ms) return fail(TT_ERR_INVALID_ARG, "null argument");
+tt_status tt_stream_pass_profile(tt_stream* s, float* ms) {
+  if (!valid(s) || !ms) return fail(TT_ERR_INVALID_ARG, "null argument");
   if (!s->evpass[0]) return fail(TT_ERR_STATE, "stream was not created with TT_FLAG_PROFILE_OPS");
   if (s->traced_plan < 0) return fail(TT_ERR_STATE, "no push yet");
-  TT_HIP(hipEventSynchronize(s->evpass[3]));
-  TT_HIP(hipEventElapsedTime(pass1_ms, s->evpass[0], s->evpass[1]));
-  TT_HIP(hipEventElapsedTime(pass2_ms, s->evpass[2], s->evpass[3]));
+  TT_HIP(hipEventSynchronize(s->evpass[5]));
+  TT_HIP(hipEventElapsedTime(ms + 0, s->evpass[0], s->evpass[1]));
+  TT_HIP(hipEventElapsedTime(ms + 1, s->evpass[0], s->evpass[2]));
+  TT_HIP(hipEventElapsedTime(ms + 2, s->evpass[3], s->evpass[4]));
+  TT_HIP(hipEventElapsedTime(ms + 3, s->evpass[3], s->evpass[5]));
   return TT_OK;
+}
+
+tt_status tt_stream_time_passes(tt_stream* s, const void* const* slices, int32_t nslices, tt_dtype dtype,
+                                int32_t reps, float* us) {
+  if (!valid(s) || !slices || !us) return fail(TT_ERR_INVALID_ARG, "null argument");
+  if (nslices < 1) return fail(TT_ERR_INVALID_ARG, "no slices");
+  for (int32_t i = 0; i < nslices; ++i)
+    if (!slices[i]) return fail(TT_ERR_INVALID_ARG, "null slice");
+  if (dtype != TT_F64 && dtype != TT_F32 && dtype != TT_BF16) return fail(TT_ERR_INVALID_ARG, "bad dtype");
+  if (reps < 1 || reps > 100000) return fail(TT_ERR_INVALID_ARG, "reps out of range");
+  if (s->pushes == 0) return fail(TT_ERR_STATE, "no push yet");
+  const int ks = s->kstar;
+  const int64_t P = s->Pk[ks], J = s->Jk[ks];
+  const int r = (int)s->r[ks];
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  tt_status st = TT_OK;
+  auto pass = [&](int which, int i) -> hipError_t {
+    const void* slice = slices[i % nslices];
+    if (which == 1)
+      return s->compute == TT_BF16
+                 ? ttk::pass1_bf16(s->stream, slice, dtype, s->p1b, P, J, r, s->B32, s->Z, s->ws, s->flag)
+                 : ttk::pass1(s->stream, slice, dtype, s->p1, P, J, r, s->B32, s->Z, s->ws, s->flag);
+    return s->compute == TT_BF16
+               ? ttk::pass2_bf16(s->stream, slice, dtype, s->p2b, P, J, r, s->A32, s->Y[0], s->ws2, s->flag)
+               : ttk::pass2(s->stream, slice, dtype, P, J, r, s->A32, s->Y[0], s->flag);
+  };
+  hipError_t e = hipEventCreate(&e0);
+  if (e == hipSuccess) e = hipEventCreate(&e1);
+  for (int q = 0; q < 4 && e == hipSuccess; ++q) {
+    ttk::pass_launch_mask() = 1 + (q & 1);  // contraction kernel, then reduction
+    e = pass(1 + q / 2, 0);                 // warm launch
+    if (e == hipSuccess) e = hipEventRecord(e0, s->stream);
+    for (int i = 0; i < reps && e == hipSuccess; ++i) e = pass(1 + q / 2, i + 1);
+    if (e == hipSuccess) e = hipEventRecord(e1, s->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    us[q] = ms * 1000.f / (float)reps;
+  }
+  ttk::pass_launch_mask() = 3;
+  // the passes' outputs are per-update scratch; the flag is zero between
+  // updates (the commit clears it) and may have been set by a timed launch
+  if (e == hipSuccess) e = hipMemsetAsync(s->flag, 0, sizeof(int), s->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) st = fail(TT_ERR_DEVICE, hipGetErrorString(e));
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return st;
 }
 
 tt_status tt_stream_destroy(tt_stream* s) {

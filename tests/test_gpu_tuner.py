@@ -62,3 +62,37 @@ def test_tuned_streams_batch_bitwise_and_groups():
     M_0 = ttals.reconstruct(c0, g0)
     assert np.linalg.norm(M_u - M_0) <= 1e-5 * np.linalg.norm(M_0)
     batch.close()
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+def test_pass_profile_times_the_passes(compute):
+    """TT_FLAG_PROFILE_OPS: the slice passes' events give positive times, the
+    contraction kernel alone no longer than its whole pass, and neither
+    profiling nor the back-to-back pass timer changes the updates (bitwise
+    equal to an unprofiled stream)."""
+    torch = torch_cuda()
+    from paper_2606_31061_amd import TTStream
+    st = exact_tt_stream((48, 40, 3), (8, 8, 3), (8, 8, 3), 2, 1501, 1601, sigma=1e-2)
+    dt = torch.bfloat16 if compute == "bf16" else torch.float32
+    xs = [to_device_slice(torch, X, dt) for X in st.frames(1, 2)]
+    say(f"pass profile {compute}")
+    a = TTStream(st.modes, st.ranks, init=st.init(), compute=compute, profile_ops=True)
+    b = TTStream(st.modes, st.ranks, init=st.init(), compute=compute)
+    for x in xs:
+        a.push(x)
+        b.push(x)
+        p = a.pass_profile()
+        assert set(p) == {"pass1_kernel", "pass1", "pass2_kernel", "pass2"}
+        assert 0.0 < p["pass1_kernel"] <= p["pass1"] and 0.0 < p["pass2_kernel"] <= p["pass2"]
+    # timing the pass kernels back to back leaves the state and the next
+    # update unchanged
+    t = a.time_passes(xs, reps=3)
+    assert set(t) == {"pass1_kernel", "pass1_reduce", "pass2_kernel", "pass2_reduce"}
+    assert t["pass1_kernel"] > 0.0 and t["pass2_kernel"] > 0.0
+    a.push(xs[1])
+    b.push(xs[1])
+    ca, ga, _ = a.get_state()
+    cb, gb, _ = b.get_state()
+    assert all(np.array_equal(x, y) for x, y in zip(ca, cb)) and np.array_equal(ga, gb)
+    a.close()
+    b.close()
