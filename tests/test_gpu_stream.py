@@ -82,14 +82,17 @@ def test_c2_video_stream_parity_prefix():
     s.close()
 
 
-def test_c3_full_size_parity_first_slices():
+@pytest.mark.parametrize("autotune", [False, True])
+def test_c3_full_size_parity_first_slices(autotune):
+    """Config 3 at full size, with the default pass plans and with the tuned
+    ones (the launch configuration bench.py times)."""
     st = config_c3(T=500)
     init = st.init()
     slices = list(st.frames(1, 3))
-    say("c3 order-9 6.2M-element slices, 3 frames")
+    say(f"c3 order-9 6.2M-element slices, 3 frames, autotune={autotune}")
     torch = torch_cuda()
     from paper_2606_31061_amd import TTStream
-    s = TTStream(st.modes, st.ranks, init=init)
+    s = TTStream(st.modes, st.ranks, init=init, autotune=autotune)
     assert s.info()["split_point"] == 3
     c, g = init
     for t, X in enumerate(slices, start=1):
