@@ -103,7 +103,10 @@ typedef struct {
 /* TT_FLAG_AUTOTUNE: at create, time candidate launch shapes of the two slice
  * passes for this stream's shape and precision (once per process and shape,
  * on hip_stream, which is synchronised) and use the fastest; streams of one
- * shape then share the plan, alone or in a batch. */
+ * shape then share the plan, alone or in a batch.  With split_point = 0 (and
+ * without TT_FLAG_NO_ORTHO) it also picks k*: up to three split points whose
+ * modelled side traffic (P_k + J_k) r_k is within 4x of the smallest are timed
+ * with their tuned passes, and the fastest is used. */
 #define TT_FLAG_AUTOTUNE 0x8u
 
 /* Create a stream.  The initial cores are the paper's random initialisation

@@ -5,7 +5,9 @@
 // contraction precision by timing candidate shapes on the device once per
 // process; the result is cached, so every stream of that shape, alone or in
 // a batch, runs the same plan and computes the same bits.  The choice
-// depends only on the shape.
+// depends only on the shape.  The cached record also keeps the time of the
+// two passes with the chosen shapes, which the runtime compares across split
+// points.
 #include "tt_internal.h"
 
 #include <map>
@@ -139,7 +141,7 @@ bool tune(int64_t P, int64_t J, int r, tt_dtype compute, int cus, hipStream_t st
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) return false;
   bool ok = true;
-  float bt = 1e30f;
+  float bt = 1e30f, total = 0.f;
   for (const auto& p : c1) {
     const float ms = time_plan(st, e0, e1, [&] {
       return pass1(st, X, TT_F32, p, P, J, r, W1, Z, static_cast<float*>(W), flag);
@@ -150,6 +152,11 @@ bool tune(int64_t P, int64_t J, int r, tt_dtype compute, int cus, hipStream_t st
       best.p1 = p;
     }
   }
+  if (!bf16) {
+    const float ms = time_plan(st, e0, e1, [&] { return pass2(st, X, TT_F32, P, J, r, W2, Y, flag); });
+    if (ms < 0) ok = false;
+    total = bt + ms;
+  }
   bt = 1e30f;
   for (const auto& p : c1b) {
     const float ms = time_plan(st, e0, e1, [&] { return pass1_bf16(st, X, TT_BF16, p, P, J, r, W1, Z, W, flag); });
@@ -159,6 +166,7 @@ bool tune(int64_t P, int64_t J, int r, tt_dtype compute, int cus, hipStream_t st
       best.p1b = p;
     }
   }
+  if (bf16) total = bt;
   bt = 1e30f;
   for (const auto& p : c2b) {
     const float ms = time_plan(st, e0, e1, [&] { return pass2_bf16(st, X, TT_BF16, p, P, J, r, W2, Y, W, flag); });
@@ -168,6 +176,8 @@ bool tune(int64_t P, int64_t J, int r, tt_dtype compute, int cus, hipStream_t st
       best.p2b = p;
     }
   }
+  if (bf16) total += bt;
+  best.ms = total;
   (void)hipStreamSynchronize(st);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);

@@ -209,6 +209,7 @@ struct PassPlans {
   Pass1Plan p1;           // FP32 contractions
   PassBPlan p1b, p2b;     // BF16 contractions
   bool tuned = false;
+  float ms = 0.f;         // tuned: device time of pass 1 + pass 2 with these plans
 };
 PassPlans default_pass_plans(int64_t P, int64_t J, int r, int cus);
 // Plans of the fastest measured launch shapes for (P, J, r) and the given

@@ -179,6 +179,35 @@ int choose_split(const tt_stream* s) {
   return best;
 }
 
+// Split point with TT_FLAG_AUTOTUNE: the split points whose modelled pass
+// output (P_k + J_k) r_k is within a factor 4 of the smallest (at most three,
+// in model order) are timed with their tuned pass plans, and the one with the
+// fastest pair of passes wins (ties: the earlier in model order).  The pass
+// times are cached per shape, so the choice repeats within a process and
+// every stream of one shape gets the same split point.
+bool tune_split(tt_stream* s, int cus) {
+  std::vector<std::pair<double, int>> cand;
+  for (int k = 1; k <= s->m; ++k)
+    if (s->r[k] <= 64) cand.push_back({(double)(s->Pk[k] + s->Jk[k]) * (double)s->r[k], k});
+  if (cand.empty()) return true;
+  std::stable_sort(cand.begin(), cand.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+  float best = 0.f;
+  int bestk = -1, tried = 0;
+  for (const auto& [cost, k] : cand) {
+    if (tried == 3 || cost > 4.0 * cand[0].first) break;
+    ++tried;
+    ttk::PassPlans pl;
+    if (ttk::tuned_pass_plans(s->Pk[k], s->Jk[k], (int)s->r[k], s->compute, cus, s->stream, &pl) != hipSuccess)
+      return false;
+    if (bestk < 0 || pl.ms < best) {
+      best = pl.ms;
+      bestk = k;
+    }
+  }
+  if (bestk > 0) s->kstar = bestk;
+  return true;
+}
+
 void plan_chain(UpdatePlan& p, const ttk::ChainOp& op) {
   p.ops.push_back(op);
   const int idx = (int)p.ops.size() - 1;
@@ -652,6 +681,12 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
   if (ttk::pass_setup() != hipSuccess || ttk::chain_setup(s->lds_limit) != hipSuccess)
     return bail(TT_ERR_DEVICE, "kernel attribute setup failed");
 
+  int cus = 256;
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
+  if ((cfg->flags & TT_FLAG_AUTOTUNE) && cfg->split_point == 0 && !(s->flags & TT_FLAG_NO_ORTHO) &&
+      !tune_split(s, cus))
+    return bail(TT_ERR_DEVICE, "tuning the split point failed");
+
   const int m_ = m;
   const auto& I = s->I;
   const auto& r = s->r;
@@ -664,8 +699,6 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
   }
   for (int k = ks; k <= m_; ++k) ymax = std::max(ymax, r[k] * s->Jk[k]);
 
-  int cus = 256;
-  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, s->device);
   {
     ttk::PassPlans plans = ttk::default_pass_plans(s->Pk[ks], s->Jk[ks], (int)r[ks], cus);
     if ((cfg->flags & TT_FLAG_AUTOTUNE) &&

@@ -93,7 +93,8 @@ def test_c3_full_size_parity_first_slices(autotune):
     torch = torch_cuda()
     from paper_2606_31061_amd import TTStream
     s = TTStream(st.modes, st.ranks, init=init, autotune=autotune)
-    assert s.info()["split_point"] == 3
+    # the byte model picks k* = 3; the tuner times k* = 3 and 4 (within 4x)
+    assert s.info()["split_point"] in ((3, 4) if autotune else (3,))
     c, g = init
     for t, X in enumerate(slices, start=1):
         s.push(to_device_slice(torch, X))

@@ -96,3 +96,21 @@ def test_pass_profile_times_the_passes(compute):
     assert all(np.array_equal(x, y) for x, y in zip(ca, cb)) and np.array_equal(ga, gb)
     a.close()
     b.close()
+
+
+def test_tuner_picks_the_split_point_per_shape():
+    """With split_point = 0 the tuner picks k* among the modelled candidates;
+    two streams of one shape get the same k* (cached pass times), and an
+    explicit split point is kept."""
+    torch_cuda()
+    from paper_2606_31061_amd import TTStream
+    st = exact_tt_stream((24, 20, 16, 3), (6, 8, 6, 3), (6, 8, 6, 3), 2, 1701, 1801, sigma=1e-2)
+    say("tuned split point (24,20,16,3)")
+    a = TTStream(st.modes, st.ranks, init=st.init(), autotune=True)
+    b = TTStream(st.modes, st.ranks, init=st.init(), autotune=True)
+    c = TTStream(st.modes, st.ranks, init=st.init(), autotune=True, split_point=1)
+    ka, kb = a.info()["split_point"], b.info()["split_point"]
+    assert ka == kb and 1 <= ka <= len(st.modes)
+    assert c.info()["split_point"] == 1
+    for s in (a, b, c):
+        s.close()
