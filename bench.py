@@ -350,7 +350,7 @@ def main():
         write_traffic(args.traffic_from[0], args.traffic_from[1], spec.name, args.compute)
         return
     if args.gpus != 1:
-        print("bench.py measures one GPU only: every stream's update runs on a single device and this build "
+        print("bench.py measures one GPU only: every stream's update runs on a single device and the library "
               "has no multi-GPU path; run with --gpus 1.", file=sys.stderr)
         raise SystemExit(2)
 

@@ -10,66 +10,97 @@
 namespace ttk {
 namespace {
 
-// Split-K FP64 GEMM: KS consecutive lanes share one output element.
-__global__ void __launch_bounds__(256) k_gemm64(int64_t M, int64_t N, int64_t K, int ks,
-                                                const double* __restrict__ A, int64_t ars, int64_t acs,
-                                                const double* __restrict__ B, int64_t brs, int64_t bcs,
-                                                double* C, int64_t crs, int64_t ccs, float* C32) {
-  const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int q = (int)(gt % ks);
-  const int64_t out = gt / ks;
-  const bool valid = out < M * N;
-  const int64_t i = valid ? out % M : 0, j = valid ? out / M : 0;
-  double acc = 0.0;
-  if (valid) {
-    const double* a = A + i * ars;
-    const double* b = B + j * bcs;
-    for (int64_t k = q; k < K; k += ks) acc = fma(a[k * acs], b[k * brs], acc);
+// Depth groups of a wide product: a power of two from 1 to 16 with about 16
+// or more multiply-adds per group (a function of K only, the same on host
+// and device).  A block of kWideThreads threads owns kWideThreads / groups
+// consecutive outputs.
+constexpr int kWideThreads = 256;
+__host__ __device__ inline int depth_groups(int64_t K) {
+  int g = 1;
+  while (g < 16 && (int64_t)g * 32 <= K) g <<= 1;
+  return g;
+}
+
+// C = A B, element strides.  Thread t of a block takes output o = base + t %
+// OB (OB = 256 / groups) and the depth group t / OB (depths k = group,
+// group + groups, ...).  Consecutive outputs run along i when A is
+// column-major (ars == 1) and along j when it is not but B is row-major
+// (bcs == 1), so the threads of one depth group read a contiguous run of one
+// operand and one broadcast value of the other; when neither holds but an
+// operand is contiguous along the depth (acs == 1 or brs == 1), thread t
+// takes depth group t % groups of output t / groups instead, so consecutive
+// threads read consecutive depths.  Each thread keeps sixteen
+// loads per operand in flight (predicated at the end of its depths) and two
+// accumulators; the groups' sums are added in group
+// order through LDS, so the result depends on the shape only.  The block
+// returns as a whole when it is past the outputs (no thread reaches the
+// barrier alone).
+__device__ __forceinline__ void wide_gemm(int64_t M, int64_t N, int64_t K, const double* A, int64_t ars,
+                                          int64_t acs, const double* B, int64_t brs, int64_t bcs, double* C,
+                                          int64_t crs, int64_t ccs, float* C32) {
+  __shared__ double red[kWideThreads];
+  const int G = depth_groups(K), OB = kWideThreads / G;
+  const int64_t nout = M * N;
+  const int64_t base = (int64_t)blockIdx.x * OB;
+  if (base >= nout) return;
+  // neither operand contiguous along an output index but one along the
+  // depth: consecutive threads take consecutive depths instead
+  const bool kfast = ars != 1 && bcs != 1 && (acs == 1 || brs == 1);
+  const int t = threadIdx.x, ol = kfast ? t / G : t % OB, g = kfast ? t % G : t / OB;
+  const int64_t o = base + ol;
+  const bool valid = o < nout;
+  const bool along_i = ars == 1 || bcs != 1;
+  const int64_t oc = valid ? o : nout - 1;
+  const int64_t i = along_i ? oc % M : oc / N, j = along_i ? oc / M : oc % N;
+  const double* a = A + i * ars + (int64_t)g * acs;
+  const double* b = B + j * bcs + (int64_t)g * brs;
+  const int64_t da = (int64_t)G * acs, db = (int64_t)G * brs;
+  const int64_t nk = K > g ? (K - g + G - 1) / G : 0;  // depths of this group
+  constexpr int U = 16;  // loads in flight per operand
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int64_t q = 0; q < nk; q += U) {
+    double x[U], y[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool in = q + u < nk;
+      x[u] = in ? a[u * da] : 0.0;
+      y[u] = in ? b[u * db] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; u += 2) {
+      acc0 = fma(x[u], y[u], acc0);
+      acc1 = fma(x[u + 1], y[u + 1], acc1);
+    }
+    a += U * da;
+    b += U * db;
   }
-  for (int o = ks >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if (valid && q == 0) {
-    if (C) C[i * crs + j * ccs] = acc;
-    if (C32) C32[i * crs + j * ccs] = (float)acc;
-  }
+  red[t] = acc0 + acc1;
+  __syncthreads();
+  if (g != 0 || !valid) return;
+  double sum = red[kfast ? ol * G : ol];
+  for (int gg = 1; gg < G; ++gg) sum += red[kfast ? ol * G + gg : ol + OB * gg];
+  if (C) C[i * crs + j * ccs] = sum;
+  if (C32) C32[i * crs + j * ccs] = (float)sum;
+}
+
+__global__ void __launch_bounds__(kWideThreads) k_gemm64(int64_t M, int64_t N, int64_t K, const double* A,
+                                                         int64_t ars, int64_t acs, const double* B, int64_t brs,
+                                                         int64_t bcs, double* C, int64_t crs, int64_t ccs,
+                                                         float* C32) {
+  wide_gemm(M, N, K, A, ars, acs, B, brs, bcs, C, crs, ccs, C32);
 }
 
 typedef const TT_CONSTANT_AS ChainOp ConstChainOp;
 typedef const TT_CONSTANT_AS uint64_t ConstWord;
 
-// Lanes sharing one output element: the depth split of an M x N x K product
-// (a function of K only, the same on host and device).
-__host__ __device__ inline int depth_split(int64_t K) {
-  int ks = 1;
-  while (ks < 64 && (int64_t)ks * 8 < K) ks <<= 1;
-  return ks;
-}
-
 // The same product for the GEMM *ops[blockIdx.y] of a batch; blocks past the
-// product's own grid return.  The op pointers and ops are read-only during
+// product's own outputs return.  The op pointers and ops are read-only during
 // the launch; reading them through the constant address space keeps the
 // descriptor in scalar registers.
-__global__ void __launch_bounds__(256) k_gemm64_ops(const ChainOp* const* __restrict__ ops) {
+__global__ void __launch_bounds__(kWideThreads) k_gemm64_ops(const ChainOp* const* __restrict__ ops) {
   const uint64_t addr = ((ConstWord*)(const void*)ops)[blockIdx.y];
   const ChainOp op = *(ConstChainOp*)addr;
-  const int64_t M = op.m, N = op.n, K = op.k;
-  const int ks = depth_split(K);
-  const int64_t gt = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  const int q = (int)(gt % ks);
-  const int64_t out = gt / ks;
-  if (blockIdx.x * (int64_t)blockDim.x >= M * N * ks) return;
-  const bool valid = out < M * N;
-  const int64_t i = valid ? out % M : 0, j = valid ? out / M : 0;
-  double acc = 0.0;
-  if (valid) {
-    const double* a = op.a + i * op.ars;
-    const double* b = op.b + j * op.bcs;
-    for (int64_t k = q; k < K; k += ks) acc = fma(a[k * op.acs], b[k * op.brs], acc);
-  }
-  for (int o = ks >> 1; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
-  if (valid && q == 0) {
-    if (op.c) op.c[i * op.crs + j * op.ccs] = acc;
-    if (op.c32) op.c32[i * op.crs + j * op.ccs] = (float)acc;
-  }
+  wide_gemm(op.m, op.n, op.k, op.a, op.ars, op.acs, op.b, op.brs, op.bcs, op.c, op.crs, op.ccs, op.c32);
 }
 
 __global__ void k_convert_out(const double* src, void* dst, int dt, int64_t n) {
@@ -88,29 +119,28 @@ inline unsigned grid_for(int64_t work, int threads, int64_t cap = 65536) {
 
 }  // namespace
 
+int64_t gemm64_blocks(int64_t M, int64_t N, int64_t K) {
+  if (M <= 0 || N <= 0) return 0;
+  const int64_t ob = kWideThreads / depth_groups(K);
+  return (M * N + ob - 1) / ob;
+}
+
 hipError_t gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K,
                   const double* A, int64_t ars, int64_t acs,
                   const double* B, int64_t brs, int64_t bcs,
                   double* C, int64_t crs, int64_t ccs, float* C32) {
   if (M <= 0 || N <= 0) return hipSuccess;
-  const int ks = depth_split(K);
-  const int64_t threads = M * N * ks;
-  const int64_t blocks = (threads + 255) / 256;
+  const int64_t blocks = gemm64_blocks(M, N, K);
   if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gemm64, dim3((unsigned)blocks), dim3(256), 0, st, M, N, K, ks, A, ars, acs, B, brs, bcs,
-                     C, crs, ccs, C32);
+  hipLaunchKernelGGL(k_gemm64, dim3((unsigned)blocks), dim3(kWideThreads), 0, st, M, N, K, A, ars, acs, B, brs,
+                     bcs, C, crs, ccs, C32);
   return hipGetLastError();
-}
-
-int64_t gemm64_blocks(int64_t M, int64_t N, int64_t K) {
-  if (M <= 0 || N <= 0) return 0;
-  return (M * N * depth_split(K) + 255) / 256;
 }
 
 hipError_t gemm64_ops(hipStream_t st, const ChainOp* const* ops_dev, int nops, int64_t gx) {
   if (nops == 0 || gx == 0) return hipSuccess;
   if (nops < 0 || nops > 65535 || gx > 0x7fffffff) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_gemm64_ops, dim3((unsigned)gx, nops), dim3(256), 0, st, ops_dev);
+  hipLaunchKernelGGL(k_gemm64_ops, dim3((unsigned)gx, nops), dim3(kWideThreads), 0, st, ops_dev);
   return hipGetLastError();
 }
 
