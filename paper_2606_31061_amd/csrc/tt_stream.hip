@@ -47,10 +47,13 @@ constexpr double kQrTol = 64.0 * 2.220446049250313e-16;
 // A contraction of at least kWideFma multiply-adds, or a deep one (depth at
 // least kWideDepth and kWideDeepFma multiply-adds: a long dot product per
 // output, bound by one workgroup's load latency), is launched over the whole
-// GPU instead of being run by the chain workgroup.
-constexpr double kWideFma = 1.0e6;
-constexpr int64_t kWideDepth = 2048;
-constexpr double kWideDeepFma = 6.5e4;
+// GPU instead of being run by the chain workgroup.  On MI355X a whole-GPU
+// launch costs about 5-6 us plus a few us where it splits the chain, while
+// the chain workgroup takes 20-35 us for products of 0.5-0.7 M multiply-adds
+// (staging and writing them through one CU), hence these thresholds.
+constexpr double kWideFma = 2.0e5;
+constexpr int64_t kWideDepth = 256;
+constexpr double kWideDeepFma = 3.0e4;
 
 thread_local std::string g_last_error = "no error";
 
