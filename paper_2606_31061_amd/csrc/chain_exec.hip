@@ -555,9 +555,15 @@ __device__ __forceinline__ void hh_factor(double* A, int m, int n, int lda, doub
   for (int j = 0; j < n; ++j) {
     double* cj = A + (int64_t)j * lda;
     double nrm = 0.0;
-    if (built >= rho && !need_r) {
-      // rank exhausted and R not wanted: the remaining columns are identity
-      // reflectors; only their tau is needed
+    if (built >= rho) {
+      // rank exhausted: every remaining column gets the identity reflector,
+      // which only zeroes that column from the diagonal down (R) and touches
+      // no other column, so all of them are done at once
+      if (need_r)
+        for (int c = j; c < n; ++c) {
+          double* cc = A + (int64_t)c * lda;
+          for (int i = c + tid; i < m; i += kCT) cc[i] = 0.0;
+        }
       for (int c = j + tid; c < n; c += kCT) tau[c] = 0.0;
       __syncthreads();
       return;
