@@ -539,6 +539,68 @@ struct Qr {
   double tol;
 };
 
+// Applies the reflector H_j = I - t v v^T (v_j = 1, v_i = A(i, j) below) to
+// columns j+1 .. n-1 of A, row-parallel, for tall matrices in device memory:
+// every thread owns rows.  Per block of at most 32 columns, one pass forms
+// the dot products v^T A(:, c), four columns at a time (one coalesced load
+// per column and row), each added lane-wise in the wave (fixed shuffle
+// order) and then in wave order through LDS (part: 17 x 33 doubles); a
+// second pass updates the block.  Few registers, so it sits next to the rest
+// of the chain without spilling.
+__device__ __forceinline__ void hh_apply_rows(double* A, int m, int n, int lda, int j, double t, double* part) {
+  const int tid = tix(), lane = tid & 63, wid = tid >> 6;
+  const double* cj = A + (int64_t)j * lda;
+  const int nc = n - j - 1;
+  if (nc <= 0) {  // still a barrier: the caller's thread-0 writes must land
+    __syncthreads();
+    return;
+  }
+  for (int cb = 0; cb < nc; cb += 32) {  // blocks of at most 32 columns
+    const int nb = nc - cb < 32 ? nc - cb : 32;
+    double* a0 = A + (int64_t)(j + 1 + cb) * lda;  // column j+1+cb
+    for (int q = 0; q < nb; q += 4) {
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int i = j + 1 + tid; i < m; i += kCT) {
+        const double vi = cj[i];
+        const double* row = a0 + i + (int64_t)q * lda;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          if (q + u < nb) acc[u] = fma(vi, row[(int64_t)u * lda], acc[u]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double d = wave_sum(acc[u]);
+        if (lane == 0 && q + u < nb) part[wid * 33 + q + u] = d;
+      }
+    }
+    __syncthreads();
+    if (tid < nb) {
+      double* a = a0 + j + (int64_t)tid * lda;
+      double d = *a;
+      for (int w = 0; w < kCW; ++w) d += part[w * 33 + tid];
+      const double tw = t * d;
+      part[kCW * 33 + tid] = tw;
+      *a -= tw;
+    }
+    __syncthreads();
+    const double* tw = part + kCW * 33;
+    for (int i = j + 1 + tid; i < m; i += kCT) {
+      const double vi = cj[i];
+      double* row = a0 + i;
+      int c = 0;
+      for (; c + 4 <= nb; c += 4) {
+        double x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = row[(int64_t)(c + u) * lda];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) row[(int64_t)(c + u) * lda] = fma(-tw[c + u], vi, x[u]);
+      }
+      for (; c < nb; ++c) row[(int64_t)c * lda] = fma(-tw[c], vi, row[(int64_t)c * lda]);
+    }
+    __syncthreads();
+  }
+}
+
 // Householder factorisation of the m x n column-major matrix A (leading
 // dimension lda) in place: R on and above the diagonal, the reflector vectors
 // (unit leading entry implied) below it, tau[j] their scalars,
@@ -549,7 +611,7 @@ struct Qr {
 // independent columns may be anywhere, so this counts reflectors, not
 // columns).
 __device__ __forceinline__ void hh_factor(double* A, int m, int n, int lda, double thr, int rho, bool need_r, double* tau,
-                          double* red) {
+                          double* red, bool rows_par) {
   const int tid = tix(), lane = tid & 63, wid = tid >> 6;
   int built = 0;
   for (int j = 0; j < n; ++j) {
@@ -594,6 +656,10 @@ __device__ __forceinline__ void hh_factor(double* A, int m, int n, int lda, doub
       cj[j] = beta;
       tau[j] = t;
     }
+    if (rows_par) {
+      hh_apply_rows(A, m, n, lda, j, t, s_lds + kLdsMs);
+      continue;
+    }
     for (int c = j + 1 + wid; c < n; c += kCW) {
       double* cc = A + (int64_t)c * lda;
       double d = (lane == 0) ? cc[j] : 0.0;
@@ -611,7 +677,8 @@ __device__ __forceinline__ void hh_factor(double* A, int m, int n, int lda, doub
 // (backward accumulation) and flips column j when sgn[j] < 0.  Columns with
 // the identity reflector (tau = 0) hold no reflector data, so they all become
 // unit vectors in one pass; each proper reflector then costs two barriers.
-__device__ __forceinline__ void hh_form_q(double* A, int m, int n, int lda, const double* tau, const double* sgn) {
+__device__ __forceinline__ void hh_form_q(double* A, int m, int n, int lda, const double* tau, const double* sgn,
+                                          bool rows_par) {
   const int tid = tix(), lane = tid & 63, wid = tid >> 6;
   for (int j = 0; j < n; ++j)
     if (tau[j] == 0.0) {
@@ -623,16 +690,20 @@ __device__ __forceinline__ void hh_form_q(double* A, int m, int n, int lda, cons
     const double t = tau[j];
     if (t == 0.0) continue;
     double* cj = A + (int64_t)j * lda;
-    for (int c = j + 1 + wid; c < n; c += kCW) {
-      double* cc = A + (int64_t)c * lda;
-      double d = (lane == 0) ? cc[j] : 0.0;
-      for (int i = j + 1 + lane; i < m; i += 64) d = fma(cj[i], cc[i], d);
-      d = wave_sum(d);
-      const double tw = t * d;
-      if (lane == 0) cc[j] -= tw;
-      for (int i = j + 1 + lane; i < m; i += 64) cc[i] = fma(-tw, cj[i], cc[i]);
+    if (rows_par) {
+      hh_apply_rows(A, m, n, lda, j, t, s_lds + kLdsMs);
+    } else {
+      for (int c = j + 1 + wid; c < n; c += kCW) {
+        double* cc = A + (int64_t)c * lda;
+        double d = (lane == 0) ? cc[j] : 0.0;
+        for (int i = j + 1 + lane; i < m; i += 64) d = fma(cj[i], cc[i], d);
+        d = wave_sum(d);
+        const double tw = t * d;
+        if (lane == 0) cc[j] -= tw;
+        for (int i = j + 1 + lane; i < m; i += 64) cc[i] = fma(-tw, cj[i], cc[i]);
+      }
+      __syncthreads();
     }
-    __syncthreads();
     for (int i = tid; i < m; i += kCT) {
       double v;
       if (i < j) v = 0.0;
@@ -665,14 +736,15 @@ __device__ __forceinline__ void householder_qr(const Qr& q, double* A, int lda) 
       p = fma(x, x, p);
     }
   const double fro = sqrt(block_sum(p, red));
-  hh_factor(A, m, n, lda, q.tol * fro, q.rho, q.R != nullptr, tau, red);
+  const bool rows_par = A == q.aux;  // tall: the matrix is in device memory
+  hh_factor(A, m, n, lda, q.tol * fro, q.rho, q.R != nullptr, tau, red, rows_par);
   for (int j = tid; j < n; j += kCT) sgn[j] = (tau[j] != 0.0 && A[j + (int64_t)j * lda] < 0.0) ? -1.0 : 1.0;
   __syncthreads();
   if (q.R) {
     for_each_ij(n, n, [&](int i, int j) { q.R[i + n * j] = (i <= j) ? sgn[i] * A[i + (int64_t)j * lda] : 0.0; });
   }
   __syncthreads();
-  hh_form_q(A, m, n, lda, tau, sgn);
+  hh_form_q(A, m, n, lda, tau, sgn, rows_par);
   for_each_ij(m, n, [&](int i, int j) { q.Q[i * q.qrs + j * q.qcs] = A[i + (int64_t)j * lda]; });
   __syncthreads();
 }

@@ -100,7 +100,8 @@ def test_passes_flag_nonfinite_slices():
 
 QR_CASES = [(8, 8, None), (72, 32, None), (480, 32, None), (512, 32, None), (96, 32, 1), (480, 32, 3),
             (32, 32, 1), (5120, 16, None), (5120, 16, 3), (1, 1, None), (300, 7, None), (16, 16, 0),
-            (513, 32, None), (7328, 32, None), (2049, 33, None), (4096, 32, 5), (1000, 1, None)]
+            (513, 32, None), (7328, 32, None), (2049, 33, None), (4096, 32, 5), (1000, 1, None),
+            (700, 48, None), (1500, 40, 7), (66, 40, None)]
 
 
 @pytest.mark.parametrize("m,n,rank", QR_CASES)
