@@ -568,7 +568,9 @@ hipError_t pass2_v(hipStream_t st, const T* X, int64_t P, int64_t J, int r, cons
 template <typename T>
 hipError_t pass2_t(hipStream_t st, const T* X, int64_t P, int64_t J, int r, const float* A, double* Y, int* flag,
                    const PassLaunch* bl) {
-  if (pass2_vec(P) == 4) return pass2_v<T, 4>(st, X, P, J, r, A, Y, flag, bl);
+  const int vec = pass2_vec(P);
+  if (vec == 4) return pass2_v<T, 4>(st, X, P, J, r, A, Y, flag, bl);
+  if (vec == 2) return pass2_v<T, 2>(st, X, P, J, r, A, Y, flag, bl);
   return pass2_v<T, 1>(st, X, P, J, r, A, Y, flag, bl);
 }
 
@@ -625,7 +627,7 @@ void pass1_grids(const Pass1Plan& pl, int64_t P, unsigned* gx, unsigned* grx) {
 }
 
 unsigned pass2_grid(int64_t J) { return (unsigned)((J + 31) / 32); }
-int pass2_vec(int64_t P) { return P % 4 == 0 ? 4 : 1; }
+int pass2_vec(int64_t P) { return P % 4 == 0 ? 4 : (P % 2 == 0 ? 2 : 1); }
 
 hipError_t pass1(hipStream_t st, const void* X, tt_dtype xdt, const Pass1Plan& pl, int64_t P, int64_t J, int r,
                  const float* B, double* Z, float* ws, int* flag, const PassLaunch* bl) {
@@ -654,6 +656,8 @@ hipError_t pass_setup() {
   hipError_t e = hipSuccess;
 #define TT_A2(T)                                    \
   if (e == hipSuccess) e = attr2<T, 4, 1>(lds);     \
+  if (e == hipSuccess) e = attr2<T, 2, 1>(lds);     \
+  if (e == hipSuccess) e = attr2<T, 2, 2>(lds);     \
   if (e == hipSuccess) e = attr2<T, 4, 2>(lds);     \
   if (e == hipSuccess) e = attr2<T, 1, 1>(lds);     \
   if (e == hipSuccess) e = attr2<T, 1, 2>(lds);

@@ -17,7 +17,7 @@ def _rng(s):
 
 
 CASES = [(32, 32, 4), (240, 960, 16), (1080, 5760, 32), (100, 77, 5), (33, 1, 8), (200, 300, 48),
-         (8, 777, 8), (4, 3, 1)]
+         (8, 777, 8), (4, 3, 1), (90, 70, 16), (6, 50, 3), (1090, 400, 40)]
 
 
 def _ref_round(X, dt):
