@@ -402,8 +402,17 @@ __global__ void __launch_bounds__(kPass2Waves * 64) k_pass2(const T* __restrict_
       const int e = lane + 64 * it;
       const int col = e / PER_COL, row = (e - col * PER_COL) * VEC;
       const bool colok = j0 + col < J;
+      if constexpr (VEC == 4) {  // one 16-byte LDS store (kLdp and row are multiples of 4)
+        f4 v;
+        v.x = (colok && row + 0 < rows) ? xr[it][0] : 0.f;
+        v.y = (colok && row + 1 < rows) ? xr[it][1] : 0.f;
+        v.z = (colok && row + 2 < rows) ? xr[it][2] : 0.f;
+        v.w = (colok && row + 3 < rows) ? xr[it][3] : 0.f;
+        *reinterpret_cast<f4*>(&Xs[col * kLdp + row]) = v;
+      } else {
 #pragma unroll
-      for (int s = 0; s < VEC; ++s) Xs[col * kLdp + row + s] = (colok && row + s < rows) ? xr[it][s] : 0.f;
+        for (int s = 0; s < VEC; ++s) Xs[col * kLdp + row + s] = (colok && row + s < rows) ? xr[it][s] : 0.f;
+      }
     }
   };
 
