@@ -48,7 +48,7 @@ constexpr int kCW = kCT / 64;
 constexpr int kLdsTotal = 20480;
 // GEMM: staged k-chunks of A and B, split-k partial blocks
 constexpr int kStageCap = 14336;
-constexpr int kLdsPart = 14336;     // 4096
+constexpr int kLdsPart = 14336;     // 4352 (4096 padded)
 // QR
 constexpr int kLdsRow = 0;          // 256: rows of R broadcast to the wave
 constexpr int kLdsRed = 256;        // 64: reductions
@@ -280,8 +280,14 @@ __device__ __forceinline__ void finish_direct(const Plan& p, int M, int N, const
   __syncthreads();
 }
 
+// Position of element x of finish_lds's buffer: one double of padding after
+// every 16, so that a walk along i (stride 16 in the block layout) spreads
+// over the LDS banks instead of hitting one.  The padded buffer holds at most
+// 64 blocks (17408 doubles).
+__device__ __forceinline__ int fpad(int x) { return x + (x >> 4); }
+
 // Finishes a product through LDS: each wave puts its block sums (or, with k
-// split, its partial block) in buf[((kg nb + b) 4 + v) 64 + l]; after a
+// split, its partial block) in buf[fpad(((kg nb + b) 4 + v) 64 + l)]; after a
 // barrier the threads walk the output with i fastest (ifast) or j fastest,
 // adding the k groups in order, so that consecutive threads store to
 // consecutive addresses.  Ends with a barrier.
@@ -298,13 +304,13 @@ __device__ __forceinline__ void finish_lds(const Plan& p, int M, int N, const v4
           if (q + f < 4 && f < p.P) s += acc[q + f < 4 ? q + f : 3];
         const int b = slot_blk(p, q);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) buf[(b * 4 + v) * 64 + lane] = s[v];
+        for (int v = 0; v < 4; ++v) buf[fpad((b * 4 + v) * 64 + lane)] = s[v];
       }
     }
   } else if (p.kg >= 0) {
     const v4d s = acc[0] + acc[1] + acc[2] + acc[3];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) buf[((p.kg * p.nb + p.sb) * 4 + v) * 64 + lane] = s[v];
+    for (int v = 0; v < 4; ++v) buf[fpad(((p.kg * p.nb + p.sb) * 4 + v) * 64 + lane)] = s[v];
   }
   __syncthreads();
   const int rows = 16 * p.nbm, total = p.nb * 256, cols = total / rows;
@@ -323,7 +329,7 @@ __device__ __forceinline__ void finish_lds(const Plan& p, int M, int N, const v4
       const int b = (i >> 4) + p.nbm * (j >> 4), il = i & 15, jl = j & 15;
       const int o = (b * 4 + (il >> 2)) * 64 + ((il & 3) << 4) + jl;
       double s = 0.0;
-      for (int g = 0; g < p.ks; ++g) s += buf[g * p.nb * 256 + o];
+      for (int g = 0; g < p.ks; ++g) s += buf[fpad(g * p.nb * 256 + o)];
       store(i, j, s);
     }
   }
@@ -394,6 +400,67 @@ __device__ __forceinline__ void stage(int dst, int drs, int dcs, int rows, int c
   }
 }
 
+// One operand walk of stage_pair: the same order and zero fill as stage, with
+// the LDS position of each loaded element kept beside it.
+struct StageWalk {
+  const double* src;
+  int64_t fs, ss;
+  int nf, df, ds, fv, sv, dfs, dss, total, dst;
+  int f, sl;
+  __device__ __forceinline__ StageWalk(int dst_, int drs, int dcs, int rows, int cols, const double* src_, int64_t rs,
+                                       int64_t cs, int r_valid, int c_valid) {
+    const bool rfast = rs <= cs;
+    src = src_;
+    nf = rfast ? rows : cols;
+    fv = rfast ? r_valid : c_valid;
+    sv = rfast ? c_valid : r_valid;
+    fs = rfast ? rs : cs;
+    ss = rfast ? cs : rs;
+    dfs = rfast ? drs : dcs;
+    dss = rfast ? dcs : drs;
+    df = kCT % nf;
+    ds = kCT / nf;
+    total = rows * cols;
+    dst = dst_;
+    f = tix() % nf;
+    sl = tix() / nf;
+  }
+  template <int U>
+  __device__ __forceinline__ void load(int e0, double (&x)[U], int (&o)[U]) {
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const bool in = e0 + u * kCT < total;
+      o[u] = in ? dst + f * dfs + sl * dss : -1;
+      x[u] = (in && f < fv && sl < sv) ? ((const TT_GLOBAL_AS double*)src)[f * fs + sl * ss] : 0.0;
+      f += df;
+      sl += ds;
+      if (f >= nf) {
+        f -= nf;
+        ++sl;
+      }
+    }
+  }
+};
+
+// stage() of both operands of a product: each round issues the loads of A
+// and of B before any LDS store, so that small operands cost one memory
+// latency instead of two.
+__device__ __forceinline__ void stage_pair(StageWalk a, StageWalk b) {
+  constexpr int U = 4;  // loads in flight per thread and operand
+  const int total = a.total > b.total ? a.total : b.total;
+  for (int e0 = tix(); e0 < total; e0 += U * kCT) {
+    double xa[U], xb[U];
+    int oa[U], ob[U];
+    a.load<U>(e0, xa, oa);
+    b.load<U>(e0, xb, ob);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (oa[u] >= 0) s_lds[oa[u]] = xa[u];
+      if (ob[u] >= 0) s_lds[ob[u]] = xb[u];
+    }
+  }
+}
+
 // C = A B from global operands.  The output is cut into tiles of at most
 // 64 blocks; for each tile the needed rows of A and columns of B go through
 // LDS one k-chunk at a time.
@@ -432,8 +499,8 @@ __device__ __forceinline__ void wg_gemm(const Gemm& g) {
         const int As = 0;            // Mp x kc, element (i, k) at i + Mp k
         const int Bs = Mp * kc;      // kc x Np, element (k, j) at j + Np k
         __syncthreads();
-        stage(As, 1, Mp, Mp, kc, Ag + (int64_t)4 * c0 * g.acs, g.ars, g.acs, Mv, K - 4 * c0);
-        stage(Bs, Np, 1, kc, Np, Bg + (int64_t)4 * c0 * g.brs, g.brs, g.bcs, K - 4 * c0, Nv);
+        stage_pair(StageWalk(As, 1, Mp, Mp, kc, Ag + (int64_t)4 * c0 * g.acs, g.ars, g.acs, Mv, K - 4 * c0),
+                   StageWalk(Bs, Np, 1, kc, Np, Bg + (int64_t)4 * c0 * g.brs, g.brs, g.bcs, K - 4 * c0, Nv));
         __syncthreads();
         const int s0 = p.s0 > c0 ? p.s0 : c0, s1 = p.s1 < c1 ? p.s1 : c1;
         if (p.na > 0 && s0 < s1) {
@@ -656,6 +723,14 @@ __device__ __forceinline__ void hh_factor(double* A, int m, int n, int lda, doub
       cj[j] = beta;
       tau[j] = t;
     }
+    if (built == rho && !need_r) {
+      // the last proper reflector: the columns after j only receive identity
+      // reflectors and are overwritten when Q is formed, so updating them
+      // serves R alone
+      for (int c = j + 1 + tid; c < n; c += kCT) tau[c] = 0.0;
+      __syncthreads();
+      return;
+    }
     if (rows_par) {
       hh_apply_rows(A, m, n, lda, j, t, s_lds + kLdsMs);
       continue;
@@ -674,21 +749,26 @@ __device__ __forceinline__ void hh_factor(double* A, int m, int n, int lda, doub
 }
 
 // Overwrites the factored A with the thin Q = H_0 ... H_{n-1} [I; 0]
-// (backward accumulation) and flips column j when sgn[j] < 0.  Columns with
+// (backward accumulation; the caller applies the column signs).  Columns with
 // the identity reflector (tau = 0) hold no reflector data, so they all become
-// unit vectors in one pass; each proper reflector then costs two barriers.
-__device__ __forceinline__ void hh_form_q(double* A, int m, int n, int lda, const double* tau, const double* sgn,
-                                          bool rows_par) {
+// unit vectors without a barrier between them; both kinds of column are found
+// from bit masks of tau (one ballot per 64 columns, the same in every wave),
+// and each proper reflector costs two barriers.
+__device__ __forceinline__ void hh_form_q(double* A, int m, int n, int lda, const double* tau, bool rows_par) {
   const int tid = tix(), lane = tid & 63, wid = tid >> 6;
-  for (int j = 0; j < n; ++j)
-    if (tau[j] == 0.0) {
+  for (int jw = 0; jw <= (n - 1) >> 6; ++jw)
+    for (uint64_t mk = __ballot(64 * jw + lane < n && tau[64 * jw + lane] == 0.0); mk != 0; mk &= mk - 1) {
+      const int j = 64 * jw + __ffsll((long long)mk) - 1;
       double* cj = A + (int64_t)j * lda;
       for (int i = tid; i < m; i += kCT) cj[i] = (i == j) ? 1.0 : 0.0;
     }
   __syncthreads();
-  for (int j = n - 1; j >= 0; --j) {
+  for (int jw = (n - 1) >> 6; jw >= 0; --jw)
+  for (uint64_t mk = __ballot(64 * jw + lane < n && tau[64 * jw + lane] != 0.0); mk != 0;) {
+    const int b = 63 - __clzll((long long)mk);
+    mk &= ~(1ull << b);
+    const int j = 64 * jw + b;
     const double t = tau[j];
-    if (t == 0.0) continue;
     double* cj = A + (int64_t)j * lda;
     if (rows_par) {
       hh_apply_rows(A, m, n, lda, j, t, s_lds + kLdsMs);
@@ -713,13 +793,6 @@ __device__ __forceinline__ void hh_form_q(double* A, int m, int n, int lda, cons
     }
     __syncthreads();  // the next reflector reads this column
   }
-  for (int j = 0; j < n; ++j) {
-    if (sgn[j] < 0.0) {
-      double* cj = A + (int64_t)j * lda;
-      for (int i = tid; i < m; i += kCT) cj[i] = -cj[i];
-    }
-  }
-  __syncthreads();
 }
 
 // Householder QR of q.M, already copied into A (column-major, leading
@@ -730,11 +803,10 @@ __device__ __forceinline__ void householder_qr(const Qr& q, double* A, int lda) 
   double* red = s_lds + kLdsRed;
   const int m = q.m, n = q.n, tid = tix();
   double p = 0.0;
-  for (int j = 0; j < n; ++j)
-    for (int i = tid; i < m; i += kCT) {
-      const double x = A[i + (int64_t)j * lda];
-      p = fma(x, x, p);
-    }
+  for_each_ij(m, n, [&](int i, int j) {
+    const double x = A[i + (int64_t)j * lda];
+    p = fma(x, x, p);
+  });
   const double fro = sqrt(block_sum(p, red));
   const bool rows_par = A == q.aux;  // tall: the matrix is in device memory
   hh_factor(A, m, n, lda, q.tol * fro, q.rho, q.R != nullptr, tau, red, rows_par);
@@ -744,8 +816,11 @@ __device__ __forceinline__ void householder_qr(const Qr& q, double* A, int lda) 
     for_each_ij(n, n, [&](int i, int j) { q.R[i + n * j] = (i <= j) ? sgn[i] * A[i + (int64_t)j * lda] : 0.0; });
   }
   __syncthreads();
-  hh_form_q(A, m, n, lda, tau, sgn, rows_par);
-  for_each_ij(m, n, [&](int i, int j) { q.Q[i * q.qrs + j * q.qcs] = A[i + (int64_t)j * lda]; });
+  hh_form_q(A, m, n, lda, tau, rows_par);
+  for_each_ij(m, n, [&](int i, int j) {
+    const double v = A[i + (int64_t)j * lda];
+    q.Q[i * q.qrs + j * q.qcs] = sgn[j] < 0.0 ? -v : v;
+  });
   __syncthreads();
 }
 
