@@ -101,7 +101,9 @@ def test_passes_flag_nonfinite_slices():
 QR_CASES = [(8, 8, None), (72, 32, None), (480, 32, None), (512, 32, None), (96, 32, 1), (480, 32, 3),
             (32, 32, 1), (5120, 16, None), (5120, 16, 3), (1, 1, None), (300, 7, None), (16, 16, 0),
             (513, 32, None), (7328, 32, None), (2049, 33, None), (4096, 32, 5), (1000, 1, None),
-            (700, 48, None), (1500, 40, 7), (66, 40, None)]
+            (700, 48, None), (1500, 40, 7), (66, 40, None),
+            # more than 64 columns: the reflector bit masks span several words
+            (600, 100, None), (300, 130, 20), (160, 70, 66)]
 
 
 @pytest.mark.parametrize("m,n,rank", QR_CASES)
@@ -138,6 +140,25 @@ def test_qr_matches_oracle(m, n, rank):
         k = max(rank, 0)
         if k:
             assert np.linalg.norm(Q[:, :k] @ Q[:, :k].T @ M - M) <= 1e-11 * nrm
+
+
+@pytest.mark.parametrize("m,n,rank", [(32, 32, 1), (480, 32, 3), (300, 130, 20), (5120, 16, 3)])
+def test_qr_without_r_gives_the_same_q(m, n, rank):
+    """R = NULL skips the work that only R needs; Q must not change."""
+    torch = torch_cuda()
+    from paper_2606_31061_amd import binding
+    say(f"qr without R m={m} n={n} rank={rank}")
+    rng = _rng(m * 7 + n)
+    M = rng.standard_normal((m, rank)) @ rng.standard_normal((rank, n))
+    Md = torch.from_numpy(M.T.copy()).cuda()
+    Q1 = torch.empty_like(Md)
+    Q2 = torch.empty_like(Md)
+    Rd = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    wk = torch.empty(m * n, dtype=torch.float64, device="cuda")
+    assert binding.tt_kernel_qr(Md, Q1, Rd, wk) == 0
+    assert binding.tt_kernel_qr(Md, Q2, None, wk) == 0
+    torch.cuda.synchronize()
+    assert torch.equal(Q1, Q2)
 
 
 @pytest.mark.parametrize("m,n,cond", [(3000, 32, 1e3), (3000, 32, 1e10), (700, 20, 1e10)])
