@@ -897,9 +897,10 @@ __device__ __forceinline__ bool cholqr2_reg(const Qr& q) {
     if (i >= n || j >= n) W[i + 32 * j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  double fro2 = 0.0;
-  for (int i = 0; i < n; ++i) fro2 += W[i * 33];
-  if (tid < 64) {
+  if (tid < 64) {  // one wave: the trace of W (= ||M||_F^2) and the factor
+    double fro2 = 0.0;
+#pragma unroll 4
+    for (int i = 0; i < n; ++i) fro2 += W[i * 33];
     const bool ok = chol_inv32<1>(W, R1, Ri, rowbuf, kCholRel * kCholRel * fro2, n);
     if (tid == 0) flag[0] = ok ? 1 : 0;
   }
@@ -1148,9 +1149,10 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
   }
   pad_identity();
   __syncthreads();
-  double fro2 = 0.0;
-  for (int i = 0; i < n; ++i) fro2 += W[i * 33];
-  if (tid < 64) {
+  if (tid < 64) {  // one wave: the trace of W (= ||M||_F^2) and the factor
+    double fro2 = 0.0;
+#pragma unroll 4
+    for (int i = 0; i < n; ++i) fro2 += W[i * 33];
     const bool ok = chol_inv32<1>(W, R1, Ri, rowbuf, kCholRel * kCholRel * fro2, n);
     if (tid == 0) flag[0] = ok ? 1 : 0;
   }
