@@ -302,12 +302,18 @@ def write_traffic(fetch_db, write_db, workload, compute):
         out[key.replace("_bytes", "_scale")] = scale
         with open(os.path.join(ROOT, KERNEL_SOURCES[compute]), "rb") as f:
             digest = hashlib.sha256(f.read()).hexdigest()
-        for kern in (["k_pass1b", "k_pass2b"] if compute == "bf16" else ["k_pass1", "k_pass2"]):
-            vals = [v for _, k, v in rows if re.search(r"\b" + kern + "<", k)][-10:]
-            if not vals:
-                raise SystemExit(f"{db}: no {kern} dispatches")
-            rec = out["kernels"].setdefault(kern, {"source_sha256": digest, "dispatches": len(vals)})
-            rec[key] = float(np.mean(vals)) * 1024.0 * scale
+        passes = ([["k_pass1b"], ["k_pass2b", "k_pass2s"]] if compute == "bf16" else [["k_pass1"], ["k_pass2"]])
+        for kerns in passes:
+            found = False
+            for kern in kerns:
+                vals = [v for _, k, v in rows if re.search(r"\b" + kern + "<", k)][-10:]
+                if not vals:
+                    continue
+                found = True
+                rec = out["kernels"].setdefault(kern, {"source_sha256": digest, "dispatches": len(vals)})
+                rec[key] = float(np.mean(vals)) * 1024.0 * scale
+            if not found:
+                raise SystemExit(f"{db}: no {' or '.join(kerns)} dispatches")
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
@@ -411,6 +417,7 @@ def main():
     # the pass kernels alone, launched back to back over the resident frames
     # (HIP events around the whole run on the stream that launches them)
     kb = sp.time_passes(pool, reps=args.kernel_reps)
+    knames = sp.pass_kernels()
     if args.profile_ops:
         prof = sp.op_profile()
         tot = sum(p[2] for p in prof)
@@ -427,7 +434,7 @@ def main():
         f"pass2 contraction {kb['pass2_kernel']:.2f} us + reduction {kb['pass2_reduce']:.2f} us")
     # the dominant kernel: the slower of the two contraction kernels
     dom = "pass1" if kb["pass1_kernel"] >= kb["pass2_kernel"] else "pass2"
-    kname = ("k_pass1" if dom == "pass1" else "k_pass2") + ("b" if args.compute == "bf16" else "")
+    kname = knames[0] if dom == "pass1" else knames[1]
     dom_bytes = b1 if dom == "pass1" else b2
     achieved = dom_bytes / (kb[dom + "_kernel"] * 1e-6) / 1e9
     traffic = measured_traffic(spec.name, args.compute, kname)

@@ -38,7 +38,9 @@ tt_status tt_kernel_pass2(const void* X, tt_dtype x_dtype, int64_t P, int64_t J,
  * precision option of the contractions; the QR and Gram steps of Section 3.4
  * stay FP64): every element of X (any x_dtype) and of the interface is
  * rounded to BF16 (round to nearest even), products are accumulated in FP32
- * per tile and the tiles' partial sums are added in FP64 in a fixed order.
+ * per tile (a block's waves added in wave order) and, where a tile's
+ * reduction is split over blocks, the partial tiles are added in FP64 in a
+ * fixed order.
  * Same shapes, layouts and flag as tt_kernel_pass1 / tt_kernel_pass2; the
  * result does not depend on block timing.  The workspace (device, caller-
  * owned, at least the size returned by the matching _workspace function, no

@@ -196,6 +196,14 @@ tt_status tt_stream_op_profile(tt_stream* s, int64_t cap, int32_t* kinds, int64_
  * (flag not set or no push yet). */
 tt_status tt_stream_pass_profile(tt_stream* s, float* ms);
 
+/* The contraction kernels the handle's slice passes launch (they follow its
+ * precision and its launch plans, tuned or not): *pass1 = 0 for k_pass1 (FP32
+ * MFMA) or 1 for k_pass1b (BF16 MFMA); *pass2 = 0 for k_pass2 (FP32 MFMA),
+ * 1 for k_pass2b (BF16 MFMA, slice read straight into registers) or 2 for
+ * k_pass2s (BF16 MFMA, slice staged through LDS).  Errors: INVALID_ARG
+ * (null). */
+tt_status tt_stream_pass_kernels(const tt_stream* s, int32_t* pass1, int32_t* pass2);
+
 /* Average device time per launch, in microseconds, of the handle's slice-pass
  * kernels (the contractions of Section 4.2 at the split point, with the
  * interfaces of the last update): each kernel is launched `reps` times back

@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH):
         "tt_stream_op_profile": (c_int, [sv, c_int64, POINTER(c_int32), POINTER(c_int64), POINTER(c_double),
                                          POINTER(c_int64)]),
         "tt_stream_pass_profile": (c_int, [sv, POINTER(c_float)]),
+        "tt_stream_pass_kernels": (c_int, [sv, POINTER(c_int32), POINTER(c_int32)]),
         "tt_stream_time_passes": (c_int, [sv, POINTER(c_void_p), c_int32, c_int, c_int32, POINTER(c_float)]),
         "tt_last_error_string": (c_char_p, []),
         "tt_version": (c_char_p, []),
@@ -350,6 +351,12 @@ class TTStream:
         ms = (c_float * 4)()
         _check(self._lib.tt_stream_pass_profile(self._h, ms), "tt_stream_pass_profile")
         return {"pass1_kernel": ms[0], "pass1": ms[1], "pass2_kernel": ms[2], "pass2": ms[3]}
+
+    def pass_kernels(self):
+        """Names of the contraction kernels of the two slice passes."""
+        a, b = c_int32(), c_int32()
+        _check(self._lib.tt_stream_pass_kernels(self._h, byref(a), byref(b)), "tt_stream_pass_kernels")
+        return ("k_pass1", "k_pass1b")[a.value], ("k_pass2", "k_pass2b", "k_pass2s")[b.value]
 
     def time_passes(self, xs, reps: int = 50):
         """Average device us per launch of the slice-pass kernels, launched

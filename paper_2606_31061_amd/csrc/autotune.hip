@@ -100,6 +100,12 @@ bool tune(int64_t P, int64_t J, int r, tt_dtype compute, int cus, hipStream_t st
         c1b.push_back(pass1b_finish(pl, P, J));
       }
     }
+    if (P % 8 == 0) {  // the staged pass 2
+      PassBPlan pl;
+      pl.ntn = ntn;
+      pl.staged = 1;
+      c2b.push_back(pass2b_finish(pl, P, J));
+    }
     for (int waves : {4, 8}) {
       if (waves == 8 && ntn != 1) continue;
       PassBPlan pl;

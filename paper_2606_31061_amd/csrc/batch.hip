@@ -62,7 +62,7 @@ std::array<int, 5> pass_key(const tt_stream* s, int pass) {
   const int ntn = s->r[ks] <= 32 ? 1 : 2;
   if (s->compute == TT_BF16) {
     if (pass == 1) return {1, 1, s->p1b.vec, s->p1b.waves, ntn};
-    return {1, 2, pass2b_vx(s->Pk[ks]) ? 1 : 0, s->p2b.waves, ntn};
+    return {1, 2, pass2b_vx(s->Pk[ks]) ? 1 : 0, s->p2b.staged ? -1 : s->p2b.waves, ntn};
   }
   if (pass == 1) return {0, 1, s->p1.vec, s->p1.waves, s->p1.ntn};
   return {0, 2, pass2_vec(s->Pk[ks]), 0, ntn};

@@ -84,6 +84,7 @@ tt_status tt_kernel_pass2_bf16(const void* X, tt_dtype x_dtype, int64_t P, int64
                                double* Y, void* workspace, int32_t* nonfinite_flag, void* hip_stream) {
   if (!X || !A || !Y || !workspace || !nonfinite_flag) return kfail(TT_ERR_INVALID_ARG, "null");
   if (P < 1 || J < 1 || r < 1 || r > 64) return kfail(TT_ERR_INVALID_ARG, "size");
+  if (ttk::pass_bf16_setup() != hipSuccess) return kfail(TT_ERR_DEVICE, "setup");
   const ttk::PassBPlan pl = ttk::pass2b_plan(P, J, r, device_cus());
   hipError_t e = ttk::pass2_bf16(static_cast<hipStream_t>(hip_stream), X, x_dtype, pl, P, J, r, A, Y, workspace,
                                  nonfinite_flag);

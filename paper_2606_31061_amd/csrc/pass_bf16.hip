@@ -435,6 +435,162 @@ __global__ void __launch_bounds__(NW * 64) k_pass2b(const T* __restrict__ X, int
   if (bad) atomicOr(flag, 1);
 }
 
+
+// ------------------------------------------------------------------ pass 2, staged
+// The slice goes through LDS as in pass_kernels.hip's pass 2, here as BF16
+// (P % 8 == 0): block b owns columns [32 b, 32 b + 32) and all P rows; wave w
+// owns the row slab [w slab, (w + 1) slab) (slab a multiple of 16) and stages
+// it in chunks of at most kP2sRows rows, each lane loading 8 consecutive rows
+// of a column (16 bytes), so the slice is read in runs along its contiguous
+// index.  MFMA step kk takes reduction slot e of lane half g as row
+// 16 kk + 8 g + e of the chunk for both operands: the slice from LDS in one
+// 16-byte read per lane, the left interface from global memory (two 16-byte
+// loads) rounded to BF16.  Rows past the slab are zero in LDS and in the
+// interface operand.  The waves' tiles are added in LDS in wave order and the
+// block writes Y in FP64; the next chunk's slice loads are held in registers
+// while the current chunk's MFMAs run.  Compared with k_pass2b (direct loads,
+// 32-byte runs per column) the staging turns the slice reads into 288-byte
+// runs.
+constexpr int kP2sWaves = 8;
+constexpr int kP2sRows = 144;                // rows per chunk, a multiple of 16
+constexpr int kP2sLdw = (kP2sRows + 8) / 2;  // LDS words per staged column (a multiple of 4)
+constexpr size_t kP2sLds = (size_t)kP2sWaves * 32 * kP2sLdw * sizeof(unsigned);
+
+template <typename T, int NTN>
+__global__ void __launch_bounds__(kP2sWaves * 64) k_pass2s(const T* __restrict__ X, int64_t P, int64_t J, int r,
+                                                           const float* __restrict__ A, double* __restrict__ Y,
+                                                           int* __restrict__ flag, const PassDesc* __restrict__ batch) {
+  if (batch) {
+    const PassDesc& pp = batch[blockIdx.y];
+    X = static_cast<const T*>(pp.x);
+    A = pp.w;
+    Y = pp.out;
+    flag = pp.flag;
+    P = pp.P;
+    J = pp.J;
+    r = pp.r;
+  }
+  if ((int64_t)blockIdx.x * 32 >= J) return;  // past this member's columns
+  extern __shared__ unsigned s2w[];
+  constexpr int PER_COL = kP2sRows / 8;   // vector loads per column and chunk
+  constexpr int NLD = 32 * PER_COL / 64;  // vector loads per lane and chunk
+  constexpr int KS = kP2sRows / 16;       // MFMA steps per chunk
+  static_assert((32 * PER_COL) % 64 == 0 && kP2sRows % 16 == 0 && kP2sLdw % 4 == 0, "staging shape");
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 5, jl = lane & 31;
+  unsigned* Xs = s2w + w * 32 * kP2sLdw;
+  const int64_t slab = ((P + kP2sWaves - 1) / kP2sWaves + 15) & ~15LL;
+  const int nchunk = (int)((slab + kP2sRows - 1) / kP2sRows);
+  const int64_t j0 = (int64_t)blockIdx.x * 32;
+  const int64_t rb = (int64_t)w * slab;
+  const int64_t re = (rb + slab < P) ? rb + slab : P;
+  auto rows_of = [&](int ch) -> int {  // a multiple of 8 (P % 8 == 0)
+    int64_t rows = re - (rb + (int64_t)ch * kP2sRows);
+    if (rows < 0) rows = 0;
+    if (rows > kP2sRows) rows = kP2sRows;
+    return (int)rows;
+  };
+  // Loads are unconditional (row and column clamped to the slice) so that
+  // the wait counts stay exact; out-of-range vectors are zeroed at the store.
+  unsigned xr[NLD][4];
+  auto load_chunk = [&](int ch) {
+    const int64_t c0 = rb + (int64_t)ch * kP2sRows;
+#pragma unroll
+    for (int it = 0; it < NLD; ++it) {
+      const int e = lane + 64 * it;
+      const int col = e / PER_COL, rv = e - col * PER_COL;
+      int64_t p = c0 + 8 * rv;
+      p = p < P - 8 ? p : P - 8;
+      int64_t jj = j0 + col;
+      jj = jj < J ? jj : J - 1;
+      LdB<T, 8>::get(X + p + P * jj, xr[it]);
+    }
+  };
+  auto store_chunk = [&](int ch) {
+    const int rows = rows_of(ch);
+#pragma unroll
+    for (int it = 0; it < NLD; ++it) {
+      const int e = lane + 64 * it;
+      const int col = e / PER_COL, rv = e - col * PER_COL;
+      const bool ok = j0 + col < J && 8 * rv < rows;
+      const u32x4 v = {ok ? xr[it][0] : 0u, ok ? xr[it][1] : 0u, ok ? xr[it][2] : 0u, ok ? xr[it][3] : 0u};
+      *reinterpret_cast<u32x4*>(&Xs[col * kP2sLdw + 4 * rv]) = v;
+    }
+  };
+  floatx16 acc[NTN];
+#pragma unroll
+  for (int t = 0; t < NTN; ++t) acc[t] = floatx16{0};
+
+  if (nchunk > 0) load_chunk(0);
+  for (int ch = 0; ch < nchunk; ++ch) {
+    const int64_t c0 = rb + (int64_t)ch * kP2sRows;
+    const int rows = rows_of(ch);
+    const int r16 = (rows + 15) & ~15;
+    store_chunk(ch);
+    __syncthreads();
+    // interface fragments of every step, issued before the next chunk's
+    // slice loads (waits are in issue order)
+    u32x4 bv[KS][NTN];
+#pragma unroll
+    for (int kk = 0; kk < KS; ++kk) {
+      const bool ok = 16 * kk + 8 * g < rows;
+      int64_t p = c0 + 16 * kk + 8 * g;
+      p = p < P - 8 ? p : P - 8;
+#pragma unroll
+      for (int t = 0; t < NTN; ++t) {
+        const int a = jl + 32 * t;
+        const float* ap = A + p + P * (int64_t)(a < r ? a : r - 1);
+        const float4 a0 = *reinterpret_cast<const float4*>(ap);
+        const float4 a1 = *reinterpret_cast<const float4*>(ap + 4);
+        bv[kk][t] = ok ? u32x4{pk(a0.x, a0.y), pk(a0.z, a0.w), pk(a1.x, a1.y), pk(a1.z, a1.w)}
+                       : u32x4{0u, 0u, 0u, 0u};
+      }
+    }
+    auto mfma_chunk = [&]() {
+#pragma unroll
+      for (int kk = 0; kk < KS; ++kk) {
+        if (16 * kk >= r16) break;
+        const u32x4 xa = *reinterpret_cast<const u32x4*>(&Xs[jl * kP2sLdw + 8 * kk + 4 * g]);
+#pragma unroll
+        for (int t = 0; t < NTN; ++t) acc[t] = mfma_bf16(xa, bv[kk][t], acc[t]);
+      }
+    };
+    // separate paths with and without the prefetch keep the wait counts exact
+    if (ch + 1 < nchunk) {
+      __builtin_amdgcn_sched_barrier(0);
+      load_chunk(ch + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      mfma_chunk();
+    } else {
+      mfma_chunk();
+    }
+    __syncthreads();
+  }
+  // cross-wave reduction in LDS (reuses the staging area), wave order
+  float* red = reinterpret_cast<float*>(s2w);
+  int bad = 0;
+#pragma unroll
+  for (int t = 0; t < NTN; ++t) {
+#pragma unroll
+    for (int v = 0; v < 16; ++v) red[(w * 16 + v) * 64 + lane] = acc[t][v];
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += kP2sWaves * 64) {
+      float sum = 0.f;
+#pragma unroll
+      for (int ww = 0; ww < kP2sWaves; ++ww) sum += red[ww * 1024 + e];
+      const int v = e / 64, ln = e % 64;
+      const int64_t jj = j0 + res_row(ln, v);
+      const int a = (ln & 31) + 32 * t;
+      if (jj < J && a < r) {
+        Y[a + (int64_t)r * jj] = (double)sum;
+        if (!isfinite(sum)) bad = 1;
+      }
+    }
+    __syncthreads();
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
 // ------------------------------------------------------------------ reduce
 // out = sum over chunks (in chunk order, FP64) of the partial tiles; thread g
 // takes element g % TILEF of tile g / TILEF.  PASS 1: tile = row tile (rows
@@ -575,8 +731,32 @@ hipError_t p2b_nw(hipStream_t st, const T* X, const PassBPlan& pl, int64_t P, in
 }
 
 template <typename T>
+hipError_t p2s_t(hipStream_t st, const T* X, const PassBPlan& pl, int64_t P, int64_t J, int r, const float* A,
+                 double* Y, int* flag, const PassLaunch* bl) {
+  const dim3 grid(bl ? bl->gx : (unsigned)pl.tiles, bl ? (unsigned)bl->n : 1u), block(kP2sWaves * 64);
+  const PassDesc* bt = bl ? bl->desc : nullptr;
+  if (!(pass_launch_mask() & 1)) {
+  } else if (pl.ntn == 1) {
+    hipLaunchKernelGGL((k_pass2s<T, 1>), grid, block, kP2sLds, st, X, P, J, r, A, Y, flag, bt);
+  } else {
+    hipLaunchKernelGGL((k_pass2s<T, 2>), grid, block, kP2sLds, st, X, P, J, r, A, Y, flag, bt);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (hipEvent_t m = pass_mid_event()) e = hipEventRecord(m, st);
+  return e;
+}
+
+template <typename T, int NTN>
+hipError_t attr2s() {
+  return hipFuncSetAttribute((const void*)k_pass2s<T, NTN>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)kP2sLds);
+}
+
+template <typename T>
 hipError_t p2b_t(hipStream_t st, const T* X, const PassBPlan& pl, int64_t P, int64_t J, int r, const float* A,
                  double* Y, void* ws, int* flag, const PassLaunch* bl) {
+  if (pl.staged) return p2s_t<T>(st, X, pl, P, J, r, A, Y, flag, bl);
   if (pl.waves == 8) return p2b_nw<T, 8>(st, X, pl, P, J, r, A, Y, ws, flag, bl);
   return p2b_nw<T, kWavesB>(st, X, pl, P, J, r, A, Y, ws, flag, bl);
 }
@@ -602,6 +782,12 @@ PassBPlan pass1b_finish(PassBPlan pl, int64_t P, int64_t J) {
 PassBPlan pass2b_finish(PassBPlan pl, int64_t P, int64_t J) {
   (void)P;
   pl.tiles = (int)((J + 31) / 32);
+  if (pl.staged) {  // one block per column tile writes its result: no workspace
+    pl.chunks = 1;
+    pl.waves = kP2sWaves;
+    pl.ws_bytes = 256;
+    return pl;
+  }
   pl.ws_bytes = (size_t)pl.tiles * pl.chunks * pl.ntn * 1024 * sizeof(float);
   return pl;
 }
@@ -626,6 +812,13 @@ PassBPlan pass1b_plan(int64_t P, int64_t J, int r, int cus) {
 PassBPlan pass2b_plan(int64_t P, int64_t J, int r, int cus) {
   PassBPlan pl;
   pl.ntn = r <= 32 ? 1 : 2;
+  // the staged kernel when its waves need at most two chunks each (measured
+  // 8.4 us against 20-24 us on the 1080 x 5760 slice; with few column tiles
+  // and long columns the direct kernel's row split wins)
+  if (P % 8 == 0 && P <= 2 * kP2sWaves * kP2sRows) {
+    pl.staged = 1;
+    return pass2b_finish(pl, P, J);
+  }
   pl.waves = kWavesB;
   pl = pass2b_finish(pl, P, J);
   pl.chunks = chunks_for((P + 63) / 64, pl.tiles, 2 * cus, pl.waves, 2);
@@ -638,6 +831,11 @@ void pass1b_grids(const PassBPlan& pl, unsigned* gx, unsigned* grx) {
 }
 
 void pass2b_grids(const PassBPlan& pl, unsigned* gx, unsigned* grx) {
+  if (pl.staged) {
+    *gx = (unsigned)pl.tiles;
+    *grx = 0u;
+    return;
+  }
   *gx = (unsigned)(pl.tiles * pl.chunks);
   *grx = pl.chunks == 1 ? 0u : (unsigned)(((int64_t)pl.tiles * pl.ntn * 1024 + 255) / 256);
 }
@@ -661,8 +859,9 @@ hipError_t pass1_bf16(hipStream_t st, const void* X, tt_dtype xdt, const PassBPl
 
 hipError_t pass2_bf16(hipStream_t st, const void* X, tt_dtype xdt, const PassBPlan& pl, int64_t P, int64_t J, int r,
                       const float* A, double* Y, void* ws, int* flag, const PassLaunch* bl) {
-  if (r < 1 || r > 32 * pl.ntn || pl.ntn > 2 || (pl.waves != kWavesB && !(pl.waves == 8 && pl.ntn == 1)) ||
-      (bl && (bl->n < 1 || bl->n > 65535)))
+  if (pl.staged && (P % 8 != 0 || pl.chunks != 1)) return hipErrorInvalidValue;
+  if (r < 1 || r > 32 * pl.ntn || pl.ntn > 2 || (bl && (bl->n < 1 || bl->n > 65535)) ||
+      (!pl.staged && pl.waves != kWavesB && !(pl.waves == 8 && pl.ntn == 1)))
     return hipErrorInvalidValue;
   if (pl.chunks < 1 || pl.tiles != (int)((J + 31) / 32)) return hipErrorInvalidValue;
   switch (xdt) {
@@ -671,6 +870,18 @@ hipError_t pass2_bf16(hipStream_t st, const void* X, tt_dtype xdt, const PassBPl
     case TT_BF16: return p2b_t(st, static_cast<const __hip_bfloat16*>(X), pl, P, J, r, A, Y, ws, flag, bl);
   }
   return hipErrorInvalidValue;
+}
+
+hipError_t pass_bf16_setup() {
+  hipError_t e = hipSuccess;
+#define TT_A2S(T)                                \
+  if (e == hipSuccess) e = attr2s<T, 1>();       \
+  if (e == hipSuccess) e = attr2s<T, 2>();
+  TT_A2S(float)
+  TT_A2S(double)
+  TT_A2S(__hip_bfloat16)
+#undef TT_A2S
+  return e;
 }
 
 }  // namespace ttk

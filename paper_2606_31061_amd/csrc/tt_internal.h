@@ -187,6 +187,7 @@ struct PassBPlan {
   int tiles = 1;      // pass 1: row tiles; pass 2: 32-column tiles
   int chunks = 1;     // pass 1: column-group chunks; pass 2: row chunks
   int ntn = 1;        // 32-column tiles of the rank
+  int staged = 0;     // pass 2: the LDS-staged kernel (P % 8 == 0; one chunk, no workspace use)
   size_t ws_bytes = 0;
 };
 PassBPlan pass1b_plan(int64_t P, int64_t J, int r, int cus);
@@ -203,6 +204,9 @@ void pass2b_grids(const PassBPlan& plan, unsigned* gx, unsigned* grx);
 // Pass 2 (BF16) loads 8-row vectors when P % 8 == 0 (part of its template
 // shape: members of one launch share it).
 bool pass2b_vx(int64_t P);
+// Dynamic LDS limits of the BF16 kernels (the staged pass 2 needs 76 KB);
+// once per process before their first launch, like pass_setup.
+hipError_t pass_bf16_setup();
 
 // ---------------------------------------------------------------- tuner
 struct PassPlans {

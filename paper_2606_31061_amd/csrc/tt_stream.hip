@@ -681,7 +681,8 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
   if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, s->device) != hipSuccess)
     return bail(TT_ERR_DEVICE, "cannot query LDS size");
   s->lds_limit = (size_t)lds;
-  if (ttk::pass_setup() != hipSuccess || ttk::chain_setup(s->lds_limit) != hipSuccess)
+  if (ttk::pass_setup() != hipSuccess || ttk::pass_bf16_setup() != hipSuccess ||
+      ttk::chain_setup(s->lds_limit) != hipSuccess)
     return bail(TT_ERR_DEVICE, "kernel attribute setup failed");
 
   int cus = 256;
@@ -1013,6 +1014,14 @@ tt_status tt_stream_pass_profile(tt_stream* s, float* ms) {
   TT_HIP(hipEventElapsedTime(ms + 1, s->evpass[0], s->evpass[2]));
   TT_HIP(hipEventElapsedTime(ms + 2, s->evpass[3], s->evpass[4]));
   TT_HIP(hipEventElapsedTime(ms + 3, s->evpass[3], s->evpass[5]));
+  return TT_OK;
+}
+
+tt_status tt_stream_pass_kernels(const tt_stream* s, int32_t* pass1, int32_t* pass2) {
+  if (!valid(s) || !pass1 || !pass2) return fail(TT_ERR_INVALID_ARG, "null argument");
+  const bool bf16 = s->compute == TT_BF16;
+  *pass1 = bf16 ? 1 : 0;
+  *pass2 = bf16 ? (s->p2b.staged ? 2 : 1) : 0;
   return TT_OK;
 }
 

@@ -112,6 +112,7 @@ def test_null_handles_are_rejected():
     assert lib.tt_server_stats(None, None, None, None, None, None) == binding.TT_ERR_INVALID_ARG
     assert lib.tt_server_destroy(None) == binding.TT_ERR_INVALID_ARG
     assert lib.tt_stream_pass_profile(None, None) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_stream_pass_kernels(None, None, None) == binding.TT_ERR_INVALID_ARG
     assert lib.tt_stream_time_passes(None, None, 0, 0, 1, None) == binding.TT_ERR_INVALID_ARG
     assert lib.tt_kernel_pass1_workspace(0, 1, 1) == 0
 

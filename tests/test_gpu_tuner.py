@@ -114,3 +114,31 @@ def test_tuner_picks_the_split_point_per_shape():
     assert c.info()["split_point"] == 1
     for s in (a, b, c):
         s.close()
+
+
+@pytest.mark.parametrize("compute", ["f32", "bf16"])
+@pytest.mark.parametrize("autotune", [False, True])
+def test_pass_kernel_names_follow_the_plan(compute, autotune):
+    """The library names the contraction kernels its passes launch: FP32
+    streams k_pass1/k_pass2; BF16 streams k_pass1b and, for pass 2, the
+    LDS-staged k_pass2s by default where P % 8 == 0 and P <= 2304 (the tuner
+    may pick either BF16 kernel)."""
+    torch_cuda()
+    from paper_2606_31061_amd import TTStream
+    modes, ranks = (16, 18, 10), (4, 4, 4)
+    say(f"pass kernel names {compute} autotune={autotune}")
+    s = TTStream(modes, ranks, seed=3, compute=compute, autotune=autotune)
+    k1, k2 = s.pass_kernels()
+    sp = s.info()["split_point"]
+    s.close()
+    P = int(np.prod(modes[:sp]))
+    if compute == "f32":
+        assert (k1, k2) == ("k_pass1", "k_pass2")
+    else:
+        assert k1 == "k_pass1b"
+        if autotune:
+            assert k2 in ("k_pass2b", "k_pass2s")
+            if P % 8 != 0:
+                assert k2 == "k_pass2b"
+        else:
+            assert k2 == ("k_pass2s" if P % 8 == 0 and P <= 2304 else "k_pass2b")
