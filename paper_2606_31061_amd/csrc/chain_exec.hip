@@ -159,15 +159,17 @@ struct View {
 // w < nb takes block w alone.  Slot q (q < na) accumulates block blk(q) over
 // the k-steps s0 + ph(q) + P t below s1.
 struct Plan {
-  int na, P;   // slots, phases per block
+  int na, P;   // slots, phases per block (1, 2 or 4)
+  int lp;      // log2 P
   int w, nbm, nb;
   int sb;      // the block of a k-split wave, or -1
   int s0, s1;  // k-step range
   int ks, kg;  // k groups, this wave's group (-1: idle)
 };
 
-__device__ __forceinline__ int slot_blk(const Plan& p, int q) { return p.sb >= 0 ? p.sb : p.w + kCW * (q / p.P); }
-__device__ __forceinline__ int slot_ph(const Plan& p, int q) { return q % p.P; }
+// P is 1, 2 or 4: the slot arithmetic uses shifts (P = 1 << lp)
+__device__ __forceinline__ int slot_blk(const Plan& p, int q) { return p.sb >= 0 ? p.sb : p.w + kCW * (q >> p.lp); }
+__device__ __forceinline__ int slot_ph(const Plan& p, int q) { return q & (p.P - 1); }
 
 __device__ __forceinline__ Plan wave_plan(int nbm, int nb, int nks, int w, bool split) {
   Plan p;
@@ -177,13 +179,15 @@ __device__ __forceinline__ Plan wave_plan(int nbm, int nb, int nks, int w, bool 
   p.sb = -1;
   p.na = 0;
   p.P = 1;
+  p.lp = 0;
   p.ks = 1;
   p.kg = 0;
   p.s0 = 0;
   p.s1 = nks;
   if (nb >= kCW) {
     const int mine = (nb - w + kCW - 1) / kCW;  // blocks w, w+16, ... below nb (at most 4)
-    p.P = mine >= 3 ? 1 : (mine == 2 ? 2 : 4);
+    p.lp = mine >= 3 ? 0 : (mine == 2 ? 1 : 2);
+    p.P = 1 << p.lp;
     p.na = mine * p.P;
     return p;
   }
@@ -197,6 +201,7 @@ __device__ __forceinline__ Plan wave_plan(int nbm, int nb, int nks, int w, bool 
     p.s0 = nks * p.kg / ks;
     p.s1 = nks * (p.kg + 1) / ks;
     p.P = 4;
+    p.lp = 2;
     p.na = 4;
   } else {
     p.kg = -1;
