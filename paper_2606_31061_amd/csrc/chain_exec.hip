@@ -80,13 +80,33 @@ __device__ __forceinline__ int tix() {
   return t;
 }
 
+// a / b (returned) and a % b (rem) for 0 <= a < 2^16 and b >= 1, from a
+// single-precision reciprocal estimate corrected to the exact quotient (the
+// estimate is within one of it; for b >= 2^24 it is below one, as is a / b):
+// a few instructions where an integer division takes dozens.
+__device__ __forceinline__ int small_div(int a, int b, int& rem) {
+  int q = (int)((float)a * __builtin_amdgcn_rcpf((float)b));
+  int r = a - q * b;
+  if (r < 0) {
+    --q;
+    r += b;
+  }
+  if (r >= b) {
+    ++q;
+    r -= b;
+  }
+  rem = r;
+  return q;
+}
+
 // fn(i, j) for every (i, j) of an m x n index space (m >= 1), the workgroup's
 // threads walking i fastest.  The indices advance incrementally, so there is no
 // integer division per element.
 template <class Fn>
 __device__ __forceinline__ void for_each_ij(int m, int n, Fn fn) {
   const int tid = tix(), di = kCT % m, dj = kCT / m;
-  for (int i = tid % m, j = tid / m; j < n;) {
+  int i;
+  for (int j = small_div(tid, m, i); j < n;) {
     fn(i, j);
     i += di;
     j += dj;
@@ -196,8 +216,7 @@ __device__ __forceinline__ Plan wave_plan(int nbm, int nb, int nks, int w, bool 
   if (ks < 1) ks = 1;
   p.ks = ks;
   if (w < nb * ks) {
-    p.sb = w % nb;
-    p.kg = w / nb;
+    p.kg = small_div(w, nb, p.sb);
     p.s0 = nks * p.kg / ks;
     p.s1 = nks * (p.kg + 1) / ks;
     p.P = 4;
@@ -225,8 +244,10 @@ __device__ __forceinline__ void mma_slots(const View& A, const View& B, const Pl
     const int b = slot_blk(p, q);
     ph[q] = slot_ph(p, q);
     const int k0 = 4 * (s0 + ph[q]) + lk;
-    pa[q] = A.off + (16 * (b % p.nbm) + li) * A.rs + k0 * A.cs;
-    pb[q] = B.off + k0 * B.rs + (16 * (b / p.nbm) + li) * B.cs;
+    int bi;
+    const int bj = small_div(b, p.nbm, bi);
+    pa[q] = A.off + (16 * bi + li) * A.rs + k0 * A.cs;
+    pb[q] = B.off + k0 * B.rs + (16 * bj + li) * B.cs;
   }
   const int da = 4 * p.P * A.cs, db = 4 * p.P * B.rs;
   int s = s0;
@@ -274,7 +295,9 @@ __device__ __forceinline__ void finish_direct(const Plan& p, int M, int N, const
       for (int f = 1; f < 4; ++f)
         if (q + f < 4 && f < p.P) s += acc[q + f < 4 ? q + f : 3];
       const int b = slot_blk(p, q);
-      const int i0 = (b % p.nbm) * 16, j0 = (b / p.nbm) * 16;
+      int bi;
+      const int bj = small_div(b, p.nbm, bi);
+      const int i0 = bi * 16, j0 = bj * 16;
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = i0 + 4 * v + (lane >> 4), j = j0 + (lane & 15);
@@ -321,7 +344,8 @@ __device__ __forceinline__ void finish_lds(const Plan& p, int M, int N, const v4
   const int rows = 16 * p.nbm, total = p.nb * 256, cols = total / rows;
   // (i, j) of element e, advanced without division
   const int nf = ifast ? rows : cols, df = kCT % nf, ds = kCT / nf;
-  int f = tix() % nf, sl = tix() / nf;
+  int f;
+  int sl = small_div(tix(), nf, f);
   for (int e = tix(); e < total; e += kCT) {
     const int i = ifast ? f : sl, j = ifast ? sl : f;
     f += df;
@@ -383,7 +407,8 @@ __device__ __forceinline__ void stage(int dst, int drs, int dcs, int rows, int c
   const int64_t fs = rfast ? rs : cs, ss = rfast ? cs : rs;
   const int dfs = rfast ? drs : dcs, dss = rfast ? dcs : drs;
   const int df = kCT % nf, ds = kCT / nf;
-  int f = tix() % nf, sl = tix() / nf;
+  int f;
+  int sl = small_div(tix(), nf, f);
   for (int e0 = tix(); e0 < total; e0 += U * kCT) {
     double x[U];
     int fi[U], si[U];
@@ -427,8 +452,7 @@ struct StageWalk {
     ds = kCT / nf;
     total = rows * cols;
     dst = dst_;
-    f = tix() % nf;
-    sl = tix() / nf;
+    sl = small_div(tix(), nf, f);
   }
   template <int U>
   __device__ __forceinline__ void load(int e0, double (&x)[U], int (&o)[U]) {
@@ -1010,7 +1034,8 @@ __device__ __forceinline__ bool cholqr2_reg(const Qr& q) {
     // incrementally: no integer division per element
     const bool ifast = q.qrs <= q.qcs;
     const int nf = ifast ? m : n, ns = ifast ? n : m, df = kCT % nf, ds = kCT / nf;
-    for (int f = tid % nf, sl = tid / nf; sl < ns;) {
+    int f;
+    for (int sl = small_div(tid, nf, f); sl < ns;) {
       const int row = ifast ? f : sl, col = ifast ? sl : f;
       q.Q[row * q.qrs + col * q.qcs] = part[row + ldq * col];
       f += df;
