@@ -39,23 +39,33 @@ __device__ __forceinline__ void wide_gemm(int64_t M, int64_t N, int64_t K, const
                                           int64_t acs, const double* B, int64_t brs, int64_t bcs, double* C,
                                           int64_t crs, int64_t ccs, float* C32) {
   __shared__ double red[kWideThreads];
-  const int G = depth_groups(K), OB = kWideThreads / G;
+  // G and OB are powers of two: shifts and masks instead of divisions
+  const int G = depth_groups(K), lg = __builtin_ctz(G), OB = kWideThreads >> lg, lob = __builtin_ctz(OB);
   const int64_t nout = M * N;
   const int64_t base = (int64_t)blockIdx.x * OB;
   if (base >= nout) return;
   // neither operand contiguous along an output index but one along the
   // depth: consecutive threads take consecutive depths instead
   const bool kfast = ars != 1 && bcs != 1 && (acs == 1 || brs == 1);
-  const int t = threadIdx.x, ol = kfast ? t / G : t % OB, g = kfast ? t % G : t / OB;
+  const int t = threadIdx.x, ol = kfast ? t >> lg : t & (OB - 1), g = kfast ? t & (G - 1) : t >> lob;
   const int64_t o = base + ol;
   const bool valid = o < nout;
   const bool along_i = ars == 1 || bcs != 1;
   const int64_t oc = valid ? o : nout - 1;
-  const int64_t i = along_i ? oc % M : oc / N, j = along_i ? oc / M : oc % N;
+  int64_t i, j;
+  if (nout <= INT32_MAX) {  // 32-bit quotients (the branch is uniform)
+    const uint32_t ou = (uint32_t)oc, d = (uint32_t)(along_i ? M : N);
+    const uint32_t qo = ou / d, ro = ou - qo * d;
+    i = along_i ? ro : qo;
+    j = along_i ? qo : ro;
+  } else {
+    i = along_i ? oc % M : oc / N;
+    j = along_i ? oc / M : oc % N;
+  }
   const double* a = A + i * ars + (int64_t)g * acs;
   const double* b = B + j * bcs + (int64_t)g * brs;
   const int64_t da = (int64_t)G * acs, db = (int64_t)G * brs;
-  const int64_t nk = K > g ? (K - g + G - 1) / G : 0;  // depths of this group
+  const int64_t nk = K > g ? (K - g + G - 1) >> lg : 0;  // depths of this group
   constexpr int U = 16;  // loads in flight per operand
   double acc0 = 0.0, acc1 = 0.0;
   for (int64_t q = 0; q < nk; q += U) {
