@@ -856,9 +856,10 @@ __device__ __forceinline__ void householder_qr(const Qr& q, double* A, int lda) 
 // Partial Gram blocks of a wave's 32-row stripe held in row fragments
 // f[s][cb] = X(r0 + 4s + l/16, 16 cb + l%16): blocks (0,0), (1,0), (1,1) of
 // X^T X go to part[(3 w + blk) * 256 + 64 v + l] (zero for a stripe wholly
-// below the matrix, live = false); after a barrier the 16 stripes are added
-// in order into W (32 x 32, column-major, mirrored).
-__device__ __forceinline__ void stripe_gram(const double (&f)[8][2], bool live, double* part, double* W) {
+// below the matrix, live = false); after a barrier the first nlive stripes
+// (those that hold rows; the rest are zero) are added in order into W
+// (32 x 32, column-major, mirrored).
+__device__ __forceinline__ void stripe_gram(const double (&f)[8][2], bool live, int nlive, double* part, double* W) {
   const int tid = tix(), lane = tid & 63, w = tid >> 6;
   v4d g00 = {0.0, 0.0, 0.0, 0.0}, g10 = g00, g11 = g00;
   if (live) {
@@ -880,8 +881,8 @@ __device__ __forceinline__ void stripe_gram(const double (&f)[8][2], bool live, 
     const int blk = tid >> 8, e = tid & 255, v = e >> 6, l = e & 63;
     const int bi = blk == 0 ? 0 : 1, bj = blk == 2 ? 1 : 0;
     double sum = 0.0;
-#pragma unroll
-    for (int ww = 0; ww < kCW; ++ww) sum += part[(3 * ww + blk) * 256 + e];
+#pragma unroll 4
+    for (int ww = 0; ww < nlive; ++ww) sum += part[(3 * ww + blk) * 256 + e];
     const int i = 16 * bi + 4 * v + (l >> 4), j = 16 * bj + (l & 15);
     W[i + 32 * j] = sum;
     if (bi != bj) W[j + 32 * i] = sum;
@@ -920,7 +921,7 @@ __device__ __forceinline__ bool cholqr2_reg(const Qr& q) {
       f[s][cb] = (row < m && col < n) ? q.M[row * q.mrs + col * q.mcs] : 0.0;
     }
   __syncthreads();
-  stripe_gram(f, live, part, W);
+  stripe_gram(f, live, (m + 31) >> 5, part, W);
   {
     const int i = tid & 31, j = tid >> 5;
     if (i >= n || j >= n) W[i + 32 * j] = (i == j) ? 1.0 : 0.0;
@@ -975,7 +976,7 @@ __device__ __forceinline__ bool cholqr2_reg(const Qr& q) {
   }
   __syncthreads();  // Ri is read above and rewritten below
   // pass 2: W = Q1^T Q1 = I + E
-  stripe_gram(f, live, part, W);
+  stripe_gram(f, live, (m + 31) >> 5, part, W);
   const int i = tid & 31, j = tid >> 5;
   const double e = (i < n && j < n) ? W[i + 32 * j] - (i == j ? 1.0 : 0.0) : 0.0;
   const double emax = block_max(fabs(e), red);
