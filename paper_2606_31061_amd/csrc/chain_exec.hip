@@ -824,6 +824,8 @@ __device__ __forceinline__ void hh_form_q(double* A, int m, int n, int lda, cons
   }
 }
 
+__device__ __forceinline__ void hh_form_q_wy(const Qr& q, const double* A, const double* tau, const double* sgn);
+
 // Householder QR of q.M, already copied into A (column-major, leading
 // dimension lda; LDS or the scratch buffer).
 __device__ __forceinline__ void householder_qr(const Qr& q, double* A, int lda) {
@@ -845,6 +847,10 @@ __device__ __forceinline__ void householder_qr(const Qr& q, double* A, int lda) 
     for_each_ij(n, n, [&](int i, int j) { q.R[i + n * j] = (i <= j) ? sgn[i] * A[i + (int64_t)j * lda] : 0.0; });
   }
   __syncthreads();
+  if (rows_par && n <= 32) {  // tall: Q in compact WY form, written to q.Q
+    hh_form_q_wy(q, A, tau, sgn);
+    return;
+  }
   hh_form_q(A, m, n, lda, tau, rows_par);
   for_each_ij(m, n, [&](int i, int j) {
     const double v = A[i + (int64_t)j * lda];
@@ -1117,6 +1123,117 @@ __device__ __forceinline__ void stripe_times_upper(const double (&g)[2][8], cons
     for (int v = 0; v < 4; ++v)
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb) f[4 * t + v][cb] = acc[t][cb][v];
+}
+
+// Q of a factored tall matrix (A = the scratch copy, m x n column-major,
+// n <= 32) in compact WY form: with the proper reflectors v_1..v_nb (columns
+// j_1 < .. < j_nb of A below the diagonal, unit at row j_k, zero above),
+// H_1 .. H_nb = I - V T V^T with T upper triangular (T_kk = tau_k,
+// T(1:k-1, k) = -tau_k T(1:k-1, 1:k-1) (V^T V)(1:k-1, k)), so
+// Q(i, c) = delta_ic - sum_k V(i, k) W(k, c),  W = T V(0:n-1, :)^T.
+// V^T V comes from 32-row stripes by MFMA (as in the Gram passes below), T
+// from one wave, and Q from the stripes again by MFMA, written to q.Q with
+// the column signs.  Two passes over A instead of two per reflector.
+__device__ __forceinline__ void hh_form_q_wy(const Qr& q, const double* A, const double* tau, const double* sgn) {
+  const int tid = tix(), lane = tid & 63, w = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int m = q.m, n = q.n;
+  int* jl = reinterpret_cast<int*>(s_lds + kLdsRow);  // proper columns, in order
+  double* G = s_lds + kLdsW;    // V^T V (32 x 32)
+  double* T = s_lds + kLdsR1;   // T (32 x 32, column-major)
+  double* Wm = s_lds + kLdsRi;  // W (32 x 32, leading dimension 33; rows past nb zero)
+  double* part = s_lds + kLdsMs;
+  const uint64_t mk = __ballot(lane < n && tau[lane] != 0.0);
+  const int nb = __popcll(mk);
+  if (tid < n && ((mk >> tid) & 1)) jl[__popcll(mk & ((1ull << tid) - 1))] = tid;
+  __syncthreads();
+  int jc[2];
+#pragma unroll
+  for (int cb = 0; cb < 2; ++cb) jc[cb] = 16 * cb + li < nb ? jl[16 * cb + li] : -1;
+  {
+    v4d g00 = {0.0, 0.0, 0.0, 0.0}, g10 = g00, g11 = g00;
+#pragma unroll 1
+    for (int r0 = 32 * w; r0 < m; r0 += kQrRows) {
+      double f[8][2];
+#pragma unroll
+      for (int s = 0; s < 8; ++s)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          const int row = r0 + 4 * s + lk, j = jc[cb];
+          const double a = A[(row < m ? row : m - 1) + (int64_t)m * (j < 0 ? 0 : j)];  // clamped
+          f[s][cb] = (j < 0 || row >= m || row < j) ? 0.0 : (row == j ? 1.0 : a);
+        }
+      gram_acc(f, g00, g10, g11);
+    }
+    __syncthreads();
+    gram_reduce(g00, g10, g11, part, G);
+  }
+  // V(0:n-1, :) into LDS, then T by one wave
+  {
+    const int c = tid & 31, k = tid >> 5;
+    if (c < n && k < nb) {
+      const int j = jl[k];
+      part[c + 32 * k] = c < j ? 0.0 : (c == j ? 1.0 : A[c + (int64_t)m * j]);
+    }
+  }
+  if (tid < 64) {
+    for (int k = 0; k < nb; ++k) {
+      const double tk = tau[jl[k]];
+      double acc = 0.0;
+      for (int qq = lane; qq < k; ++qq) acc += T[lane + 32 * qq] * G[qq + 32 * k];
+      if (lane < 32) T[lane + 32 * k] = lane < k ? -tk * acc : (lane == k ? tk : 0.0);
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
+  {
+    const int k = tid & 31, c = tid >> 5;
+    double acc = 0.0;
+    if (k < nb && c < n)
+      for (int qq = k; qq < nb; ++qq) acc += T[k + 32 * qq] * part[c + 32 * qq];
+    Wm[k + 33 * c] = acc;
+  }
+  __syncthreads();
+#pragma unroll 1
+  for (int r0 = 32 * w; r0 < m; r0 += kQrRows) {
+    double g[2][8];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int kc = 0; kc < 8; ++kc) {
+        const int row = r0 + 16 * t + li, kq = 4 * kc + lk;
+        const int j = kq < nb ? jl[kq] : -1;
+        const double a = A[(row < m ? row : m - 1) + (int64_t)m * (j < 0 ? 0 : j)];  // clamped
+        g[t][kc] = (j < 0 || row >= m || row < j) ? 0.0 : (row == j ? 1.0 : a);
+      }
+    v4d acc[2][2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) acc[t][cb] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kc = 0; kc < 8; ++kc) {
+      const double b0 = Wm[(4 * kc + lk) + 33 * li], b1 = Wm[(4 * kc + lk) + 33 * (16 + li)];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        acc[t][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[t][kc], b0, acc[t][0], 0, 0, 0);
+        acc[t][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(g[t][kc], b1, acc[t][1], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          const int row = r0 + 16 * t + 4 * v + lk, col = 16 * cb + li;
+          if (row < m && col < n) {
+            const double x = (row == col ? 1.0 : 0.0) - acc[t][cb][v];
+            q.Q[row * q.qrs + col * q.qcs] = sgn[col] < 0.0 ? -x : x;
+          }
+        }
+  }
+  __syncthreads();
 }
 
 // CholeskyQR2 of a tall m x n matrix (m > 512, n <= 32), streamed in
