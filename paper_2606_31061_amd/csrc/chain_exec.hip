@@ -1160,8 +1160,9 @@ __device__ __forceinline__ void hh_form_q_wy(const Qr& q, const double* A, const
 #pragma unroll
         for (int cb = 0; cb < 2; ++cb) {
           const int row = r0 + 4 * s + lk, j = jc[cb];
-          const double a = A[(row < m ? row : m - 1) + (int64_t)m * (j < 0 ? 0 : j)];  // clamped
-          f[s][cb] = (j < 0 || row >= m || row < j) ? 0.0 : (row == j ? 1.0 : a);
+          double a = row == j ? 1.0 : 0.0;
+          if (j >= 0 && row > j && row < m) a = A[row + (int64_t)m * j];  // only lanes that need it load
+          f[s][cb] = a;
         }
       gram_acc(f, g00, g10, g11);
     }
@@ -1203,8 +1204,9 @@ __device__ __forceinline__ void hh_form_q_wy(const Qr& q, const double* A, const
       for (int kc = 0; kc < 8; ++kc) {
         const int row = r0 + 16 * t + li, kq = 4 * kc + lk;
         const int j = kq < nb ? jl[kq] : -1;
-        const double a = A[(row < m ? row : m - 1) + (int64_t)m * (j < 0 ? 0 : j)];  // clamped
-        g[t][kc] = (j < 0 || row >= m || row < j) ? 0.0 : (row == j ? 1.0 : a);
+        double a = row == j ? 1.0 : 0.0;
+        if (j >= 0 && row > j && row < m) a = A[row + (int64_t)m * j];
+        g[t][kc] = a;
       }
     v4d acc[2][2];
 #pragma unroll
