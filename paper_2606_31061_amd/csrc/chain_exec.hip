@@ -833,13 +833,19 @@ __device__ __forceinline__ void householder_qr(const Qr& q, double* A, int lda) 
   double* sgn = s_lds + kLdsSgn;
   double* red = s_lds + kLdsRed;
   const int m = q.m, n = q.n, tid = tix();
+  const bool rows_par = A == q.aux;  // tall: the matrix is in device memory (lda = m)
   double p = 0.0;
-  for_each_ij(m, n, [&](int i, int j) {
-    const double x = A[i + (int64_t)j * lda];
-    p = fma(x, x, p);
-  });
+  if (rows_par) {
+    const int64_t total = (int64_t)m * n;
+#pragma unroll 8
+    for (int64_t e = tid; e < total; e += kCT) p = fma(A[e], A[e], p);
+  } else {
+    for_each_ij(m, n, [&](int i, int j) {
+      const double x = A[i + (int64_t)j * lda];
+      p = fma(x, x, p);
+    });
+  }
   const double fro = sqrt(block_sum(p, red));
-  const bool rows_par = A == q.aux;  // tall: the matrix is in device memory
   hh_factor(A, m, n, lda, q.tol * fro, q.rho, q.R != nullptr, tau, red, rows_par);
   for (int j = tid; j < n; j += kCT) sgn[j] = (tau[j] != 0.0 && A[j + (int64_t)j * lda] < 0.0) ? -1.0 : 1.0;
   __syncthreads();
@@ -1396,8 +1402,15 @@ __device__ __forceinline__ void wg_qr(const Qr& q) {
     householder_qr(q, s_lds + kLdsMs, ld);
     return;
   }
-  // larger matrices: Householder in the device scratch buffer
-  for_each_ij(m, n, [&](int i, int j) { q.aux[i + (int64_t)m * j] = q.M[i * q.mrs + j * q.mcs]; });
+  // larger matrices: Householder in the device scratch buffer (a contiguous
+  // column-major M is copied flat, eight loads in flight per thread)
+  if (q.mrs == 1 && q.mcs == m) {
+    const int64_t total = (int64_t)m * n;
+#pragma unroll 8
+    for (int64_t e = tix(); e < total; e += kCT) q.aux[e] = q.M[e];
+  } else {
+    for_each_ij(m, n, [&](int i, int j) { q.aux[i + (int64_t)m * j] = q.M[i * q.mrs + j * q.mcs]; });
+  }
   __syncthreads();
   householder_qr(q, q.aux, m);
 }
