@@ -1244,6 +1244,36 @@ __device__ __forceinline__ void hh_form_q_wy(const Qr& q, const double* A, const
   __syncthreads();
 }
 
+// Stores a wave's 32-row stripe held as row fragments (f[s][cb] is the
+// element (4 s + l / 16, 16 cb + l % 16) of rows r0 .. r0 + 31) to
+// X[row * rs + col * cs] (row < m, col < n) through the wave's own 32 x 32 LDS
+// tile, whose columns are XOR-swizzled by the row so that the fragment writes
+// and the column reads both spread over the banks: the global stores then run
+// along rows, contiguous for a column-major X.
+__device__ __forceinline__ void store_stripe(const double (&f)[8][2], double* tile, int r0, int m, int n, double* X,
+                                             int64_t rs, int64_t cs) {
+  const int lane = tix() & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const int r = 4 * s + lk, c = 16 * cb + li;
+      tile[r * 32 + (c ^ r)] = f[s][cb];
+    }
+  __builtin_amdgcn_wave_barrier();
+  const int r = lane & 31, row = r0 + r, h = lane >> 5;
+  if (row < m) {
+    double* xr = X + row * rs + h * cs;
+    const int64_t step = 2 * cs;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int c = 2 * k + h;
+      if (c < n) xr[k * step] = tile[r * 32 + (c ^ r)];
+    }
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
 // CholeskyQR2 of a tall m x n matrix (m > 512, n <= 32), streamed in
 // 512-row stripes (wave w takes rows 32 w .. 32 w + 31 of each stripe):
 //   A: W = M^T M,                   R1 = chol(W), Ri = R1^-1
@@ -1322,14 +1352,7 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
     auto finish = [&](const double (&g)[2][8], int st) {
       stripe_times_upper(g, Ri, f);
       gram_acc(f, h00, h10, h11);
-      const int r0 = kQrRows * st + 32 * w;
-#pragma unroll
-      for (int s = 0; s < 8; ++s)
-#pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-          const int row = r0 + 4 * s + lk, col = 16 * cb + li;
-          if (row < m && col < n) Q1[row + (int64_t)m * col] = f[s][cb];
-        }
+      store_stripe(f, part + 1024 * w, kQrRows * st + 32 * w, m, n, Q1, 1, m);
     };
 #pragma unroll 1
     for (int st = 0; st < nst; ++st) {
