@@ -101,8 +101,9 @@ typedef struct {
 #define TT_FLAG_NO_ORTHO 0x2u
 #define TT_FLAG_PROFILE_OPS 0x4u /* time every chain operation (tt_stream_op_profile) */
 /* TT_FLAG_AUTOTUNE: at create, time candidate launch shapes of the two slice
- * passes for this stream's shape and precision (once per process and shape,
- * on hip_stream, which is synchronised) and use the fastest; streams of one
+ * passes for this stream's shape and precision (with BF16, pass 2's kernel
+ * too: staged through LDS or direct; once per process and shape, on
+ * hip_stream, which is synchronised) and use the fastest; streams of one
  * shape then share the plan, alone or in a batch.  With split_point = 0 (and
  * without TT_FLAG_NO_ORTHO) it also picks k*: up to three split points whose
  * modelled side traffic (P_k + J_k) r_k is within 4x of the smallest are timed
