@@ -178,20 +178,17 @@ def batched_section(torch, n_streams, rounds, warmup, compute, tune):
     return out
 
 
-def serving_section(torch, spec, n_streams, rate_hz, duration, compute, tune, max_wave, lanes, budget_slices):
+def serving_section(torch, spec, frames, n_streams, rate_hz, duration, compute, tune, max_wave, lanes,
+                    budget_slices, single_seconds):
     """Serving: n_streams streams of the config-3 shape with Poisson arrivals at
     rate_hz each (seeded exponential gaps) for `duration` seconds, served with
     continuous batching (TTServer) under an HBM budget of budget_slices slices;
-    then the same arrival trace for a quarter of the time through one-at-a-time
-    single-stream serving.  Slices come from a pool of resident frames."""
+    then the first single_seconds of the same arrival trace through
+    one-at-a-time single-stream serving.  Slices come from the resident frame
+    pool `frames` (more bytes than the Infinity Cache holds)."""
     from paper_2606_31061_amd import TTServer, TTStream
     from ttgen import init_cores
-    pool_n = 8
-    frames = []
-    for t in range(1, pool_n + 1):
-        x = torch.from_numpy(np.ascontiguousarray(spec.frame(t).reshape(-1, order="F"))).cuda()
-        frames.append(x.to(torch.bfloat16) if compute == "bf16" else x)
-    torch.cuda.synchronize()
+    pool_n = len(frames)
     slice_bytes = frames[0].numel() * frames[0].element_size()
     rng = np.random.Generator(np.random.PCG64(1005))
 
@@ -241,37 +238,72 @@ def serving_section(torch, spec, n_streams, rate_hz, duration, compute, tune, ma
     cont = run(arr, max_wave, lanes, budget)
     log(f"continuous batching: {cont['updates_per_s']:.0f} updates/s, p50 {cont['latency_ms']['p50']:.2f} ms "
         f"p99 {cont['latency_ms']['p99']:.2f} ms, mean wave {cont['mean_wave']:.1f}")
-    short = [a for a in arr if a[0] < duration / 4]
+    short = [a for a in arr if a[0] < single_seconds]
     single = run(short, 1, 1, 0)
     log(f"single-stream serving ({len(short)} requests): {single['updates_per_s']:.0f} updates/s, "
         f"p50 {single['latency_ms']['p50']:.2f} ms p99 {single['latency_ms']['p99']:.2f} ms")
-    return {"workload": f"c5_{n_streams}_streams_c3_shape_poisson_{rate_hz:g}hz",
+    return {"workload": f"c5_{n_streams}_streams_c3_shape_poisson_{rate_hz:g}hz", "compute": compute,
             "offered_updates_per_s": n_streams * rate_hz, "duration_s": duration,
+            "frame_pool": pool_n, "frame_pool_bytes": pool_n * slice_bytes,
             "max_wave": max_wave, "lanes": lanes, "hbm_budget_bytes": budget,
-            "continuous_batching": cont, "single_stream": single}
+            "continuous_batching": cont, "single_stream": single,
+            "single_stream_trace_s": single_seconds}
 
 
-def cpu_baseline(spec, seconds_budget: float):
-    """The FP64 oracle as it stands, timed on the host on a bounded sample."""
-    from oracle import ttals
+def host_description():
+    """nproc and the CPU model of the host the oracle runs on."""
+    model = "unknown"
     try:
-        from threadpoolctl import threadpool_info
-        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
-    except Exception:
-        threads = os.cpu_count() or 1
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        nproc = os.cpu_count() or 1
+    return {"nproc": nproc, "cpu_model": model}
+
+
+def _oracle_rate(spec, seconds_budget, max_slices=50):
+    from oracle import ttals
     cores, g = spec.init()
     n, t_used = 0, 0.0
     t = 1
-    while t_used < seconds_budget and t <= 50:
+    while t_used < seconds_budget and t <= max_slices:
         X = spec.frame(t)
         t0 = time.perf_counter()
         cores, g, _ = ttals.online_step(cores, g, X)
         t_used += time.perf_counter() - t0
         n += 1
         t += 1
-    return {"value": n / t_used, "unit": "slice updates/s", "cores": int(threads), "kind": "oracle",
-            "sample": f"first {n} slices of the same stream (literal FP64 Algorithm 1, NumPy), "
-                      f"{t_used:.1f} s of CPU work"}
+    return n, t_used
+
+
+def cpu_baseline(spec, seconds_budget: float):
+    """The FP64 oracle as it stands, timed on the host on a bounded sample,
+    twice: on every host core (the BLAS thread pool's default) and on one
+    thread (the paper's single-thread setting, Section 5)."""
+    try:
+        from threadpoolctl import threadpool_info, threadpool_limits
+        threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    except Exception:
+        threadpool_limits = None
+        threads = os.cpu_count() or 1
+    n, t_used = _oracle_rate(spec, seconds_budget / 2)
+    out = {"value": n / t_used, "unit": "slice updates/s", "cores": int(threads), "kind": "oracle",
+           "sample": f"first {n} slices of the same stream (literal FP64 Algorithm 1, NumPy), "
+                     f"{t_used:.1f} s of CPU work on {threads} threads",
+           "host": host_description()}
+    if threadpool_limits is not None:
+        with threadpool_limits(limits=1):
+            n1, t1 = _oracle_rate(spec, seconds_budget / 2)
+        out["single_thread"] = {"value": n1 / t1, "unit": "slice updates/s", "cores": 1,
+                                "sample": f"first {n1} slices, {t1:.1f} s of CPU work"}
+    return out
 
 
 def write_traffic(fetch_db, write_db, workload, compute):
@@ -327,17 +359,22 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="c3", choices=["c3", "c2"])
     ap.add_argument("--latency-steps", type=int, default=200)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=24.0,
+                    help="CPU seconds of the oracle sample, split between the all-core and the one-thread run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-reps", type=int, default=50)
     ap.add_argument("--compute", default="f32", choices=["f32", "bf16"],
-                    help="contraction precision; bf16 also stores the slices as BF16")
+                    help="contraction precision of the headline; bf16 also stores the slices as BF16")
+    ap.add_argument("--no-other-precision", action="store_true",
+                    help="skip the single-stream measurement in the other contraction precision")
     ap.add_argument("--batch", type=int, default=64,
                     help="streams in the batched measurement (0: skip it)")
     ap.add_argument("--batch-rounds", type=int, default=20)
     ap.add_argument("--serve-streams", type=int, default=256,
                     help="streams in the serving measurement (0: skip it)")
-    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--serve-seconds", type=float, default=5.0)
+    ap.add_argument("--serve-single-seconds", type=float, default=2.0,
+                    help="seconds of the same trace replayed through one-at-a-time serving")
     ap.add_argument("--serve-rate", type=float, default=30.0)
     ap.add_argument("--no-autotune", action="store_true",
                     help="use the default pass launch shapes instead of tuning them for the workload")
@@ -361,83 +398,24 @@ def main():
         raise SystemExit(2)
 
     import torch
-    from paper_2606_31061_amd import TTStream
 
     assert torch.cuda.is_available(), "bench needs a GPU"
     torch.cuda.set_device(0)
     spec, pool_n = make_workload(args.workload, args.pool or None)
     log(f"workload {spec.name}: modes {spec.modes} ranks {spec.ranks}; generating {pool_n} frames")
-    pool = []
+    pools = {"f32": []}
     for t in range(1, pool_n + 1):
         X = spec.frame(t)
-        x = torch.from_numpy(np.ascontiguousarray(X.reshape(-1, order="F"))).cuda()
-        pool.append(x.to(torch.bfloat16) if args.compute == "bf16" else x)
+        pools["f32"].append(torch.from_numpy(np.ascontiguousarray(X.reshape(-1, order="F"))).cuda())
+    pools["bf16"] = [x.to(torch.bfloat16) for x in pools["f32"]]
     torch.cuda.synchronize()
-    cores, g = spec.init()
     tune = not args.no_autotune
-    s = TTStream(spec.modes, spec.ranks, init=(cores, g), compute=args.compute, autotune=tune)
-    info = s.info()
-    k = info["split_point"]
-    P = int(np.prod(spec.modes[:k]))
-    J = int(np.prod(spec.modes[k:]))
-    r = spec.ranks[k - 1]
-    log(f"split point k*={k}: P={P} J={J} r={r}; device bytes {info['device_bytes']}")
+    other = "bf16" if args.compute == "f32" else "f32"
 
-    for i in range(args.warmup):
-        s.push(pool[i % pool_n])
-    s.synchronize()
-    log(f"warmup {args.warmup} done")
-
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        s.push(pool[(args.warmup + i) % pool_n])
-    s.synchronize()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
-    log(f"timed {args.steps} steps in {elapsed:.4f} s")
-
-    # per-slice latency: push to committed state, one slice at a time
-    lat = [float("nan")]
-    for i in range(args.latency_steps):
-        if i == 0:
-            lat = []
-        ts = time.perf_counter()
-        s.push(pool[i % pool_n])
-        s.synchronize()
-        lat.append((time.perf_counter() - ts) * 1e3)
-    dev_ms = s.last_push_ms()
-    s.close()
-    log(f"latency p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
-
-    # the passes inside the update, and optionally the chain's operations
-    sp = TTStream(spec.modes, spec.ranks, init=(cores, g), profile_ops=True, compute=args.compute, autotune=tune)
-    kt = time_passes_in_update(sp, pool, args.kernel_reps)
-    # the pass kernels alone, launched back to back over the resident frames
-    # (HIP events around the whole run on the stream that launches them)
-    kb = sp.time_passes(pool, reps=args.kernel_reps)
-    knames = sp.pass_kernels()
-    if args.profile_ops:
-        prof = sp.op_profile()
-        tot = sum(p[2] for p in prof)
-        log(f"chain operations of one update: {len(prof)} ops, {tot:.1f} us on the chain workgroup")
-        for i, (kind, dims, us) in enumerate(prof):
-            log(f"  op {i:3d} {kind:6s} m={dims[0]:6d} n={dims[1]:6d} k={dims[2]:6d} {us:9.2f} us")
-    sp.close()
-    b1, b2 = pass_bytes(P, J, r, 2 if args.compute == "bf16" else 4)
-    gb = {key: (b1 if key.startswith("pass1") else b2) / (ms * 1e-3) / 1e9 for key, ms in kt.items()}
-    log(f"in the update (events around each pass): pass1 {kt['pass1']*1e3:.1f} us (contraction kernel "
-        f"{kt['pass1_kernel']*1e3:.1f} us), pass2 {kt['pass2']*1e3:.1f} us (contraction kernel "
-        f"{kt['pass2_kernel']*1e3:.1f} us)")
-    log(f"back to back: pass1 contraction {kb['pass1_kernel']:.2f} us + reduction {kb['pass1_reduce']:.2f} us; "
-        f"pass2 contraction {kb['pass2_kernel']:.2f} us + reduction {kb['pass2_reduce']:.2f} us")
-    # the dominant kernel: the slower of the two contraction kernels
-    dom = "pass1" if kb["pass1_kernel"] >= kb["pass2_kernel"] else "pass2"
-    kname = knames[0] if dom == "pass1" else knames[1]
-    dom_bytes = b1 if dom == "pass1" else b2
-    achieved = dom_bytes / (kb[dom + "_kernel"] * 1e-6) / 1e9
-    traffic = measured_traffic(spec.name, args.compute, kname)
+    main_res = single_stream_section(torch, spec, pools[args.compute], args.compute, tune, args)
+    other_res = None
+    if not args.no_other_precision:
+        other_res = single_stream_section(torch, spec, pools[other], other, tune, args, quiet=True)
 
     if args.copy_calibration:
         # a plain copy of known size: rocprofv3's FETCH_SIZE / WRITE_SIZE of this
@@ -454,23 +432,26 @@ def main():
 
     serving = None
     if args.serve_streams > 0:
-        serving = serving_section(torch, spec, args.serve_streams, args.serve_rate, args.serve_seconds, args.compute,
-                                  tune, max_wave=32, lanes=2, budget_slices=24)
+        serving = {}
+        for c in (args.compute, other):
+            serving[c] = serving_section(torch, spec, pools[c], args.serve_streams, args.serve_rate,
+                                         args.serve_seconds, c, tune, max_wave=32, lanes=2, budget_slices=24,
+                                         single_seconds=args.serve_single_seconds)
 
     cpu = None
     if not args.no_cpu_baseline:
-        log("timing the FP64 oracle on the host")
+        log("timing the FP64 oracle on the host (all cores, then one thread)")
         cpu = cpu_baseline(spec, args.cpu_seconds)
 
-    value = args.steps / elapsed
+    k, P, J, r = main_res["split"]
     line = {
         "metric": "TT-ALS slice updates/s, HBM GB/s vs peak; p50/p99 per-slice latency",
-        "value": value,
+        "value": main_res["value"],
         "unit": "slice updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed * 1e3 / args.steps,
+        "ms_per_step": main_res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -486,22 +467,111 @@ def main():
             "parallelism": "single stream, one GPU",
             "pass_plans": "tuned" if tune else "default",
         },
+        "latency_ms": main_res["latency_ms"],
+        "roofline": main_res["roofline"],
+        "slice_kernels": main_res["slice_kernels"],
+        "other_precision": other_res and {key: other_res[key] for key in
+                                          ("compute", "value", "ms_per_step", "latency_ms", "roofline",
+                                           "slice_kernels")},
+        "batched": batched,
+        "serving": serving,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def single_stream_section(torch, spec, pool, compute, tune, args, quiet=False):
+    """The headline measurement for one contraction precision: K timed
+    updates of one stream over the resident frame pool, per-slice latency,
+    and the slice-pass kernels (the roofline kernel, and the update-level
+    fraction of the HBM roofline)."""
+    from paper_2606_31061_amd import TTStream
+    pool_n = len(pool)
+    cores, g = spec.init()
+    s = TTStream(spec.modes, spec.ranks, init=(cores, g), compute=compute, autotune=tune)
+    info = s.info()
+    k = info["split_point"]
+    P = int(np.prod(spec.modes[:k]))
+    J = int(np.prod(spec.modes[k:]))
+    r = spec.ranks[k - 1]
+    log(f"[{compute}] split point k*={k}: P={P} J={J} r={r}; device bytes {info['device_bytes']}")
+
+    for i in range(args.warmup):
+        s.push(pool[i % pool_n])
+    s.synchronize()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        s.push(pool[(args.warmup + i) % pool_n])
+    s.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    log(f"[{compute}] timed {args.steps} steps in {elapsed:.4f} s: {args.steps / elapsed:.0f} updates/s")
+
+    # per-slice latency: push to committed state, one slice at a time
+    lat = []
+    for i in range(args.latency_steps):
+        ts = time.perf_counter()
+        s.push(pool[i % pool_n])
+        s.synchronize()
+        lat.append((time.perf_counter() - ts) * 1e3)
+    dev_ms = s.last_push_ms()
+    s.close()
+    log(f"[{compute}] latency p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms")
+
+    # the passes inside the update, and optionally the chain's operations
+    sp = TTStream(spec.modes, spec.ranks, init=(cores, g), profile_ops=True, compute=compute, autotune=tune)
+    kt = time_passes_in_update(sp, pool, args.kernel_reps)
+    # the pass kernels alone, launched back to back over the resident frames
+    # (HIP events around the whole run on the stream that launches them)
+    kb = sp.time_passes(pool, reps=args.kernel_reps)
+    knames = sp.pass_kernels()
+    if args.profile_ops and not quiet:
+        prof = sp.op_profile()
+        tot = sum(p[2] for p in prof)
+        log(f"chain operations of one update: {len(prof)} ops, {tot:.1f} us on the chain workgroup")
+        for i, (kind, dims, us) in enumerate(prof):
+            log(f"  op {i:3d} {kind:6s} m={dims[0]:6d} n={dims[1]:6d} k={dims[2]:6d} {us:9.2f} us")
+    sp.close()
+    b1, b2 = pass_bytes(P, J, r, 2 if compute == "bf16" else 4)
+    gb = {key: (b1 if key.startswith("pass1") else b2) / (ms * 1e-3) / 1e9 for key, ms in kt.items()}
+    log(f"[{compute}] in the update: pass1 {kt['pass1']*1e3:.1f} us (contraction kernel "
+        f"{kt['pass1_kernel']*1e3:.1f} us), pass2 {kt['pass2']*1e3:.1f} us (contraction kernel "
+        f"{kt['pass2_kernel']*1e3:.1f} us)")
+    log(f"[{compute}] back to back: pass1 contraction {kb['pass1_kernel']:.2f} us + reduction "
+        f"{kb['pass1_reduce']:.2f} us; pass2 contraction {kb['pass2_kernel']:.2f} us + reduction "
+        f"{kb['pass2_reduce']:.2f} us")
+    # the dominant kernel: the slower of the two contraction kernels
+    dom = "pass1" if kb["pass1_kernel"] >= kb["pass2_kernel"] else "pass2"
+    kname = knames[0] if dom == "pass1" else knames[1]
+    dom_bytes = b1 if dom == "pass1" else b2
+    achieved = dom_bytes / (kb[dom + "_kernel"] * 1e-6) / 1e9
+    traffic = measured_traffic(spec.name, compute, kname)
+    ms_step = elapsed * 1e3 / args.steps
+    update_gbs = (b1 + b2) / (ms_step * 1e-3) / 1e9
+    return {
+        "compute": compute,
+        "split": (k, P, J, r),
+        "value": args.steps / elapsed,
+        "ms_per_step": ms_step,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "device_last": dev_ms},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "bytes_per_launch": dom_bytes,
-                     "kernel_us": kb[dom + "_kernel"]},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_source": (f"{os.path.relpath(TRAFFIC_FILE, ROOT)}: rocprofv3 FETCH_SIZE and WRITE_SIZE "
+                                        f"of {kname} on the current kernel source, scaled by a 256 MiB copy")
+                     if traffic is not None else None,
+                     "bytes_per_launch": dom_bytes, "kernel_us": kb[dom + "_kernel"],
+                     "update_bytes": b1 + b2, "update_gbs": update_gbs,
+                     "update_frac": update_gbs / HBM_PEAK_GBS},
         "slice_kernels": {"pass1_bytes": b1, "pass2_bytes": b2,
                           "back_to_back_us": kb,
                           "back_to_back_gbs": {"pass1_kernel": b1 / (kb["pass1_kernel"] * 1e-6) / 1e9,
                                                "pass2_kernel": b2 / (kb["pass2_kernel"] * 1e-6) / 1e9},
                           "in_update_us": {key: ms * 1e3 for key, ms in kt.items()},
                           "in_update_gbs": gb},
-        "batched": batched,
-        "serving": serving,
-        "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
 
 
 if __name__ == "__main__":

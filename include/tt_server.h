@@ -19,9 +19,18 @@
  * whole budget is admitted alone).
  *
  * Slices are device pointers owned by the caller; a slice must stay valid
- * until its request is reported by tt_server_take.  While registered, a
- * stream must not be pushed directly or be a member of a batch.  A handle is
- * not internally synchronised.
+ * until its request is reported by tt_server_take.
+ *
+ * Registered streams.  While registered (from tt_server_add until the server
+ * is destroyed), a stream's updates run on the server's lanes:
+ * tt_stream_push_slice and tt_stream_time_passes on it return TT_ERR_STATE,
+ * and tt_batch_create refuses it.  Every other tt_stream_* call that reads or
+ * writes its state (synchronize, time, get_state, set_state, get_history,
+ * reconstruct, op_profile, destroy) first waits for the last wave a lane
+ * launched for it, so it sees the state after the stream's latest admitted
+ * request.  Destroying a registered stream drops its still-queued requests
+ * (they are never reported) and later submits for its id return
+ * TT_ERR_INVALID_ARG.  A server handle is not internally synchronised.
  */
 #ifndef TT_SERVER_H
 #define TT_SERVER_H
@@ -43,12 +52,15 @@ typedef struct {
 /* Errors: INVALID_ARG (null or out-of-range fields), DEVICE, OOM. */
 tt_status tt_server_create(const tt_server_config* cfg, tt_server** out);
 
-/* Registers stream s (on the current device, not profiled, not already
- * registered) and returns its id (0, 1, ... in order of registration). */
+/* Registers stream s (on the current device, not profiled, not registered
+ * with any server) and returns its id (0, 1, ... in order of registration).
+ * Errors: INVALID_ARG (null, destroyed or profiled stream, another device,
+ * already registered here), STATE (registered with another server), DEVICE. */
 tt_status tt_server_add(tt_server* sv, tt_stream* s, int32_t* id);
 
 /* Queues one slice for stream id; tag is returned with the result.  The
- * request's latency is counted from this call. */
+ * request's latency is counted from this call.  Errors: INVALID_ARG (null
+ * slice, bad dtype, unknown id or a destroyed stream). */
 tt_status tt_server_submit(tt_server* sv, int32_t id, const void* slice, tt_dtype dtype, uint64_t tag);
 
 /* Retires finished waves, admits queued requests and launches waves on free
@@ -71,7 +83,8 @@ tt_status tt_server_take(tt_server* sv, int64_t cap, uint64_t* tags, double* lat
 tt_status tt_server_stats(const tt_server* sv, int64_t* waves, int64_t* retired, int64_t* queued,
                           int64_t* in_flight, uint64_t* peak_bytes);
 
-/* Waits for the server's work and releases it (the streams stay valid). */
+/* Waits for the server's work and releases it; its streams stay valid and are
+ * no longer registered (they may be pushed directly again). */
 tt_status tt_server_destroy(tt_server* sv);
 
 #ifdef __cplusplus

@@ -64,7 +64,12 @@ typedef enum {
 typedef enum { TT_F64 = 0, TT_F32 = 1, TT_BF16 = 2 } tt_dtype;
 
 /* Optional device allocator.  alloc returns device memory of at least `bytes`
- * bytes (256-byte aligned) or NULL; free releases it.  NULL -> hipMalloc. */
+ * bytes (256-byte aligned) or NULL; free releases it.  NULL -> hipMalloc.
+ * The handle calls alloc on the calling thread from tt_stream_create, and
+ * lazily from tt_stream_push_slice (staging of host slices) and
+ * tt_stream_reconstruct (reconstruction buffers); it calls free once for every
+ * block it got, at tt_stream_destroy or when tt_stream_create fails.  A NULL
+ * from alloc makes that call return OOM (create frees what it had). */
 typedef struct {
   void* (*alloc)(size_t bytes, void* ctx);
   void (*free)(void* ptr, void* ctx);
@@ -90,14 +95,20 @@ typedef struct {
 
 /* Flags. */
 #define TT_FLAG_SYNC_PUSH 0x1u   /* push waits for its update and reports NONFINITE */
-/* TT_FLAG_NO_ORTHO: the "w/o Ortho" ablation of Section 5 (the LQ/QR
- * orthogonalisation steps removed).  No normalisation of g, no LQ sweep, no
- * QR: each local problem is solved exactly through the Gram matrices of the
- * non-orthonormal interfaces, G~_k = (A_k^T A_k)^-1 A_k^T X B_k^T
- * (B_k B_k^T)^-1 and G_k <- G~_k, and g = (A^T A)^-1 A^T vec(X); each Gram
- * system S is solved as (S + 1e-12 tr(S)/r I)^-1 (it is singular where the
- * interface has fewer columns than rows).  A non-positive Cholesky pivot
- * rejects the update like a non-finite slice.  TT-ranks <= 32. */
+/* TT_FLAG_NO_ORTHO: the "w/o Ortho" ablation of Section 5, read as removing
+ * the right-orthogonalisation of Section 3.4.1: g is not normalised and there
+ * is no LQ sweep, so the right interfaces B_k built from the current cores are
+ * not orthonormal.  Each local problem is then solved exactly with their Gram
+ * matrix, G~_k = A_k^T X B_k^T (B_k B_k^T)^+ (the pseudo-inverse: (B_k B_k^T)^-1
+ * when r_k <= J_k, else B_k (B_k^T B_k)^-2 B_k^T), with no shift, and the
+ * forward sweep keeps its thin QR (G_k <- Fold(Q), A_{k+1} = A_k x G_k, g =
+ * A_n^T vec(X)) exactly as without the flag.  In exact arithmetic this gives
+ * the same M_t as the method (only the gauge of the right interfaces differs),
+ * so the ablation can show the error growth of the Section 5 ablation table
+ * only through the rounding that the Gram matrices' conditioning amplifies.
+ * A non-positive Cholesky pivot of a Gram matrix rejects the update like a
+ * non-finite slice.  TT-ranks <= 32, and r_k <= I_{k+1}..I_m below the split
+ * point. */
 #define TT_FLAG_NO_ORTHO 0x2u
 #define TT_FLAG_PROFILE_OPS 0x4u /* time every chain operation (tt_stream_op_profile) */
 /* TT_FLAG_AUTOTUNE: at create, time candidate launch shapes of the two slice
@@ -120,12 +131,15 @@ typedef struct {
 tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out);
 
 /* Push slice X_t (I_1*...*I_m elements, i_1 fastest) and run one update.
+ * A stream registered with a server (include/tt_server.h) is updated through
+ * the server only: pushing it directly returns STATE.
  * dtype is the slice's element type (F64, F32 or BF16; converted on load);
  * on_device != 0 means `slice` is a device pointer, else a host pointer (the
  * library copies it to the device first and the call returns after the copy).
  * A slice containing NaN/Inf leaves the state unchanged; that is reported by
  * the next tt_stream_synchronize (or by this call with TT_FLAG_SYNC_PUSH).
- * Errors: INVALID_ARG, DEVICE, NONFINITE (sync mode only). */
+ * Errors: INVALID_ARG, STATE (registered with a server), OOM (host slice
+ * staging), DEVICE, NONFINITE (sync mode only). */
 tt_status tt_stream_push_slice(tt_stream* s, const void* slice, tt_dtype dtype, int on_device);
 
 /* Write M_t = G_1 x ... x G_m x g_n[t], the reconstruction of the latest slice
@@ -135,9 +149,11 @@ tt_status tt_stream_push_slice(tt_stream* s, const void* slice, tt_dtype dtype, 
  * Errors: INVALID_ARG, STATE (no slice pushed yet), DEVICE. */
 tt_status tt_stream_reconstruct(tt_stream* s, void* out, tt_dtype dtype, int on_device);
 
-/* Destroy a handle and free everything it owns (waits for its work first).
- * Further use of the handle returns INVALID_ARG while the memory is still
- * recognisable; callers must not use it. */
+/* Destroy a handle and free everything it owns (waits for its work first; a
+ * stream registered with a server leaves it, see include/tt_server.h).  The
+ * library keeps a registry of live handles and checks every handle against
+ * it before use, so any later call with the destroyed handle returns
+ * INVALID_ARG. */
 tt_status tt_stream_destroy(tt_stream* s);
 
 /* Wait for all work of the handle.  Returns NONFINITE if any update since the
@@ -158,12 +174,15 @@ tt_status tt_stream_info(const tt_stream* s, int64_t* cores_len, int64_t* r_last
 tt_status tt_stream_get_state(tt_stream* s, double* cores, double* g, int64_t* t_out);
 
 /* Replace the state by host FP64 cores and g and set the update counter to t
- * (checkpoint/resume; injection of a reference state).  Waits first. */
+ * (checkpoint/resume; injection of a reference state).  Waits first.  The
+ * history (tt_stream_get_history) restarts empty at t. */
 tt_status tt_stream_set_state(tt_stream* s, const double* cores, const double* g, int64_t t);
 
-/* Copy up to `rows` of the kept temporal rows, oldest first, to host memory
- * (rows x r_m, row-major: one r_m-vector per update).  *rows_out receives the
- * number copied.  STATE if keep_history was 0. */
+/* Copy up to `rows` of the kept temporal rows g_n[t] (Algorithm 1's output
+ * per update), oldest first, to host memory (rows x r_m, row-major: one
+ * r_m-vector per update).  The ring keeps the rows of the last
+ * history_capacity updates since creation or the last set_state.  *rows_out
+ * receives the number copied.  STATE if keep_history was 0. */
 tt_status tt_stream_get_history(tt_stream* s, double* out, int64_t rows, int64_t* rows_out);
 
 /* Largest feasible ranks <= ranks_in: r_k <= r_{k-1} I_k and r_{k-1} <= I_k r_k

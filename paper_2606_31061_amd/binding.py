@@ -40,8 +40,23 @@ class TTError(RuntimeError):
         self.status = status
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, c_size_t, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
+
+
 class tt_allocator(Structure):
-    _fields_ = [("alloc", c_void_p), ("free", c_void_p), ("ctx", c_void_p)]
+    _fields_ = [("alloc", ALLOC_FN), ("free", FREE_FN), ("ctx", c_void_p)]
+
+
+def make_allocator(alloc, free):
+    """tt_allocator from Python callables alloc(nbytes) -> device pointer (int,
+    0 on failure) and free(ptr).  The returned structure holds the ctypes
+    callbacks; keep it alive as long as the handle that uses it."""
+    a = ALLOC_FN(lambda n, ctx: int(alloc(int(n))) or None)
+    f = FREE_FN(lambda p, ctx: free(int(p or 0)))
+    st = tt_allocator(a, f, None)
+    st._keep = (a, f)
+    return st
 
 
 class tt_stream_config(Structure):
@@ -151,7 +166,8 @@ def tt_clamp_ranks(modes: Sequence[int], ranks: Sequence[int]):
 
 def tt_stream_create(modes, ranks, *, init_cores: Optional[np.ndarray] = None, seed: int = 0,
                      hip_stream: int = 0, keep_history: bool = False, history_capacity: int = 0,
-                     split_point: int = 0, flags: int = 0, compute: int = TT_F32):
+                     split_point: int = 0, flags: int = 0, compute: int = TT_F32,
+                     allocator: Optional[tt_allocator] = None):
     lib = load_library()
     m = len(modes)
     cfg = tt_stream_config()
@@ -170,6 +186,8 @@ def tt_stream_create(modes, ranks, *, init_cores: Optional[np.ndarray] = None, s
     cfg.history_capacity = history_capacity
     cfg.split_point = split_point
     cfg.flags = flags
+    if allocator is not None:
+        cfg.allocator = ctypes.pointer(allocator)
     h = c_void_p()
     _check(lib.tt_stream_create(byref(cfg), byref(h)), "tt_stream_create")
     return h
@@ -216,12 +234,14 @@ class TTStream:
     modes: slice mode sizes I_1..I_m; ranks: feasible TT-ranks r_1..r_m.
     init: optional (cores, g) in FP64 (cores[k] of shape (r_{k-1}, I_k, r_k)).
     stream: torch.cuda.Stream (default: the current stream).
+    allocator: optional tt_allocator (make_allocator) for the handle's device
+    memory; it must outlive the handle.
     """
 
     def __init__(self, modes, ranks, init=None, *, seed: int = 0, stream=None, keep_history: bool = False,
                  history_capacity: int = 0, split_point: int = 0, sync_push: bool = False,
                  profile_ops: bool = False, compute: str = "f32", autotune: bool = False,
-                 no_ortho: bool = False):
+                 no_ortho: bool = False, allocator: Optional[tt_allocator] = None):
         self.modes = tuple(int(v) for v in modes)
         self.ranks = tuple(int(v) for v in ranks)
         self.n = int(np.prod(self.modes))
@@ -232,6 +252,7 @@ class TTStream:
             parts.append(np.asarray(g, dtype=np.float64).reshape(-1))
             flat = np.concatenate(parts)
         self._stream = stream
+        self._allocator = allocator
         sp = int(stream.cuda_stream) if stream is not None else self._current_stream_handle()
         self.hip_stream = sp
         self._h = tt_stream_create(self.modes, self.ranks, init_cores=flat, seed=seed, hip_stream=sp,
@@ -240,7 +261,8 @@ class TTStream:
                                    flags=(TT_FLAG_SYNC_PUSH if sync_push else 0)
                                    | (TT_FLAG_PROFILE_OPS if profile_ops else 0)
                                    | (TT_FLAG_AUTOTUNE if autotune else 0)
-                                   | (TT_FLAG_NO_ORTHO if no_ortho else 0))
+                                   | (TT_FLAG_NO_ORTHO if no_ortho else 0),
+                                   allocator=allocator)
         self._lib = load_library()
 
     @staticmethod

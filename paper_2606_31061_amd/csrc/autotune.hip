@@ -57,7 +57,10 @@ struct Scratch {
   }
   void* get(size_t bytes) {
     void* p = nullptr;
-    if (hipMalloc(&p, bytes < 256 ? 256 : bytes) != hipSuccess) return nullptr;
+    if (hipMalloc(&p, bytes < 256 ? 256 : bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
     ptrs.push_back(p);
     return p;
   }

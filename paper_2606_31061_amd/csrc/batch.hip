@@ -320,7 +320,9 @@ struct tt_batch {
 
 namespace {
 
-bool batch_valid(const tt_batch* b) { return b != nullptr && b->magic == kBatchMagic; }
+bool batch_valid(const tt_batch* b) {
+  return b != nullptr && ttk::handle_live(b, ttk::kHandleBatch) && b->magic == kBatchMagic;
+}
 
 void batch_drop_graphs(tt_batch* b) {
   for (hipGraphExec_t& g : b->graph) {
@@ -358,6 +360,7 @@ tt_status tt_batch_create(tt_stream* const* streams, int32_t n, void* hip_stream
     if (s->stream != static_cast<hipStream_t>(hip_stream))
       return fail_msg(TT_ERR_INVALID_ARG, "stream uses another HIP stream");
     if (s->trace) return fail_msg(TT_ERR_INVALID_ARG, "streams with TT_FLAG_PROFILE_OPS cannot be batched");
+    if (s->server) return fail_msg(TT_ERR_STATE, "stream is registered with a server");
     for (int j = 0; j < i; ++j)
       if (streams[j] == s) return fail_msg(TT_ERR_INVALID_ARG, "duplicate stream");
   }
@@ -377,6 +380,7 @@ tt_status tt_batch_create(tt_stream* const* streams, int32_t n, void* hip_stream
   ttk::wave_build(b->wave);
   void* d = nullptr;
   if (hipMalloc(&d, b->wave.bytes) != hipSuccess) {
+    (void)hipGetLastError();
     delete b;
     return fail_msg(TT_ERR_OOM, "batch descriptor allocation failed");
   }
@@ -392,6 +396,7 @@ tt_status tt_batch_create(tt_stream* const* streams, int32_t n, void* hip_stream
     }
     b->host[q] = static_cast<char*>(h);
   }
+  ttk::handle_register(b, ttk::kHandleBatch);
   *out = b;
   return TT_OK;
 }
@@ -476,6 +481,7 @@ tt_status tt_batch_info(const tt_batch* b, int32_t* n_streams, int32_t* n_groups
 tt_status tt_batch_destroy(tt_batch* b) {
   if (!batch_valid(b)) return fail_msg(TT_ERR_INVALID_ARG, "invalid batch");
   (void)hipStreamSynchronize(b->stream);
+  ttk::handle_unregister(b);
   batch_release(b);
   b->magic = kDeadMagic;
   delete b;
@@ -485,6 +491,7 @@ tt_status tt_batch_destroy(tt_batch* b) {
 }  // extern "C"
 
 // ===================================================================== server
+
 
 constexpr uint64_t kServerMagic = 0x5454534552564552ULL;  // "TTSERVER"
 constexpr int kMaxLanes = 8;
@@ -540,7 +547,9 @@ struct tt_server {
 
 namespace {
 
-bool server_valid(const tt_server* s) { return s != nullptr && s->magic == kServerMagic; }
+bool server_valid(const tt_server* s) {
+  return s != nullptr && ttk::handle_live(s, ttk::kHandleServer) && s->magic == kServerMagic;
+}
 
 void lane_release(Lane& L) {
   if (L.stream) (void)hipStreamSynchronize(L.stream);
@@ -567,7 +576,7 @@ tt_status lane_retire(tt_server* sv, Lane& L, bool wait, int* done) {
     const Request& r = L.reqs[k];
     const int rej = L.rej_host[k] - sv->rejected_seen[r.id];
     sv->rejected_seen[r.id] = L.rej_host[k];
-    sv->streams[r.id]->rejected_seen = L.rej_host[k];
+    if (sv->streams[r.id]) sv->streams[r.id]->rejected_seen = L.rej_host[k];
     sv->results.push_back(Result{r.tag, std::chrono::duration<double>(now - r.t0).count(), rej > 0 ? 1 : 0});
     sv->in_flight[r.id] = 0;
     sv->bytes_admitted -= r.bytes;
@@ -624,7 +633,10 @@ tt_status lane_launch(tt_server* sv, Lane& L) {
     const size_t cap = std::max(L.wave.bytes, size_t(1) << 16);
     void* d = nullptr;
     void* h = nullptr;
-    if (hipMalloc(&d, cap) != hipSuccess) return fail_msg(TT_ERR_OOM, "server descriptor buffer");
+    if (hipMalloc(&d, cap) != hipSuccess) {
+      (void)hipGetLastError();
+      return fail_msg(TT_ERR_OOM, "server descriptor buffer");
+    }
     if (hipHostMalloc(&h, cap, hipHostMallocDefault) != hipSuccess) {
       (void)hipFree(d);
       return fail_msg(TT_ERR_OOM, "server staging buffer");
@@ -650,6 +662,8 @@ tt_status lane_launch(tt_server* sv, Lane& L) {
     TT_HIP_RT(hipMemcpyAsync(L.rej_host + k, L.wave.members[k]->rejected, sizeof(int), hipMemcpyDeviceToHost,
                              L.stream));
   TT_HIP_RT(hipEventRecord(L.done, L.stream));
+  // calls on a member's handle (state, reconstruction, destroy) wait for this wave
+  for (tt_stream* m : L.wave.members) m->ext_done = L.done;
   ttk::wave_commit(L.wave);
   L.reqs = std::move(pick);
   L.busy = true;
@@ -685,6 +699,7 @@ tt_status tt_server_create(const tt_server_config* cfg, tt_server** out) {
       return fail_msg(TT_ERR_DEVICE, "server lane creation failed");
     }
   }
+  ttk::handle_register(sv, ttk::kHandleServer);
   *out = sv;
   return TT_OK;
 }
@@ -697,9 +712,12 @@ tt_status tt_server_add(tt_server* sv, tt_stream* s, int32_t* id) {
     return fail_msg(TT_ERR_INVALID_ARG, "stream lives on another device");
   for (const tt_stream* t : sv->streams)
     if (t == s) return fail_msg(TT_ERR_INVALID_ARG, "stream already registered");
+  if (s->server) return fail_msg(TT_ERR_STATE, "stream is registered with another server");
   // the stream's own earlier work completes before the server's lanes use it
   TT_HIP_RT(hipStreamSynchronize(s->stream));
   *id = (int32_t)sv->streams.size();
+  s->server = sv;
+  s->server_id = *id;
   sv->streams.push_back(s);
   sv->in_flight.push_back(0);
   sv->queued.push_back(0);
@@ -710,6 +728,7 @@ tt_status tt_server_add(tt_server* sv, tt_stream* s, int32_t* id) {
 tt_status tt_server_submit(tt_server* sv, int32_t id, const void* slice, tt_dtype dtype, uint64_t tag) {
   if (!server_valid(sv) || !slice) return fail_msg(TT_ERR_INVALID_ARG, "invalid argument");
   if (id < 0 || id >= (int32_t)sv->streams.size()) return fail_msg(TT_ERR_INVALID_ARG, "unknown stream id");
+  if (!sv->streams[id]) return fail_msg(TT_ERR_INVALID_ARG, "the stream of this id was destroyed");
   if (dtype != TT_F64 && dtype != TT_F32 && dtype != TT_BF16) return fail_msg(TT_ERR_INVALID_ARG, "bad dtype");
   sv->queue.push_back(Request{id, slice, dtype, tag, slice_bytes(sv->streams[id], dtype), Clock::now()});
   sv->queued[id] += 1;
@@ -783,9 +802,29 @@ tt_status tt_server_stats(const tt_server* sv, int64_t* waves, int64_t* retired,
 tt_status tt_server_destroy(tt_server* sv) {
   if (!server_valid(sv)) return fail_msg(TT_ERR_INVALID_ARG, "invalid server");
   for (Lane& L : sv->lanes) lane_release(L);
+  for (tt_stream* s : sv->streams)
+    if (s) {  // the lanes (and their events) are gone; the stream is its own again
+      s->server = nullptr;
+      s->server_id = -1;
+      s->ext_done = nullptr;
+    }
+  ttk::handle_unregister(sv);
   sv->magic = kDeadMagic;
   delete sv;
   return TT_OK;
 }
 
 }  // extern "C"
+
+void ttk::server_forget(tt_server* sv, int32_t id) {
+  if (!server_valid(sv) || id < 0 || id >= (int32_t)sv->streams.size()) return;
+  for (auto it = sv->queue.begin(); it != sv->queue.end();) {
+    if (it->id == id) {
+      it = sv->queue.erase(it);
+      sv->queued[id] -= 1;
+    } else {
+      ++it;
+    }
+  }
+  sv->streams[id] = nullptr;
+}

@@ -93,6 +93,13 @@ struct tt_stream {
   ttk::PassBPlan p1b, p2b;   // BF16 contractions
   int rejected_seen = 0;
   int64_t pushes = 0;
+  int64_t hist_t0 = 0;       // update count when the history ring was (re)started
+  // serving: the server the stream is registered with (its lanes, not the
+  // stream's own HIP stream, then run its updates) and the completion event of
+  // the last wave a lane launched for it (owned by the lane)
+  struct tt_server* server = nullptr;
+  int32_t server_id = -1;
+  hipEvent_t ext_done = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evcopy = nullptr;
   // TT_FLAG_PROFILE_OPS: per pass, before it, after its contraction kernel,
   // after its reduction (pass 1: 0, 1, 2; pass 2: 3, 4, 5)
@@ -106,7 +113,27 @@ struct tt_stream {
 
 namespace ttk {
 
-inline bool stream_valid(const tt_stream* s) { return s != nullptr && s->magic == kStreamMagic; }
+// Live handles of every kind: a handle is checked against this registry
+// before it is dereferenced, so a destroyed (freed) handle is rejected rather
+// than read.
+enum HandleKind { kHandleStream = 1, kHandleBatch = 2, kHandleServer = 3 };
+void handle_register(const void* p, int kind);
+void handle_unregister(const void* p);
+bool handle_live(const void* p, int kind);
+
+inline bool stream_valid(const tt_stream* s) {
+  return s != nullptr && handle_live(s, kHandleStream) && s->magic == kStreamMagic;
+}
+
+// Waits for all work that may read or write the stream's state: its own HIP
+// stream and, when a server runs its updates, the last wave a lane launched
+// for it.
+hipError_t stream_quiesce(const tt_stream* s);
+
+// A registered stream is being destroyed: the server drops its queued
+// requests and refuses further ones for that id (its lanes' waves that used
+// the stream have completed: the caller quiesced it).
+void server_forget(struct tt_server* sv, int32_t id);
 
 // Records msg as the calling thread's last error and returns st (std::string form).
 inline tt_status fail_msg(tt_status st, const std::string& msg) { return set_error(st, msg.c_str()); }

@@ -24,9 +24,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <array>
+#include <unordered_map>
 #include <vector>
 
 namespace ttk {
@@ -103,6 +105,36 @@ void normal_fill(std::vector<double>& v, uint64_t seed) {
 
 tt_status ttk::set_error(tt_status st, const char* msg) { return fail(st, msg); }
 
+namespace {
+std::mutex g_handles_mu;
+std::unordered_map<const void*, int>& live_handles() {
+  static std::unordered_map<const void*, int> m;
+  return m;
+}
+}  // namespace
+
+void ttk::handle_register(const void* p, int kind) {
+  std::lock_guard<std::mutex> lk(g_handles_mu);
+  live_handles()[p] = kind;
+}
+
+void ttk::handle_unregister(const void* p) {
+  std::lock_guard<std::mutex> lk(g_handles_mu);
+  live_handles().erase(p);
+}
+
+bool ttk::handle_live(const void* p, int kind) {
+  std::lock_guard<std::mutex> lk(g_handles_mu);
+  const auto it = live_handles().find(p);
+  return it != live_handles().end() && it->second == kind;
+}
+
+hipError_t ttk::stream_quiesce(const tt_stream* s) {
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e == hipSuccess && s->ext_done) e = hipEventSynchronize(s->ext_done);
+  return e;
+}
+
 
 namespace {
 
@@ -115,7 +147,10 @@ void* dev_alloc(tt_stream* s, size_t bytes) {
   if (s->has_alloc) {
     p = s->alloc.alloc(bytes, s->alloc.ctx);
   } else {
-    if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      p = nullptr;
+      (void)hipGetLastError();  // the failure is reported as OOM; it must not resurface at a later launch check
+    }
   }
   if (p) {
     s->owned.push_back(p);
@@ -714,17 +749,15 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
   }
   const bool bf16 = s->compute == TT_BF16;
 
+  // after the first failed allocation nothing more is requested
   bool ok = true;
-  auto D = [&](size_t n) -> double* {
-    double* p = static_cast<double*>(dev_alloc(s, n * sizeof(double)));
+  auto V = [&](size_t bytes) -> void* {
+    void* p = ok ? dev_alloc(s, bytes) : nullptr;
     ok = ok && p;
     return p;
   };
-  auto F = [&](size_t n) -> float* {
-    float* p = static_cast<float*>(dev_alloc(s, n * sizeof(float)));
-    ok = ok && p;
-    return p;
-  };
+  auto D = [&](size_t n) -> double* { return static_cast<double*>(V(n * sizeof(double))); };
+  auto F = [&](size_t n) -> float* { return static_cast<float*>(V(n * sizeof(float))); };
   s->state[0] = D(s->state_len);
   s->state[1] = D(s->state_len);
   s->work = D(s->state_len);
@@ -754,12 +787,11 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
     s->gram_tmp = D(std::max<int64_t>(qrmax, 2 * 32 * 32));
     s->gram_g = D(gtmax);
   }
-  s->ws = bf16 ? static_cast<float*>(dev_alloc(s, s->p1b.ws_bytes)) : F(s->p1.ws_floats);
-  if (bf16) s->ws2 = static_cast<float*>(dev_alloc(s, s->p2b.ws_bytes));
-  if (bf16 && (!s->ws || !s->ws2)) ok = false;
-  s->flag = static_cast<int*>(dev_alloc(s, sizeof(int) * 2));
-  s->rejected = s->flag + 1;
-  s->tdev = static_cast<int64_t*>(dev_alloc(s, sizeof(int64_t)));
+  s->ws = bf16 ? static_cast<float*>(V(s->p1b.ws_bytes)) : F(s->p1.ws_floats);
+  if (bf16) s->ws2 = static_cast<float*>(V(s->p2b.ws_bytes));
+  s->flag = static_cast<int*>(V(sizeof(int) * 2));
+  s->rejected = s->flag ? s->flag + 1 : nullptr;
+  s->tdev = static_cast<int64_t*>(V(sizeof(int64_t)));
   if (cfg->keep_history) {
     s->hist_cap = cfg->history_capacity > 0 ? cfg->history_capacity : 1024;
     s->hist = D((size_t)s->hist_cap * r[m_]);
@@ -822,6 +854,7 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
   }
   TT_HIP_BAIL(hipStreamSynchronize(s->stream));
 #undef TT_HIP_BAIL
+  ttk::handle_register(s, ttk::kHandleStream);
   *out = s;
   return TT_OK;
 }
@@ -830,6 +863,7 @@ tt_status tt_stream_push_slice(tt_stream* s, const void* slice, tt_dtype dtype, 
   if (!valid(s)) return fail(TT_ERR_INVALID_ARG, "invalid handle");
   if (!slice) return fail(TT_ERR_INVALID_ARG, "null slice");
   if (dtype != TT_F64 && dtype != TT_F32 && dtype != TT_BF16) return fail(TT_ERR_INVALID_ARG, "bad dtype");
+  if (s->server) return fail(TT_ERR_STATE, "the stream is registered with a server; submit its slices there");
   const void* X = slice;
   if (!on_device) {
     const size_t bytes = (size_t)s->N * dtype_size(dtype);
@@ -858,7 +892,7 @@ tt_status tt_stream_push_slice(tt_stream* s, const void* slice, tt_dtype dtype, 
 
 tt_status tt_stream_synchronize(tt_stream* s) {
   if (!valid(s)) return fail(TT_ERR_INVALID_ARG, "invalid handle");
-  TT_HIP(hipStreamSynchronize(s->stream));
+  TT_HIP(ttk::stream_quiesce(s));
   int rej = 0;
   TT_HIP(hipMemcpy(&rej, s->rejected, sizeof(int), hipMemcpyDeviceToHost));
   if (rej > s->rejected_seen) {
@@ -870,7 +904,7 @@ tt_status tt_stream_synchronize(tt_stream* s) {
 
 tt_status tt_stream_time(tt_stream* s, int64_t* t_out) {
   if (!valid(s) || !t_out) return fail(TT_ERR_INVALID_ARG, "invalid handle or null output");
-  TT_HIP(hipStreamSynchronize(s->stream));
+  TT_HIP(ttk::stream_quiesce(s));
   TT_HIP(hipMemcpy(t_out, s->tdev, sizeof(int64_t), hipMemcpyDeviceToHost));
   return TT_OK;
 }
@@ -887,7 +921,7 @@ tt_status tt_stream_info(const tt_stream* s, int64_t* cores_len, int64_t* r_last
 
 tt_status tt_stream_get_state(tt_stream* s, double* cores, double* g, int64_t* t_out) {
   if (!valid(s)) return fail(TT_ERR_INVALID_ARG, "invalid handle");
-  TT_HIP(hipStreamSynchronize(s->stream));
+  TT_HIP(ttk::stream_quiesce(s));
   if (cores) TT_HIP(hipMemcpy(cores, s->master(), sizeof(double) * s->cores_len, hipMemcpyDeviceToHost));
   if (g) TT_HIP(hipMemcpy(g, s->g_of(s->master()), sizeof(double) * s->r[s->m], hipMemcpyDeviceToHost));
   if (t_out) TT_HIP(hipMemcpy(t_out, s->tdev, sizeof(int64_t), hipMemcpyDeviceToHost));
@@ -901,10 +935,11 @@ tt_status tt_stream_set_state(tt_stream* s, const double* cores, const double* g
     if (!std::isfinite(cores[i])) return fail(TT_ERR_NONFINITE, "cores contain NaN/Inf");
   for (int64_t i = 0; i < s->r[s->m]; ++i)
     if (!std::isfinite(g[i])) return fail(TT_ERR_NONFINITE, "g contains NaN/Inf");
-  TT_HIP(hipStreamSynchronize(s->stream));
+  TT_HIP(ttk::stream_quiesce(s));
   TT_HIP(hipMemcpy(s->master(), cores, sizeof(double) * s->cores_len, hipMemcpyHostToDevice));
   TT_HIP(hipMemcpy(s->g_of(s->master()), g, sizeof(double) * s->r[s->m], hipMemcpyHostToDevice));
   TT_HIP(hipMemcpy(s->tdev, &t, sizeof(int64_t), hipMemcpyHostToDevice));
+  s->hist_t0 = t;  // the ring holds no row of the new state's past
   return TT_OK;
 }
 
@@ -912,9 +947,10 @@ tt_status tt_stream_get_history(tt_stream* s, double* out, int64_t rows, int64_t
   if (!valid(s) || !out || !rows_out) return fail(TT_ERR_INVALID_ARG, "invalid handle or null output");
   if (!s->hist) return fail(TT_ERR_STATE, "history was not enabled");
   int64_t t = 0;
-  TT_HIP(hipStreamSynchronize(s->stream));
+  TT_HIP(ttk::stream_quiesce(s));
   TT_HIP(hipMemcpy(&t, s->tdev, sizeof(int64_t), hipMemcpyDeviceToHost));
-  const int64_t have = std::min(t, s->hist_cap);
+  // rows written since creation or the last set_state: update u wrote row u % hist_cap
+  const int64_t have = std::min(std::max<int64_t>(t - s->hist_t0, 0), s->hist_cap);
   const int64_t n = std::min(have, rows);
   const int64_t rm = s->r[s->m];
   std::vector<double> ring((size_t)s->hist_cap * rm);
@@ -932,12 +968,12 @@ tt_status tt_stream_reconstruct(tt_stream* s, void* out, tt_dtype dtype, int on_
   if (!valid(s) || !out) return fail(TT_ERR_INVALID_ARG, "invalid handle or null output");
   if (dtype != TT_F64 && dtype != TT_F32) return fail(TT_ERR_INVALID_ARG, "reconstruct dtype must be F64/F32");
   int64_t t = 0;
-  TT_HIP(hipStreamSynchronize(s->stream));
+  TT_HIP(ttk::stream_quiesce(s));
   TT_HIP(hipMemcpy(&t, s->tdev, sizeof(int64_t), hipMemcpyDeviceToHost));
   if (t == 0) return fail(TT_ERR_STATE, "no slice has been pushed");
-  if (!s->recon[0]) {
-    s->recon[0] = static_cast<double*>(dev_alloc(s, sizeof(double) * s->N));
-    s->recon[1] = static_cast<double*>(dev_alloc(s, sizeof(double) * s->N));
+  if (!s->recon[0] || !s->recon[1]) {
+    if (!s->recon[0]) s->recon[0] = static_cast<double*>(dev_alloc(s, sizeof(double) * s->N));
+    if (s->recon[0] && !s->recon[1]) s->recon[1] = static_cast<double*>(dev_alloc(s, sizeof(double) * s->N));
     if (!s->recon[0] || !s->recon[1]) return fail(TT_ERR_OOM, "reconstruction buffers");
   }
   hipStream_t st = s->stream;
@@ -982,7 +1018,7 @@ tt_status tt_stream_op_profile(tt_stream* s, int64_t cap, int32_t* kinds, int64_
   if (!valid(s) || !count || (cap > 0 && (!kinds || !dims || !us))) return fail(TT_ERR_INVALID_ARG, "null argument");
   if (!s->trace) return fail(TT_ERR_STATE, "stream was not created with TT_FLAG_PROFILE_OPS");
   if (s->traced_plan < 0) return fail(TT_ERR_STATE, "no push yet");
-  TT_HIP(hipStreamSynchronize(s->stream));
+  TT_HIP(ttk::stream_quiesce(s));
   const UpdatePlan& P = s->plan[s->traced_plan];
   std::vector<int64_t> stamps(2 * P.ops.size());
   TT_HIP(hipMemcpy(stamps.data(), s->trace, sizeof(int64_t) * stamps.size(), hipMemcpyDeviceToHost));
@@ -1034,6 +1070,7 @@ tt_status tt_stream_time_passes(tt_stream* s, const void* const* slices, int32_t
   if (dtype != TT_F64 && dtype != TT_F32 && dtype != TT_BF16) return fail(TT_ERR_INVALID_ARG, "bad dtype");
   if (reps < 1 || reps > 100000) return fail(TT_ERR_INVALID_ARG, "reps out of range");
   if (s->pushes == 0) return fail(TT_ERR_STATE, "no push yet");
+  if (s->server) return fail(TT_ERR_STATE, "the stream is registered with a server");
   const int ks = s->kstar;
   const int64_t P = s->Pk[ks], J = s->Jk[ks];
   const int r = (int)s->r[ks];
@@ -1075,7 +1112,9 @@ tt_status tt_stream_time_passes(tt_stream* s, const void* const* slices, int32_t
 
 tt_status tt_stream_destroy(tt_stream* s) {
   if (!valid(s)) return fail(TT_ERR_INVALID_ARG, "invalid handle");
-  (void)hipStreamSynchronize(s->stream);
+  (void)ttk::stream_quiesce(s);
+  if (s->server) ttk::server_forget(s->server, s->server_id);
+  ttk::handle_unregister(s);
   release(s);
   s->magic = kDead;
   delete s;

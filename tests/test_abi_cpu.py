@@ -23,7 +23,7 @@ def _lib():
 
 def _declared_functions():
     names = []
-    for h in ("tt_stream.h", "tt_kernels.h"):
+    for h in sorted(f for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h")):
         text = open(os.path.join(ROOT, "include", h)).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
         names += re.findall(r"\b(tt_[a-z0-9_]+)\s*\(", text)
@@ -33,7 +33,10 @@ def _declared_functions():
 def test_library_exports_every_declared_symbol():
     binding, lib = _lib()
     names = _declared_functions()
-    assert len(names) >= 18
+    # every header contributes: stream, batch, server and kernel entry points
+    for prefix in ("tt_stream_", "tt_batch_", "tt_server_", "tt_kernel_"):
+        assert any(n.startswith(prefix) for n in names), prefix
+    assert len(names) >= 40
     handle = ctypes.CDLL(binding.LIB_PATH)
     for n in names:
         assert hasattr(handle, n), f"missing export {n}"
@@ -123,3 +126,26 @@ def test_product_path_does_not_import_the_oracle():
             if f.endswith((".py", ".hip", ".h", ".cpp")):
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
+
+
+def test_unknown_and_destroyed_handles_are_rejected_without_dereference():
+    """A pointer that is not a live handle (never created, or destroyed) is
+    rejected through the library's handle registry before it is read."""
+    binding, lib = _lib()
+    fake = ctypes.create_string_buffer(4096)  # readable memory that is no handle
+    p = ctypes.cast(fake, ctypes.c_void_p)
+    assert lib.tt_stream_synchronize(p) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_stream_destroy(p) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_stream_push_slice(p, p, 1, 1) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_batch_destroy(p) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_server_destroy(p) == binding.TT_ERR_INVALID_ARG
+    assert lib.tt_server_poll(p, None) == binding.TT_ERR_INVALID_ARG
+
+
+def test_allocator_structure_marshals_python_callables():
+    binding, _ = _lib()
+    calls = []
+    al = binding.make_allocator(lambda n: calls.append(("a", n)) or 0, lambda q: calls.append(("f", q)))
+    assert al.alloc(256, None) is None          # the callable's 0 becomes NULL
+    al.free(None, None)
+    assert calls == [("a", 256), ("f", 0)]

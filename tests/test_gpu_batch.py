@@ -123,10 +123,10 @@ def test_nonfinite_slice_is_rejected_for_its_member_only():
     batch.close()
 
 
-def _mixed_members(n, seed, T, max_elems=60000):
+def _mixed_members(n, seed, T, max_elems=60000, noise_rel=None):
     """Streams of uneven order (3-5), mode sizes and ranks ({4,8,16,32},
-    clamped to feasibility), low rank plus noise; every third member uses
-    BF16 contractions."""
+    clamped to feasibility), low rank plus noise (sigma 1e-2, or noise_rel
+    times the signal's RMS); every third member uses BF16 contractions."""
     from paper_2606_31061_amd.binding import tt_clamp_ranks
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
@@ -139,7 +139,8 @@ def _mixed_members(n, seed, T, max_elems=60000):
         rank = int(rng.choice([4, 8, 16, 32]))
         ranks = tuple(int(v) for v in tt_clamp_ranks(modes, [rank] * len(modes)))
         q = len(out)
-        st = exact_tt_stream(modes, ranks, ranks, T, seed + 10 * q, seed + 10 * q + 1, sigma=1e-2)
+        st = exact_tt_stream(modes, ranks, ranks, T, seed + 10 * q, seed + 10 * q + 1, sigma=1e-2,
+                             noise_rel=noise_rel)
         out.append((st, "bf16" if q % 3 == 2 else "f32"))
     return out
 

@@ -5,8 +5,9 @@ contractions, against the FP64 oracle on the same slices and initial cores.
 
 Each case prints one line `[precision] config ... RE_oracle ... dRE_f32 ...
 dRE_bf16 ...` (the deviation |RE_gpu - RE_oracle|) and asserts the bounds:
-FP32 within 1e-5 of the oracle (FP32 slices and interfaces, FP64 chain), BF16
-within RE_TOL_BF16 (the slice and the interface rounded to BF16 at 2^-9
+FP32 within 1e-5 of the oracle's error, relative (|RE_f32 - RE_oracle| <=
+1e-5 RE_oracle: FP32 slices and interfaces, FP64 chain), BF16 within
+RE_TOL_BF16 absolute (the slice and the interface rounded to BF16 at 2^-9
 relative per entry)."""
 
 import sys
@@ -20,14 +21,14 @@ from ttgen import config_c1, config_c2, config_c3
 
 pytestmark = pytest.mark.gpu
 
-RE_TOL_F32 = 1e-5
-RE_TOL_BF16 = 3e-3
+RE_TOL_F32 = 1e-5      # relative to the oracle's RE
+RE_TOL_BF16 = 3e-3     # absolute
 
 CASES = {
     # config: (spec factory, slices)
     "c1_order3_32x32_r4": (lambda: config_c1(T=200), 200),
-    "c2_order4_240x320x3_r16": (lambda: config_c2(T=1000), 12),
-    "c3_order9_1080x1920x3_r32": (lambda: config_c3(T=500), 4),
+    "c2_order4_240x320x3_r16": (lambda: config_c2(T=1000), 40),
+    "c3_order9_1080x1920x3_r32": (lambda: config_c3(T=500), 20),
 }
 
 
@@ -60,6 +61,6 @@ def test_precision_per_config(config):
     re_bf16 = float(np.sqrt(_gpu_re(torch, spec, init, xs, "bf16") / xn2))
     d32, d16 = abs(re_f32 - re_or), abs(re_bf16 - re_or)
     print(f"[precision] config {config} slices {T} RE_oracle {re_or:.6e} RE_f32 {re_f32:.6e} "
-          f"dRE_f32 {d32:.2e} RE_bf16 {re_bf16:.6e} dRE_bf16 {d16:.2e}", file=sys.stderr, flush=True)
-    assert d32 <= RE_TOL_F32, (config, re_f32, re_or)
+          f"dRE_f32 {d32:.2e} (rel {d32 / re_or:.2e}) RE_bf16 {re_bf16:.6e} dRE_bf16 {d16:.2e}", file=sys.stderr, flush=True)
+    assert d32 <= RE_TOL_F32 * re_or, (config, re_f32, re_or, d32 / re_or)
     assert d16 <= RE_TOL_BF16, (config, re_bf16, re_or)
