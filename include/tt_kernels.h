@@ -29,6 +29,24 @@ tt_status tt_kernel_pass1(const void* X, tt_dtype x_dtype, int64_t P, int64_t J,
                           void* hip_stream);
 size_t tt_kernel_pass1_workspace(int64_t P, int64_t J, int32_t r);
 
+/* tt_kernel_pass1 without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the FP32 partial tiles go to a static
+ * device array of tt_kernel_pass1_noalloc_max() bytes (32 MiB) that the
+ * library holds on every GPU it runs on until the process ends.  Same
+ * arguments, kernels, launch plan and results (bit for bit) as
+ * tt_kernel_pass1; it allocates nothing.  All calls on one GPU share that
+ * GPU's array: calls whose work overlaps on one GPU (different HIP streams,
+ * or host threads) race on it and must be serialised by the caller (calls on
+ * one HIP stream are ordered).  Nothing in the array needs clearing: every
+ * partial tile is written before it is read.  Errors: as tt_kernel_pass1,
+ * plus TT_ERR_UNSUPPORTED when tt_kernel_pass1_workspace(P, J, r) exceeds
+ * tt_kernel_pass1_noalloc_max() (e.g. 1080 x 5760 slices at r = 32 need
+ * 13 MB), and TT_ERR_DEVICE if the array's device address cannot be found. */
+tt_status tt_kernel_pass1_noalloc(const void* X, tt_dtype x_dtype, int64_t P, int64_t J, int32_t r,
+                                  const float* B, double* Z, int32_t* nonfinite_flag, void* hip_stream);
+size_t tt_kernel_pass1_noalloc_max(void);
+
 /* Pass 2 of an update (Eq. 5 for the cores k > k*, contracted with the left
  * interface first): Y = A^T X, A P x r FP32, Y r x J FP64.  1 <= r <= 64. */
 tt_status tt_kernel_pass2(const void* X, tt_dtype x_dtype, int64_t P, int64_t J, int32_t r,

@@ -130,6 +130,8 @@ def load_library(path: str = LIB_PATH):
         "tt_batch_destroy": (c_int, [sv]),
         "tt_kernel_pass1": (c_int, [sv, c_int, c_int64, c_int64, c_int32, sv, sv, sv, sv, sv]),
         "tt_kernel_pass1_workspace": (c_size_t, [c_int64, c_int64, c_int32]),
+        "tt_kernel_pass1_noalloc": (c_int, [sv, c_int, c_int64, c_int64, c_int32, sv, sv, sv, sv]),
+        "tt_kernel_pass1_noalloc_max": (c_size_t, []),
         "tt_kernel_pass2": (c_int, [sv, c_int, c_int64, c_int64, c_int32, sv, sv, sv, sv]),
         "tt_kernel_qr": (c_int, [c_int32, c_int32, sv, sv, sv, sv, sv]),
         "tt_kernel_pass1_bf16": (c_int, [sv, c_int, c_int64, c_int64, c_int32, sv, sv, sv, sv, sv]),
@@ -418,6 +420,16 @@ def tt_kernel_pass1(X, P: int, J: int, r: int, B, Z, workspace, flag, hip_stream
                                           c_void_p(B.data_ptr()), c_void_p(Z.data_ptr()),
                                           c_void_p(workspace.data_ptr()), c_void_p(flag.data_ptr()),
                                           c_void_p(hip_stream or None))
+
+
+def tt_kernel_pass1_noalloc(X, P: int, J: int, r: int, B, Z, flag, hip_stream: int = 0) -> int:
+    return load_library().tt_kernel_pass1_noalloc(c_void_p(X.data_ptr()), _dtype_code_torch(X), P, J, r,
+                                                  c_void_p(B.data_ptr()), c_void_p(Z.data_ptr()),
+                                                  c_void_p(flag.data_ptr()), c_void_p(hip_stream or None))
+
+
+def tt_kernel_pass1_noalloc_max() -> int:
+    return int(load_library().tt_kernel_pass1_noalloc_max())
 
 
 def tt_kernel_pass1_workspace(P: int, J: int, r: int) -> int:

@@ -2,11 +2,19 @@
 #include "tt_internal.h"
 #include "tt_kernels.h"
 
+#include <mutex>
 #include <string>
 
 namespace ttk {
 hipError_t pass_setup();
 }  // namespace ttk
+
+// Workspace of tt_kernel_pass1_noalloc: a fixed device array, one copy per
+// GPU, held until the process ends.  Host code never passes its name to a
+// kernel: the name is a host-side stand-in; the device address comes from
+// hipGetSymbolAddress, once per device (scratch_ptr below).
+constexpr size_t kNoAllocScratchBytes = size_t(32) << 20;
+static __device__ __align__(256) float scratch[kNoAllocScratchBytes / sizeof(float)];
 
 
 namespace {
@@ -24,6 +32,28 @@ int device_cus() {
 }
 
 ttk::Pass1Plan plan_for(int64_t P, int64_t J, int r) { return ttk::pass1_plan(P, J, r, device_cus()); }
+
+// Device address of this device's `scratch`, looked up on the first call per
+// device (with that device current) and kept; null if the lookup failed.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_ptr(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
 
 size_t lds_limit() {
   int dev = 0, lds = 65536;
@@ -50,6 +80,26 @@ tt_status tt_kernel_pass1(const void* X, tt_dtype x_dtype, int64_t P, int64_t J,
                             static_cast<float*>(workspace), nonfinite_flag);
   return e == hipSuccess ? TT_OK : kfail(TT_ERR_DEVICE, "pass1", e);
 }
+
+tt_status tt_kernel_pass1_noalloc(const void* X, tt_dtype x_dtype, int64_t P, int64_t J, int32_t r, const float* B,
+                                  double* Z, int32_t* nonfinite_flag, void* hip_stream) {
+  if (!X || !B || !Z || !nonfinite_flag) return kfail(TT_ERR_INVALID_ARG, "null");
+  if (P < 1 || J < 1 || r < 1 || r > 64) return kfail(TT_ERR_INVALID_ARG, "size");
+  if (x_dtype != TT_F64 && x_dtype != TT_F32 && x_dtype != TT_BF16) return kfail(TT_ERR_INVALID_ARG, "dtype");
+  const ttk::Pass1Plan pl = plan_for(P, J, r);
+  if (pl.ws_floats * sizeof(float) > kNoAllocScratchBytes)
+    return kfail(TT_ERR_UNSUPPORTED, "pass1_noalloc: the partial tiles of this shape exceed the 32 MiB static "
+                                     "scratch (tt_kernel_pass1_workspace(P, J, r) > tt_kernel_pass1_noalloc_max())");
+  if (ttk::pass_setup() != hipSuccess) return kfail(TT_ERR_DEVICE, "setup");
+  void* ws = nullptr;
+  hipError_t e = scratch_ptr(&ws);
+  if (e != hipSuccess) return kfail(TT_ERR_DEVICE, "pass1_noalloc: hipGetSymbolAddress of the scratch", e);
+  e = ttk::pass1(static_cast<hipStream_t>(hip_stream), X, x_dtype, pl, P, J, r, B, Z, static_cast<float*>(ws),
+                 nonfinite_flag);
+  return e == hipSuccess ? TT_OK : kfail(TT_ERR_DEVICE, "pass1_noalloc", e);
+}
+
+size_t tt_kernel_pass1_noalloc_max(void) { return kNoAllocScratchBytes; }
 
 tt_status tt_kernel_pass2(const void* X, tt_dtype x_dtype, int64_t P, int64_t J, int32_t r, const float* A, double* Y,
                           int32_t* nonfinite_flag, void* hip_stream) {
