@@ -94,7 +94,8 @@ def batched_section(torch, n_streams, rounds, warmup, compute, tune):
     one through the single-stream path."""
     from paper_2606_31061_amd import TTBatch, TTStream, binding
     from ttgen import config_c4_streams
-    specs = config_c4_streams(n_streams, 1004, T=2, clamp=binding.tt_clamp_ranks, max_elems=1 << 21)
+    nfr = 3  # frames per stream: the round's frame set (317 MB) exceeds the 256 MB Infinity Cache
+    specs = config_c4_streams(n_streams, 1004, T=nfr, clamp=binding.tt_clamp_ranks, max_elems=1 << 21)
     orders = sorted(len(sp.modes) + 1 for sp in specs)
     elems = [sp.n_elems for sp in specs]
     log(f"batched workload: {n_streams} streams, orders {orders[0]}-{orders[-1]}, slices {min(elems)}-{max(elems)} "
@@ -102,7 +103,7 @@ def batched_section(torch, n_streams, rounds, warmup, compute, tune):
     side = torch.cuda.Stream()
     out = {}
     with torch.cuda.stream(side):
-        frames = [[torch.from_numpy(np.ascontiguousarray(X.reshape(-1, order="F"))).cuda() for X in sp.frames(1, 2)]
+        frames = [[torch.from_numpy(np.ascontiguousarray(X.reshape(-1, order="F"))).cuda() for X in sp.frames(1, nfr)]
                   for sp in specs]
         if compute == "bf16":
             frames = [[x.to(torch.bfloat16) for x in f] for f in frames]
@@ -122,9 +123,9 @@ def batched_section(torch, n_streams, rounds, warmup, compute, tune):
             def one(i):
                 if solo:
                     for st, f in zip(streams, frames):
-                        st.push(f[i % 2])
+                        st.push(f[i % nfr])
                 else:
-                    b.push([f[i % 2] for f in frames])
+                    b.push([f[i % nfr] for f in frames])
 
             def sync():
                 if solo:
@@ -160,9 +161,15 @@ def batched_section(torch, n_streams, rounds, warmup, compute, tune):
         log(f"batched (eager launches): {e_rate:.0f} updates/s")
         s_rate, s_ms, s_lat = run(False, True)
         log(f"single-stream path, streams one after another: {s_rate:.0f} updates/s")
+    frame_bytes = sum(f[0].numel() * f[0].element_size() for f in frames) * nfr
     out = {
-        "workload": f"c4_{n_streams}_streams_order3-5_modes16-256_ranks4-32_max2M",
+        "workload": f"c4_narrowed_{n_streams}_streams_order3-5_modes16-256_ranks4-32_slices_le_2M_entries",
+        "narrowed": "shapes whose slice exceeds 2^21 entries are drawn again; the literal distribution (modes "
+                    "uniform in [16, 256] at order 5) has slices of up to 4.3e9 entries (17 GB in FP32), which "
+                    "64 resident streams cannot hold",
         "streams": n_streams,
+        "frames_per_stream": nfr,
+        "frame_set_bytes": frame_bytes,
         "rounds": rounds,
         "updates_per_s": g_rate,
         "ms_per_round": g_ms,

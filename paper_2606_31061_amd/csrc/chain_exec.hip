@@ -1411,8 +1411,83 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
   return true;
 }
 
+// Thin QR of a matrix whose proper reflectors are capped at one (rho = 1,
+// e.g. the last core's local solution, which is always rank one), R not
+// wanted: the Householder factorisation with the identity-reflector rule
+// builds exactly one proper reflector H = I - t v v^T, at the first column j0
+// whose norm from the diagonal down exceeds tol ||M||_F (identity reflectors
+// before it change no other column), so Q = H [I; 0] in closed form:
+// Q(:, j) = e_j for j < j0 and e_j - t v v_j for j >= j0, column j0 negated
+// when R(j0, j0) = beta < 0.  One pass over M for the column norms, v staged
+// in LDS (M may alias Q), one pass writing Q.  m <= kRank1Rows.
+constexpr int kRank1Rows = 16384;
+__device__ __forceinline__ void rank1_qr(const Qr& q) {
+  const int tid = tix(), lane = tid & 63, wid = tid >> 6;
+  const int m = q.m, n = q.n;
+  double* cf = s_lds + kLdsTau;  // full column norms^2
+  double* cr = s_lds + kLdsSgn;  // norms^2 from the diagonal down
+  double* v = s_lds + kLdsMs;    // the reflector (m values)
+  double* sc = s_lds + kLdsRed;  // [0] t, [1] sign of column j0, [2] j0 (as double)
+  for (int j = wid; j < n; j += kCW) {
+    double pf = 0.0, pr = 0.0;
+    for (int i = lane; i < m; i += 64) {
+      const double x = q.M[i * q.mrs + (int64_t)j * q.mcs];
+      pf = fma(x, x, pf);
+      if (i >= j) pr = fma(x, x, pr);
+    }
+    pf = wave_sum(pf);
+    pr = wave_sum(pr);
+    if (lane == 0) {
+      cf[j] = pf;
+      cr[j] = pr;
+    }
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double fro2 = 0.0;
+    for (int j = 0; j < n; ++j) fro2 += cf[j];
+    const double thr = q.tol * sqrt(fro2);
+    int j0 = n;
+    for (int j = 0; j < n && j0 == n; ++j)
+      if (sqrt(cr[j]) > thr) j0 = j;
+    double t = 0.0, flip = 1.0, scal = 0.0;
+    if (j0 < n) {
+      const double alpha = q.M[j0 * q.mrs + (int64_t)j0 * q.mcs];
+      const double nrm = sqrt(cr[j0]);
+      const double beta = alpha >= 0.0 ? -nrm : nrm;
+      scal = 1.0 / (alpha - beta);
+      t = (beta - alpha) / beta;
+      flip = beta < 0.0 ? -1.0 : 1.0;
+    }
+    sc[0] = t;
+    sc[1] = flip;
+    sc[2] = (double)j0;
+    sc[3] = scal;
+  }
+  __syncthreads();
+  const double t = sc[0], flip = sc[1], scal = sc[3];
+  const int j0 = (int)sc[2];
+  if (j0 < n)
+    for (int i = tid; i < m; i += kCT)
+      v[i] = (i < j0) ? 0.0 : (i == j0 ? 1.0 : q.M[i * q.mrs + (int64_t)j0 * q.mcs] * scal);
+  __syncthreads();
+  for_each_ij(m, n, [&](int i, int j) {
+    double val = (i == j) ? 1.0 : 0.0;
+    if (j >= j0 && j0 < n) {
+      val -= t * v[i] * v[j];
+      if (j == j0) val *= flip;
+    }
+    q.Q[i * q.qrs + j * q.qcs] = val;
+  });
+  __syncthreads();
+}
+
 __device__ __forceinline__ void wg_qr(const Qr& q) {
   const int m = q.m, n = q.n;
+  if (q.rho == 1 && !q.R && m <= kRank1Rows) {
+    rank1_qr(q);
+    return;
+  }
   if (q.rho >= n && m <= kQrRows && n <= 32 && cholqr2_reg(q)) return;
   if (q.rho >= n && m > kQrRows && n <= 32 && q.aux && cholqr2_tall(q)) return;
   if (m <= kQrRows && n <= 32) {
