@@ -156,6 +156,17 @@ tt_status tt_stream_reconstruct(tt_stream* s, void* out, tt_dtype dtype, int on_
  * INVALID_ARG. */
 tt_status tt_stream_destroy(tt_stream* s);
 
+/* Wait until the last pushed update has committed its result (Algorithm 1's
+ * time-t output: the cores, g_n[t] and so M_t).  An update ends by preparing
+ * the next one (the right-orthogonalisation of Section 3.4.1 and the right
+ * interfaces, which read only the committed state); that work may still run
+ * when this returns, and a following push waits for it on the handle's
+ * stream.  This is the latency a slice sees when slices arrive with gaps.
+ * It reports no rejected slice (tt_stream_synchronize does).  For a stream
+ * registered with a server it waits for the stream's lane work.
+ * Errors: INVALID_ARG, DEVICE. */
+tt_status tt_stream_wait_update(tt_stream* s);
+
 /* Wait for all work of the handle.  Returns NONFINITE if any update since the
  * previous call discarded a non-finite slice, else OK (or DEVICE). */
 tt_status tt_stream_synchronize(tt_stream* s);
@@ -191,8 +202,10 @@ tt_status tt_stream_get_history(tt_stream* s, double* out, int64_t rows, int64_t
  * Errors: INVALID_ARG (null), SHAPE (m < 1 or sizes < 1). */
 tt_status tt_clamp_ranks(int32_t m, const int64_t* modes, const int64_t* ranks_in, int64_t* ranks_out);
 
-/* Device time of the last completed push in milliseconds (HIP events around
- * the update on the handle's stream).  Waits for the handle's work. */
+/* Device time of the last completed push in milliseconds, from the push to
+ * the commit of its result (HIP events on the handle's stream; the
+ * preparation of the next update that follows the commit is not included).
+ * Waits for that update. */
 tt_status tt_stream_last_push_ms(tt_stream* s, float* ms);
 
 /* Per-operation device times of the last push, for a stream created with

@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH):
         "tt_stream_reconstruct": (c_int, [sv, sv, c_int, c_int]),
         "tt_stream_destroy": (c_int, [sv]),
         "tt_stream_synchronize": (c_int, [sv]),
+        "tt_stream_wait_update": (c_int, [sv]),
         "tt_stream_time": (c_int, [sv, POINTER(c_int64)]),
         "tt_stream_info": (c_int, [sv, POINTER(c_int64), POINTER(c_int64), POINTER(c_int32), POINTER(c_int64)]),
         "tt_stream_get_state": (c_int, [sv, POINTER(c_double), POINTER(c_double), POINTER(c_int64)]),
@@ -294,6 +295,11 @@ class TTStream:
 
     def synchronize(self) -> None:
         _check(tt_stream_synchronize(self._h), "tt_stream_synchronize")
+
+    def wait_update(self) -> None:
+        """Wait until the last pushed update has committed (the next update's
+        preparation may still run)."""
+        _check(self._lib.tt_stream_wait_update(self._h), "tt_stream_wait_update")
 
     def synchronize_status(self) -> int:
         return tt_stream_synchronize(self._h)

@@ -116,10 +116,14 @@ void wave_build(Wave& w) {
     for (auto& x : mp) x.segs.push_back({0, 0});
     for (const Step& st : P.steps) {
       if (st.kind == kStepChain) {
-        mp[ph].segs.back() = {st.first, st.count};
+        auto& sg = mp[ph].segs.back();
+        if (sg.second > 0 && sg.first + sg.second == st.first) sg.second += st.count;  // split only by a mark
+        else sg = {st.first, st.count};
       } else if (st.kind == kStepWide) {
         mp[ph].wides.push_back(st.first);
         mp[ph].segs.push_back({0, 0});
+      } else if (st.kind == kStepMark) {
+        // the commit mark: no work, and no boundary for a wave
       } else {
         ++ph;
       }

@@ -17,7 +17,9 @@ constexpr uint64_t kStreamMagic = 0x54545354524d3031ULL;  // "TTSTRM01"
 // The update as a sequence of steps over its operation list: chain segments
 // (operations first .. first + count - 1 on one workgroup), whole-GPU
 // products (operation first) and the two slice passes.
-enum StepKind { kStepChain = 0, kStepWide = 1, kStepPass1 = 2, kStepPass2 = 3 };
+// kStepMark: no work; the single-stream path records the commit event there
+// (the update's result is final; later steps prepare the next update).
+enum StepKind { kStepChain = 0, kStepWide = 1, kStepPass1 = 2, kStepPass2 = 3, kStepMark = 4 };
 struct Step {
   int kind;
   int first;
@@ -56,7 +58,8 @@ struct tt_stream {
 
   double* state[2] = {nullptr, nullptr};
   int cur = 0;               // state[cur] is the committed state
-  ttk::UpdatePlan plan[2];        // plan[p] reads state[p], writes state[p ^ 1]
+  ttk::UpdatePlan plan[2];        // plan[p] reads state[p], writes state[p ^ 1], then prepares the next update
+  ttk::UpdatePlan sweep0[2];      // sweep0[p]: the preparation alone, from state[p] (creation, set_state)
   double* work = nullptr;
   double* Rbuf = nullptr;
   int64_t* trace = nullptr;  // 2 stamps per chain op (TT_FLAG_PROFILE_OPS)
@@ -101,6 +104,7 @@ struct tt_stream {
   int32_t server_id = -1;
   hipEvent_t ext_done = nullptr;
   hipEvent_t ev0 = nullptr, ev1 = nullptr, evcopy = nullptr;
+  hipEvent_t evcommit = nullptr;  // recorded when the last pushed update has committed
   // TT_FLAG_PROFILE_OPS: per pass, before it, after its contraction kernel,
   // after its reduction (pass 1: 0, 1, 2; pass 2: 3, 4, 5)
   hipEvent_t evpass[6] = {};

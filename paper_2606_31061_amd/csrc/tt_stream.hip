@@ -41,6 +41,7 @@ using ttk::kStepChain;
 using ttk::kStepWide;
 using ttk::kStepPass1;
 using ttk::kStepPass2;
+using ttk::kStepMark;
 
 namespace {
 
@@ -168,6 +169,7 @@ void release(tt_stream* s) {
   if (s->ev0) (void)hipEventDestroy(s->ev0);
   if (s->ev1) (void)hipEventDestroy(s->ev1);
   if (s->evcopy) (void)hipEventDestroy(s->evcopy);
+  if (s->evcommit) (void)hipEventDestroy(s->evcommit);
   for (hipEvent_t& e : s->evpass)
     if (e) (void)hipEventDestroy(e);
 }
@@ -455,21 +457,16 @@ void build_plan_noortho(tt_stream* s, int par) {
   }
 }
 
-// The update that reads state[par] and writes state[par ^ 1].
-void build_plan(tt_stream* s, int par) {
-  UpdatePlan& P = s->plan[par];
-  P.ops.clear();
-  P.steps.clear();
-  double* master = s->state[par];
-  double* fresh = s->state[par ^ 1];
+// The right-orthogonalisation of the state `master` (Algorithm 1, step 1:
+// normalise g, LQ sweep k = m..2) into the work state, then the right
+// interfaces B_k, k = m-1..k* (step 2), B_{k*} also in FP32 for pass 1.
+// The committed state is only read.
+void plan_sweep(tt_stream* s, UpdatePlan& P, double* master) {
   double* work = s->work;
   const int m = s->m, ks = s->kstar;
   const auto& I = s->I;
   const auto& r = s->r;
-  const auto& Pk = s->Pk;
   const auto& Jk = s->Jk;
-
-  // right-orthogonalisation: normalise g into the work state, then the LQ sweep
   {
     ttk::ChainOp op;
     op.type = ttk::kOpNormG;
@@ -507,6 +504,27 @@ void build_plan(tt_stream* s, int par) {
   } else {
     plan_copy(P, s->g_of(work), nullptr, s->B32, r[m]);
   }
+}
+
+// The update that reads state[par] and writes state[par ^ 1].  Its steps 1-2
+// (the right-orthogonalisation and the right interfaces) read only the
+// committed state, so they are planned at the end of the previous update,
+// right after its commit (plan_sweep of the state just committed; the first
+// update's is run at creation and after set_state): an update starts with
+// pass 1, and its commit is not delayed by the next update's sweep.
+void build_plan(tt_stream* s, int par) {
+  UpdatePlan& P = s->plan[par];
+  P.ops.clear();
+  P.steps.clear();
+  double* master = s->state[par];
+  double* fresh = s->state[par ^ 1];
+  double* work = s->work;
+  const int m = s->m, ks = s->kstar;
+  const auto& I = s->I;
+  const auto& r = s->r;
+  const auto& Pk = s->Pk;
+  const auto& Jk = s->Jk;
+  auto Bk = [&](int k) -> double* { return k == m ? s->g_of(work) : s->B[k]; };
 
   P.steps.push_back({kStepPass1, 0, 0});
 
@@ -572,13 +590,26 @@ void build_plan(tt_stream* s, int par) {
     op.hist_cap = s->hist_cap;
     plan_chain(P, op);
   }
+  // the update's result is committed here (an event marks it); then the next
+  // update's steps 1-2 from the committed state (a rejected slice restored it)
+  P.steps.push_back({kStepMark, 0, 0});
+  plan_sweep(s, P, fresh);
+}
+
+// Steps 1-2 alone for the state in state[par]: run once before the first
+// update and after tt_stream_set_state.
+void build_sweep_plan(tt_stream* s, int par) {
+  UpdatePlan& P = s->sweep0[par];
+  P.ops.clear();
+  P.steps.clear();
+  plan_sweep(s, P, s->state[par]);
 }
 
 // Runs the steps of plan P of stream s with slice X.  trace (if not null)
 // receives two stamps per chain operation; pass_ev (if not null) three events
 // per pass: before it, after its contraction kernel, after its reduction.
 tt_status run_steps(hipStream_t st, const tt_stream* s, const UpdatePlan& P, const void* X, tt_dtype xdt,
-                    int64_t* trace, hipEvent_t const* pass_ev = nullptr) {
+                    int64_t* trace, hipEvent_t const* pass_ev = nullptr, hipEvent_t mark_ev = nullptr) {
   const int ks = s->kstar;
   for (size_t si = 0; si < P.steps.size(); ++si) {
     const Step& step = P.steps[si];
@@ -617,6 +648,9 @@ tt_status run_steps(hipStream_t st, const tt_stream* s, const UpdatePlan& P, con
         if (pass_ev) TT_HIP(hipEventRecord(pass_ev[5], st));
         break;
       }
+      case kStepMark:
+        if (mark_ev) TT_HIP(hipEventRecord(mark_ev, st));
+        break;
       default:
         return fail(TT_ERR_DEVICE, "corrupt update plan");
     }
@@ -625,7 +659,15 @@ tt_status run_steps(hipStream_t st, const tt_stream* s, const UpdatePlan& P, con
 }
 
 tt_status run_plan(tt_stream* s, const void* X, tt_dtype xdt) {
-  return run_steps(s->stream, s, s->plan[s->cur], X, xdt, s->trace, s->evpass[0] ? s->evpass : nullptr);
+  return run_steps(s->stream, s, s->plan[s->cur], X, xdt, s->trace, s->evpass[0] ? s->evpass : nullptr,
+                   s->evcommit);
+}
+
+// Steps 1-2 of the first update from the committed state (after creation or
+// set_state); stream-ordered.  Nothing to prepare for the ablation's plan.
+tt_status run_first_sweep(tt_stream* s) {
+  if (s->flags & TT_FLAG_NO_ORTHO) return TT_OK;
+  return run_steps(s->stream, s, s->sweep0[s->cur], nullptr, TT_F32, nullptr);
 }
 
 }  // namespace
@@ -808,6 +850,7 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
   TT_HIP_BAIL(hipEventCreate(&s->ev0));
   TT_HIP_BAIL(hipEventCreate(&s->ev1));
   TT_HIP_BAIL(hipEventCreateWithFlags(&s->evcopy, hipEventDisableTiming));
+  TT_HIP_BAIL(hipEventCreate(&s->evcommit));
 
   std::vector<double> init(s->state_len);
   if (cfg->init_cores) std::memcpy(init.data(), cfg->init_cores, sizeof(double) * s->state_len);
@@ -817,10 +860,14 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
   TT_HIP_BAIL(hipMemcpyAsync(s->state[0], init.data(), sizeof(double) * s->state_len, hipMemcpyHostToDevice,
                              s->stream));
   s->cur = 0;
-  for (int par = 0; par < 2; ++par) {
-    if (s->flags & TT_FLAG_NO_ORTHO) build_plan_noortho(s, par);
+  for (int q = 0; q < 4; ++q) {
+    const int par = q & 1;
+    const bool sweep = q >= 2;
+    if (sweep && (s->flags & TT_FLAG_NO_ORTHO)) continue;
+    if (sweep) build_sweep_plan(s, par);
+    else if (s->flags & TT_FLAG_NO_ORTHO) build_plan_noortho(s, par);
     else build_plan(s, par);
-    UpdatePlan& P = s->plan[par];
+    UpdatePlan& P = sweep ? s->sweep0[par] : s->plan[par];
     for (const ttk::ChainOp& op : P.ops)
       if (!ttk::chain_op_supported(op)) return bail(TT_ERR_UNSUPPORTED, "a core re-orthogonalisation exceeds 256 columns");
     // one device block: ops, then a segment per step, then a pointer per op
@@ -851,6 +898,10 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
     (void)hipDeviceGetAttribute(&s->wall_khz, hipDeviceAttributeWallClockRate, s->device);
     if (s->wall_khz <= 0) s->wall_khz = 100000;
     for (hipEvent_t& e : s->evpass) TT_HIP_BAIL(hipEventCreate(&e));
+  }
+  {
+    const tt_status st0 = run_first_sweep(s);
+    if (st0 != TT_OK) return bail(st0, g_last_error);
   }
   TT_HIP_BAIL(hipStreamSynchronize(s->stream));
 #undef TT_HIP_BAIL
@@ -887,6 +938,17 @@ tt_status tt_stream_push_slice(tt_stream* s, const void* slice, tt_dtype dtype, 
   s->pushes++;
   if (!on_device) TT_HIP(hipEventSynchronize(s->evcopy));
   if (s->flags & TT_FLAG_SYNC_PUSH) return tt_stream_synchronize(s);
+  return TT_OK;
+}
+
+tt_status tt_stream_wait_update(tt_stream* s) {
+  if (!valid(s)) return fail(TT_ERR_INVALID_ARG, "invalid handle");
+  if (s->server) {  // a lane runs its updates
+    TT_HIP(ttk::stream_quiesce(s));
+    return TT_OK;
+  }
+  if (s->pushes == 0) return TT_OK;
+  TT_HIP(hipEventSynchronize((s->flags & TT_FLAG_NO_ORTHO) ? s->ev1 : s->evcommit));
   return TT_OK;
 }
 
@@ -940,6 +1002,10 @@ tt_status tt_stream_set_state(tt_stream* s, const double* cores, const double* g
   TT_HIP(hipMemcpy(s->g_of(s->master()), g, sizeof(double) * s->r[s->m], hipMemcpyHostToDevice));
   TT_HIP(hipMemcpy(s->tdev, &t, sizeof(int64_t), hipMemcpyHostToDevice));
   s->hist_t0 = t;  // the ring holds no row of the new state's past
+  // the next update's steps 1-2 were prepared from the replaced state
+  const tt_status st = run_first_sweep(s);
+  if (st != TT_OK) return st;
+  TT_HIP(hipStreamSynchronize(s->stream));
   return TT_OK;
 }
 
@@ -1008,8 +1074,9 @@ tt_status tt_stream_reconstruct(tt_stream* s, void* out, tt_dtype dtype, int on_
 tt_status tt_stream_last_push_ms(tt_stream* s, float* ms) {
   if (!valid(s) || !ms) return fail(TT_ERR_INVALID_ARG, "invalid handle or null output");
   if (!s->timed) return fail(TT_ERR_STATE, "no push yet");
-  TT_HIP(hipEventSynchronize(s->ev1));
-  TT_HIP(hipEventElapsedTime(ms, s->ev0, s->ev1));
+  hipEvent_t end = (s->flags & TT_FLAG_NO_ORTHO) ? s->ev1 : s->evcommit;
+  TT_HIP(hipEventSynchronize(end));
+  TT_HIP(hipEventElapsedTime(ms, s->ev0, end));
   return TT_OK;
 }
 

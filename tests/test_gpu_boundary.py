@@ -192,3 +192,26 @@ def test_server_registered_stream_rules():
     assert np.array_equal(served[2].get_state()[1], solo[2].get_state()[1])
     for s in served[::2] + solo:
         s.close()
+
+
+def test_wait_update_returns_the_committed_result():
+    """tt_stream_wait_update: after it returns, the pushed update's result is
+    committed (the next update's preparation may still run); the push to commit
+    device time is reported and does not exceed push to all work."""
+    torch = torch_cuda()
+    from paper_2606_31061_amd import TTStream
+    st = config_c1(T=6)
+    init = st.init()
+    xs = list(st.frames(1, st.T))
+    say("wait_update on c1")
+    ref = ttals.run_stream(xs, init[0], init[1], keep_M=True)
+    s = TTStream(st.modes, st.ranks, init=init)
+    s.wait_update()                     # nothing pushed yet: returns at once
+    for X, info in zip(xs, ref.infos):
+        s.push(to_device_slice(torch, X))
+        s.wait_update()
+        assert s.last_push_ms() > 0.0
+        M = s.reconstruct()
+        assert np.linalg.norm(M - info.M) <= 1e-5 * np.linalg.norm(X)
+    assert s.time() == len(xs)
+    s.close()
