@@ -22,16 +22,21 @@ using Key = std::tuple<int64_t, int64_t, int, int>;
 std::mutex g_mu;
 std::map<Key, PassPlans> g_cache;
 
-// Block counts that fill the chip about half, once, twice and four times.
+// Chunk counts whose tiles x chunks blocks fill the chip about half, once,
+// twice and four times: for each, the largest count that stays within that
+// many blocks (no CU gets one block more than the others) and the smallest
+// that reaches it.
 std::vector<int> fill_counts(int tiles, int cus, int64_t max_chunks) {
   std::vector<int> out;
   for (int f : {1, 2, 4, 8}) {
-    int64_t c = ((int64_t)cus * f / 2 + tiles - 1) / tiles;
-    if (c > max_chunks) c = max_chunks;
-    if (c < 1) c = 1;
-    bool seen = false;
-    for (int v : out) seen = seen || v == (int)c;
-    if (!seen) out.push_back((int)c);
+    const int64_t target = (int64_t)cus * f / 2;
+    for (int64_t c : {target / tiles, (target + tiles - 1) / tiles}) {
+      if (c > max_chunks) c = max_chunks;
+      if (c < 1) c = 1;
+      bool seen = false;
+      for (int v : out) seen = seen || v == (int)c;
+      if (!seen) out.push_back((int)c);
+    }
   }
   return out;
 }
