@@ -1482,12 +1482,57 @@ __device__ __forceinline__ void rank1_qr(const Qr& q) {
   __syncthreads();
 }
 
+// Thin QR of a tall matrix (m > kQrRows, n <= 32) whose proper reflectors are
+// capped at 2 <= rho < n (a local solution of rank at most rho), R not
+// wanted, M not Q.  Householder would build rho proper reflectors, each a
+// pass over the matrix streamed through one CU; instead Q's first rho columns
+// come from CholeskyQR2 of M's first rho columns (the same columns, up to
+// rounding, as Householder's when those columns are independent) and the
+// other n - rho columns are an orthonormal completion: e_j - Q_rho Q_rho(j,:)^T
+// for j = rho..n-1, orthonormalised by CholeskyQR2.  A completion is what
+// Householder's identity reflectors provide too (any one gives the same
+// update).  Returns false when a Cholesky pivot fails (the leading columns
+// are not independent): the Householder path then decides, from M.
+__device__ __forceinline__ bool capped_tall_qr(const Qr& q) {
+  const int m = q.m, n = q.n, rho = q.rho;
+  Qr a = q;
+  a.n = rho;
+  a.R = nullptr;
+  if (!cholqr2_tall(a)) return false;
+  // W = Q_rho(rho..n-1, :) (small) through LDS, then C = E - Q_rho W^T
+  const int nc = n - rho;
+  double* W = s_lds + kLdsW;  // nc x rho, leading dimension 32
+  for (int e = tix(); e < nc * rho; e += kCT) {
+    const int jc = e % nc, k = e / nc;
+    W[jc + 32 * k] = q.Q[(rho + jc) * q.qrs + k * q.qcs];
+  }
+  __syncthreads();
+  double* C = q.Q + (int64_t)rho * q.qcs;
+  for_each_ij(m, nc, [&](int i, int jc) {
+    double v = (i == rho + jc) ? 1.0 : 0.0;
+    for (int k = 0; k < rho; ++k) v = fma(-q.Q[i * q.qrs + k * q.qcs], W[jc + 32 * k], v);
+    C[i * q.qrs + jc * q.qcs] = v;
+  });
+  __syncthreads();
+  Qr b = q;
+  b.n = nc;
+  b.rho = nc;
+  b.M = C;
+  b.mrs = q.qrs;
+  b.mcs = q.qcs;
+  b.Q = C;
+  b.R = nullptr;
+  return cholqr2_tall(b);
+}
+
 __device__ __forceinline__ void wg_qr(const Qr& q) {
   const int m = q.m, n = q.n;
   if (q.rho == 1 && !q.R && m <= kRank1Rows) {
     rank1_qr(q);
     return;
   }
+  if (q.rho >= 2 && q.rho < n && m > kQrRows && n <= 32 && q.aux && !q.R && q.M != q.Q && capped_tall_qr(q))
+    return;
   if (q.rho >= n && m <= kQrRows && n <= 32 && cholqr2_reg(q)) return;
   if (q.rho >= n && m > kQrRows && n <= 32 && q.aux && cholqr2_tall(q)) return;
   if (m <= kQrRows && n <= 32) {

@@ -149,6 +149,7 @@ SHAPES = [
     ((7, 6), (5, 1)),
     ((9,), (4,)),
     ((64, 2, 33), (40, 33, 33)),
+    ((40, 20, 3), (32, 9, 3)),        # a tail core of 640 x 9 with rank <= 3 (tall, capped QR)
 ]
 
 
