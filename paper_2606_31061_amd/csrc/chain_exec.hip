@@ -1482,24 +1482,167 @@ __device__ __forceinline__ void rank1_qr(const Qr& q) {
   __syncthreads();
 }
 
-// Thin QR of a tall matrix (m > kQrRows, n <= 32) whose proper reflectors are
-// capped at 2 <= rho < n (a local solution of rank at most rho), R not
-// wanted, M not Q.  Householder would build rho proper reflectors, each a
-// pass over the matrix streamed through one CU; instead Q's first rho columns
-// come from CholeskyQR2 of M's first rho columns (the same columns, up to
-// rounding, as Householder's when those columns are independent) and the
-// other n - rho columns are an orthonormal completion: e_j - Q_rho Q_rho(j,:)^T
-// for j = rho..n-1, orthonormalised by CholeskyQR2.  A completion is what
-// Householder's identity reflectors provide too (any one gives the same
-// update).  Returns false when a Cholesky pivot fails (the leading columns
-// are not independent): the Householder path then decides, from M.
-__device__ __forceinline__ bool capped_tall_qr(const Qr& q) {
+// Workgroup sums of K values per thread (fixed order: reproducible); every
+// thread gets the K totals in out[].  Uses red[0 .. 16 K).
+template <int K>
+__device__ __forceinline__ void block_sums(double (&v)[K], double* red, double (&out)[K]) {
+  const int lane = tix() & 63, wid = tix() >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < K; ++k) red[wid * K + k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kCW; ++w) t += red[w * K + k];
+    out[k] = t;
+  }
+}
+
+// Thin QR with the proper reflectors capped at 2 <= rho <= 4 (a local
+// solution of rank at most rho), R not wanted: Householder builds its rho
+// proper reflectors from the first rho columns alone (when none of them
+// takes an identity reflector), and the other columns only receive identity
+// reflectors, so Q = H_1 .. H_rho [I; 0] = E - V T V_top^T (compact WY form:
+// V the m x rho reflectors, unit diagonal, T upper triangular, V_top the
+// first n rows of V), column j negated where R(j, j) = beta_j < 0.  The
+// m x rho panel is factored in LDS; Q is written in one pass.  Returns false,
+// with nothing written, when one of the first rho columns would take an
+// identity reflector (the general path then decides).  m rho <= kMsDoubles.
+constexpr int kMsDoubles = 16448;
+constexpr int kSmallRho = 4;
+__device__ __forceinline__ bool small_capped_qr(const Qr& q) {
+  const int tid = tix();
   const int m = q.m, n = q.n, rho = q.rho;
-  Qr a = q;
-  a.n = rho;
-  a.R = nullptr;
-  if (!cholqr2_tall(a)) return false;
-  // W = Q_rho(rho..n-1, :) (small) through LDS, then C = E - Q_rho W^T
+  double* Pn = s_lds + kLdsMs;        // the panel, column-major, leading dimension m
+  double* red = s_lds + kLdsRow;      // block sums (up to 16 values)
+  double* U = s_lds + kLdsW;          // U = T V_top^T, rho x n (leading dimension kSmallRho)
+  double* sc = s_lds + kLdsTau;       // tau[4], beta[4], T (4 x 4, column-major)
+  // panel into LDS and ||M||_F^2
+  double p = 0.0;
+  for_each_ij(m, n, [&](int i, int j) {
+    const double x = q.M[i * q.mrs + j * q.mcs];
+    p = fma(x, x, p);
+    if (j < rho) Pn[i + m * j] = x;
+  });
+  double fro2;
+  {
+    double a[1] = {p}, o[1];
+    block_sums<1>(a, red, o);
+    fro2 = o[0];
+  }
+  const double thr = q.tol * sqrt(fro2);
+  for (int j = 0; j < rho; ++j) {
+    double* cj = Pn + m * j;
+    double a[1] = {0.0}, o[1];
+    for (int i = j + tid; i < m; i += kCT) a[0] = fma(cj[i], cj[i], a[0]);
+    block_sums<1>(a, red, o);
+    const double nrm = sqrt(o[0]);
+    if (!(nrm > thr)) return false;  // uniform: every thread saw the same sum
+    const double alpha = cj[j];
+    const double beta = alpha >= 0.0 ? -nrm : nrm;
+    const double scal = 1.0 / (alpha - beta);
+    const double t = (beta - alpha) / beta;
+    __syncthreads();                  // cj[j] read by every thread before it is replaced
+    for (int i = j + 1 + tid; i < m; i += kCT) cj[i] *= scal;
+    if (tid == 0) {
+      cj[j] = 1.0;                    // the reflector's unit leading entry
+      sc[j] = t;
+      sc[kSmallRho + j] = beta;
+    }
+    __syncthreads();
+    // H_j on the panel's later columns: c -= t v (v^T c), rows j..m-1
+    if (j + 1 < rho) {
+      double w[kSmallRho - 1], wo[kSmallRho - 1];
+#pragma unroll
+      for (int c = 0; c < kSmallRho - 1; ++c) w[c] = 0.0;
+      for (int i = j + tid; i < m; i += kCT) {
+        const double vi = cj[i];
+#pragma unroll
+        for (int c = 0; c < kSmallRho - 1; ++c)
+          if (j + 1 + c < rho) w[c] = fma(vi, Pn[i + m * (j + 1 + c)], w[c]);
+      }
+      block_sums<kSmallRho - 1>(w, red, wo);
+      for (int i = j + tid; i < m; i += kCT) {
+        const double vi = cj[i];
+#pragma unroll
+        for (int c = 0; c < kSmallRho - 1; ++c)
+          if (j + 1 + c < rho) Pn[i + m * (j + 1 + c)] = fma(-t * wo[c], vi, Pn[i + m * (j + 1 + c)]);
+      }
+      __syncthreads();
+    }
+  }
+  // T of the compact WY form: T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) V(:, 0:j)^T v_j;
+  // the pair products V(:, a)^T V(:, b), a < b, in the order (0,1), (0,2), (1,2), (0,3), ...
+  {
+    constexpr int NP = kSmallRho * (kSmallRho - 1) / 2;
+    double g[NP], go[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) g[k] = 0.0;
+    for (int i = tid; i < m; i += kCT) {
+      int k = 0;
+#pragma unroll
+      for (int b = 1; b < kSmallRho; ++b)
+#pragma unroll
+        for (int a = 0; a < b; ++a) {
+          if (b < rho) {
+            const double va = i < a ? 0.0 : Pn[i + m * a];
+            const double vb = i < b ? 0.0 : Pn[i + m * b];
+            g[k] = fma(va, vb, g[k]);
+          }
+          ++k;
+        }
+    }
+    block_sums<NP>(g, red, go);
+    if (tid == 0) {
+      double* T = sc + 2 * kSmallRho;
+      for (int e = 0; e < kSmallRho * kSmallRho; ++e) T[e] = 0.0;
+      int k = 0;
+      for (int b = 0; b < rho; ++b) {
+        T[b + kSmallRho * b] = sc[b];
+        for (int a = 0; a < b; ++a) {
+          double acc = 0.0;
+          for (int c = a; c < b; ++c) acc += T[a + kSmallRho * c] * go[k + c];
+          T[a + kSmallRho * b] = -sc[b] * acc;
+        }
+        k += b;
+      }
+    }
+    __syncthreads();
+  }
+  // U = T V_top^T (rho x n); V_top(c, b) = 0 for c < b, 1 for c == b
+  for (int e = tid; e < rho * n; e += kCT) {
+    const int a = e % rho, c = e / rho;
+    const double* T = sc + 2 * kSmallRho;
+    double acc = 0.0;
+    for (int b = a; b < rho; ++b) {
+      const double vcb = c < b ? 0.0 : (c == b ? 1.0 : Pn[c + m * b]);
+      acc = fma(T[a + kSmallRho * b], vcb, acc);
+    }
+    U[a + kSmallRho * c] = acc;
+  }
+  __syncthreads();
+  for_each_ij(m, n, [&](int i, int c) {
+    double val = (i == c) ? 1.0 : 0.0;
+    for (int a = 0; a < rho; ++a) {
+      const double via = i < a ? 0.0 : (i == a ? 1.0 : Pn[i + m * a]);
+      val = fma(-via, U[a + kSmallRho * c], val);
+    }
+    if (c < rho && sc[kSmallRho + c] < 0.0) val = -val;
+    q.Q[i * q.qrs + c * q.qcs] = val;
+  });
+  __syncthreads();
+  return true;
+}
+
+// The completion of a tall QR capped at rho < n (see wg_qr): W = Q_rho(rho..n-1, :)
+// through LDS, then C = E - Q_rho W^T into Q's columns rho..n-1.
+__device__ __forceinline__ void capped_completion(const Qr& q) {
+  const int m = q.m, n = q.n, rho = q.rho;
   const int nc = n - rho;
   double* W = s_lds + kLdsW;  // nc x rho, leading dimension 32
   for (int e = tix(); e < nc * rho; e += kCT) {
@@ -1514,15 +1657,6 @@ __device__ __forceinline__ bool capped_tall_qr(const Qr& q) {
     C[i * q.qrs + jc * q.qcs] = v;
   });
   __syncthreads();
-  Qr b = q;
-  b.n = nc;
-  b.rho = nc;
-  b.M = C;
-  b.mrs = q.qrs;
-  b.mcs = q.qcs;
-  b.Q = C;
-  b.R = nullptr;
-  return cholqr2_tall(b);
 }
 
 __device__ __forceinline__ void wg_qr(const Qr& q) {
@@ -1531,10 +1665,45 @@ __device__ __forceinline__ void wg_qr(const Qr& q) {
     rank1_qr(q);
     return;
   }
-  if (q.rho >= 2 && q.rho < n && m > kQrRows && n <= 32 && q.aux && !q.R && q.M != q.Q && capped_tall_qr(q))
-    return;
+  if (q.rho >= 2 && q.rho <= kSmallRho && q.rho < n && !q.R && q.M != q.Q && (int64_t)m * q.rho <= kMsDoubles && n <= 256) {
+    const bool done = small_capped_qr(q);
+    __syncthreads();
+    if (done) return;
+  }
   if (q.rho >= n && m <= kQrRows && n <= 32 && cholqr2_reg(q)) return;
-  if (q.rho >= n && m > kQrRows && n <= 32 && q.aux && cholqr2_tall(q)) return;
+  // Tall (m > kQrRows, n <= 32): streamed CholeskyQR2.  A QR capped at
+  // 2 <= rho < n proper reflectors (a local solution of rank at most rho, R not
+  // wanted, M not Q) would make Householder stream the matrix through one CU
+  // rho times; instead Q's first rho columns come from CholeskyQR2 of M's
+  // first rho columns (Householder's, up to rounding, when those columns are
+  // independent) and the other n - rho from orthonormalising the completion
+  // e_j - Q_rho Q_rho(j,:)^T, j = rho..n-1 (identity reflectors give a
+  // completion too; the update does not depend on which one).  A failed
+  // Cholesky pivot leaves the decision to Householder, from M.
+  if (m > kQrRows && n <= 32 && q.aux) {
+    const bool capped = q.rho >= 2 && q.rho < n && !q.R && q.M != q.Q;
+    if (q.rho >= n || capped) {
+      bool ok = true;
+      for (int pass = 0; pass < (capped ? 2 : 1) && ok; ++pass) {
+        Qr a = q;
+        if (capped && pass == 0) {
+          a.n = q.rho;
+          a.R = nullptr;
+        } else if (capped) {
+          capped_completion(q);
+          a.n = n - q.rho;
+          a.rho = a.n;
+          a.M = q.Q + (int64_t)q.rho * q.qcs;
+          a.mrs = q.qrs;
+          a.mcs = q.qcs;
+          a.Q = const_cast<double*>(a.M);
+          a.R = nullptr;
+        }
+        ok = cholqr2_tall(a);
+      }
+      if (ok) return;
+    }
+  }
   if (m <= kQrRows && n <= 32) {
     // Householder in LDS
     const int mp = round16(m);
