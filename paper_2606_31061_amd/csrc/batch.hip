@@ -120,8 +120,10 @@ void wave_build(Wave& w) {
         if (sg.second > 0 && sg.first + sg.second == st.first) sg.second += st.count;  // split only by a mark
         else sg = {st.first, st.count};
       } else if (st.kind == kStepWide) {
-        mp[ph].wides.push_back(st.first);
-        mp[ph].segs.push_back({0, 0});
+        for (int q = 0; q < st.count; ++q) {  // a joined launch of the stream: one slot per product
+          mp[ph].wides.push_back(st.first + q);
+          mp[ph].segs.push_back({0, 0});
+        }
       } else if (st.kind == kStepMark) {
         // the commit mark: no work, and no boundary for a wave
       } else {

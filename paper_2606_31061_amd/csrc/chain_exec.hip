@@ -490,6 +490,72 @@ __device__ __forceinline__ void stage_pair(StageWalk a, StageWalk b) {
   }
 }
 
+// Small products (at most kSmallWork multiply-adds per thread): no staging
+// and no matrix cores, whose set-up (index walks, LDS round trips, barriers)
+// costs several microseconds per operation, more than such a product's
+// arithmetic.  Output e = i + M j goes to thread e % (M N) of depth group
+// e / (M N): when M N leaves room, the depth is split into G groups (a power of
+// two, at most 16), each thread adds its group's terms in k order and the
+// groups are added in group order through LDS; otherwise each thread takes
+// outputs e, e + kCT, ... over the whole depth.  Consecutive threads walk i,
+// the contiguous index of column-major operands.
+constexpr int kSmallFma = 65536;
+constexpr int kSmallWork = 24;  // multiply-adds per thread
+static_assert(kCT == 1024, "small_gemm_fits divides by kCT with a shift");
+// log2 of the number of depth groups: at most 16 groups, two outputs' worth
+// of threads per group and output, two terms per group
+__device__ __forceinline__ int small_gemm_lg(int MN, int K) {
+  int lg = 0;
+  while (lg < 4 && (MN << (lg + 1)) <= kCT && (2 << lg) <= K) ++lg;
+  return lg;
+}
+__device__ __forceinline__ bool small_gemm_fits(int MN, int K) {
+  const int lg = small_gemm_lg(MN, K);
+  return ((MN + kCT - 1) >> 10) * ((K + (1 << lg) - 1) >> lg) <= kSmallWork;
+}
+__device__ __forceinline__ void small_gemm(const Gemm& g, int M, int N, int K) {
+  const int tid = tix();
+  const int MN = M * N;
+  const int lg = small_gemm_lg(MN, K), G = 1 << lg;
+  auto dot = [&](int e, int k0, int k1) {
+    int i;
+    const int j = small_div(e, M, i);
+    const double* a = g.A + i * (int)g.ars;
+    const double* b = g.B + j * (int)g.bcs;
+    const int as = (int)g.acs, bs = (int)g.brs;
+    double acc = 0.0;
+#pragma unroll 4
+    for (int k = k0; k < k1; ++k) acc = fma(a[k * as], b[k * bs], acc);
+    return acc;
+  };
+  auto store = [&](int e, double v) {
+    int i;
+    const int j = small_div(e, M, i);
+    const int o = i * (int)g.crs + j * (int)g.ccs;
+    if (g.C) g.C[o] = v;
+    if (g.C32) g.C32[o] = (float)v;
+  };
+  if (G == 1) {
+    for (int e = tid; e < MN; e += kCT) store(e, dot(e, 0, K));
+  } else {
+    double* part = s_lds + kLdsPart;  // G * MN <= kCT doubles
+    const int kper = (K + G - 1) >> lg;
+    int e;
+    const int grp = small_div(tid, MN, e);
+    if (grp < G) {
+      const int k0 = grp * kper, k1 = k0 + kper < K ? k0 + kper : K;
+      part[tid] = dot(e, k0, k1);
+    }
+    __syncthreads();
+    if (tid < MN) {
+      double v = 0.0;
+      for (int q = 0; q < G; ++q) v += part[q * MN + tid];
+      store(tid, v);
+    }
+  }
+  __syncthreads();
+}
+
 // C = A B from global operands.  The output is cut into tiles of at most
 // 64 blocks; for each tile the needed rows of A and columns of B go through
 // LDS one k-chunk at a time.
@@ -497,6 +563,10 @@ __device__ __forceinline__ void wg_gemm(const Gemm& g) {
   const int M = (int)g.M, N = (int)g.N, K = (int)g.K;
   if (M <= 0 || N <= 0) {
     __syncthreads();
+    return;
+  }
+  if ((int64_t)M * N * K <= kSmallFma && small_gemm_fits(M * N, K)) {
+    small_gemm(g, M, N, K);
     return;
   }
   const int w = tix() >> 6;
@@ -1826,6 +1896,16 @@ __global__ void __launch_bounds__(kCT) k_chain(const ChainSeg* __restrict__ segs
   const ChainSeg sg = ((ConstChainSeg*)(const void*)segs)[blockIdx.x];
   ConstChainOp* ops = (ConstChainOp*)(uint64_t)sg.ops;
   const int count = sg.count;
+  {
+    // One burst of vector loads, one per 64-byte line of the segment's
+    // descriptors, brings them into L2 together: each operation's scalar
+    // descriptor load then waits for an L2 hit, not a trip to memory.
+    const uint32_t* words = reinterpret_cast<const uint32_t*>(sg.ops);
+    const int nw = count * (int)(sizeof(ChainOp) / 4);
+    uint32_t acc = 0;
+    for (int e = 16 * (int)threadIdx.x; e < nw; e += 16 * kCT) acc ^= words[e];
+    asm volatile("" ::"v"(acc));
+  }
   for (int i = 0; i < count; ++i) {
     const ChainOp op = ops[i];
     if (trace && threadIdx.x == 0) trace[2 * i] = (int64_t)wall_clock64();

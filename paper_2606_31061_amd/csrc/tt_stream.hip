@@ -257,7 +257,41 @@ void plan_chain(UpdatePlan& p, const ttk::ChainOp& op) {
     p.steps.push_back({kStepChain, idx, 1});
 }
 
-// C = A B (see ttk::ChainOp); large products become launches of their own.
+// Byte range [lo, hi) an m x n operand with element strides rs, cs spans.
+struct Span {
+  uintptr_t lo = 0, hi = 0;
+};
+Span span_of(const void* p, int64_t m, int64_t n, int64_t rs, int64_t cs, size_t elem) {
+  Span r;
+  if (!p || m <= 0 || n <= 0) return r;
+  r.lo = reinterpret_cast<uintptr_t>(p);
+  r.hi = r.lo + (size_t)((m - 1) * rs + (n - 1) * cs + 1) * elem;
+  return r;
+}
+bool overlap(const Span& a, const Span& b) { return a.lo < b.hi && b.lo < a.hi; }
+
+// True if product y neither reads nor writes what product x writes, nor
+// writes what x reads: the two may run in one launch.
+bool independent(const ttk::ChainOp& x, const ttk::ChainOp& y) {
+  const Span xw[2] = {span_of(x.c, x.m, x.n, x.crs, x.ccs, 8), span_of(x.c32, x.m, x.n, x.crs, x.ccs, 4)};
+  const Span xr[2] = {span_of(x.a, x.m, x.k, x.ars, x.acs, 8), span_of(x.b, x.k, x.n, x.brs, x.bcs, 8)};
+  const Span yw[2] = {span_of(y.c, y.m, y.n, y.crs, y.ccs, 8), span_of(y.c32, y.m, y.n, y.crs, y.ccs, 4)};
+  const Span yr[2] = {span_of(y.a, y.m, y.k, y.ars, y.acs, 8), span_of(y.b, y.k, y.n, y.brs, y.bcs, 8)};
+  for (const Span& w : xw)
+    for (const Span& r : yr)
+      if (overlap(w, r)) return false;
+  for (const Span& w : yw) {
+    for (const Span& r : xr)
+      if (overlap(w, r)) return false;
+    for (const Span& v : xw)
+      if (overlap(w, v)) return false;
+  }
+  return true;
+}
+
+// C = A B (see ttk::ChainOp); large products become launches of their own,
+// and a large product independent of the large products planned right
+// before it joins their launch.
 void plan_gemm(UpdatePlan& p, int64_t M, int64_t N, int64_t K, const double* A, int64_t ars, int64_t acs,
                const double* B, int64_t brs, int64_t bcs, double* C, int64_t crs, int64_t ccs, float* C32) {
   ttk::ChainOp op;
@@ -278,7 +312,14 @@ void plan_gemm(UpdatePlan& p, int64_t M, int64_t N, int64_t K, const double* A, 
   const double fma = (double)M * (double)N * (double)K;
   if (fma >= kWideFma || (K >= kWideDepth && fma >= kWideDeepFma)) {
     p.ops.push_back(op);
-    p.steps.push_back({kStepWide, (int)p.ops.size() - 1, 1});
+    const int idx = (int)p.ops.size() - 1;
+    bool join = !p.steps.empty() && p.steps.back().kind == kStepWide &&
+                p.steps.back().first + p.steps.back().count == idx;
+    for (int q = join ? p.steps.back().first : idx; join && q < idx; ++q) join = independent(p.ops[q], op);
+    if (join)
+      p.steps.back().count++;
+    else
+      p.steps.push_back({kStepWide, idx, 1});
   } else {
     plan_chain(p, op);
   }
@@ -618,8 +659,12 @@ tt_status run_steps(hipStream_t st, const tt_stream* s, const UpdatePlan& P, con
         TT_HIP(ttk::chain_run(st, P.segs + si, 1, trace ? trace + 2 * step.first : nullptr));
         break;
       case kStepWide: {
-        const ttk::ChainOp& o = P.ops[step.first];
-        TT_HIP(ttk::gemm64_ops(st, P.opptr + step.first, 1, ttk::gemm64_blocks(o.m, o.n, o.k)));
+        int64_t gx = 0;
+        for (int q = step.first; q < step.first + step.count; ++q) {
+          const ttk::ChainOp& o = P.ops[q];
+          gx = std::max(gx, ttk::gemm64_blocks(o.m, o.n, o.k));
+        }
+        TT_HIP(ttk::gemm64_ops(st, P.opptr + step.first, step.count, gx));
         break;
       }
       case kStepPass1: {
