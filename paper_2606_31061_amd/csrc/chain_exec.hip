@@ -99,6 +99,37 @@ __device__ __forceinline__ int small_div(int a, int b, int& rem) {
   return q;
 }
 
+// use(i, j, ld(i, j)) for every (i, j) of an m x n index space (m, n >= 1)
+// in the order of for_each_ij, U elements per thread at a time: the U loads
+// are issued together (unconditionally, element (0, 0) standing in past the
+// end) before any use, instead of one memory round trip per element.
+template <int U, class Ld, class Use>
+__device__ __forceinline__ void for_each_ij_ld(int m, int n, Ld ld, Use use) {
+  const int tid = tix(), di = kCT % m, dj = kCT / m;
+  int i;
+  int j = small_div(tid, m, i);
+  while (j < n) {
+    int ii[U], jj[U];
+    double x[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      ii[u] = i;
+      jj[u] = j;
+      const bool ok = j < n;
+      x[u] = ld(ok ? i : 0, ok ? j : 0);
+      i += di;
+      j += dj;
+      if (i >= m) {
+        i -= m;
+        ++j;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (jj[u] < n) use(ii[u], jj[u], x[u]);
+  }
+}
+
 // fn(i, j) for every (i, j) of an m x n index space (m >= 1), the workgroup's
 // threads walking i fastest.  The indices advance incrementally, so there is no
 // integer division per element.
@@ -123,16 +154,55 @@ __device__ __forceinline__ double read_lane(double x, int lane) {
   return __hiloint2double(hi, lo);
 }
 
+// Wave reductions without LDS traffic: DPP moves pair lanes within quads
+// (xor 1, xor 2) and rows (the half-row and row mirrors), the lane-swap
+// instructions pair rows 16 and 32 lanes apart.  Each step adds a lane's value
+// and its partner's, in an order that makes every lane of a pair compute the
+// same bits (x + y == y + x), so every lane ends with the same total.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+// the two values the lanes l and l ^ 16 (l ^ 32) hold, lower row first
+template <int D>
+__device__ __forceinline__ void row_pair(double v, double& a, double& b) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  if constexpr (D == 16) {
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    a = __hiloint2double(h[0], l[0]);
+    b = __hiloint2double(h[1], l[1]);
+  } else {
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    a = __hiloint2double(h[0], l[0]);
+    b = __hiloint2double(h[1], l[1]);
+  }
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_d<0xB1>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_d<0x4E>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_d<0x141>(v);  // row_half_mirror
+  v += dpp_d<0x140>(v);  // row_mirror
+  double a, b;
+  row_pair<16>(v, a, b);
+  v = a + b;
+  row_pair<32>(v, a, b);
+  return a + b;
 }
 
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmax(v, dpp_d<0xB1>(v));
+  v = fmax(v, dpp_d<0x4E>(v));
+  v = fmax(v, dpp_d<0x141>(v));
+  v = fmax(v, dpp_d<0x140>(v));
+  double a, b;
+  row_pair<16>(v, a, b);
+  v = fmax(a, b);
+  row_pair<32>(v, a, b);
+  return fmax(a, b);
 }
 
 // Workgroup sum (fixed order: reproducible); every thread gets the total.
@@ -416,7 +486,12 @@ __device__ __forceinline__ void stage(int dst, int drs, int dcs, int rows, int c
     for (int u = 0; u < U; ++u) {
       fi[u] = f;
       si[u] = sl;
-      x[u] = (e0 + u * kCT < total && f < fv && sl < sv) ? src[f * fs + sl * ss] : 0.0;
+      // unconditional load (element 0 stands in for the padding), so that no
+      // load sits in a branch of its own: the compiler then waits for each
+      // branch's load before issuing the next one
+      const bool ok = e0 + u * kCT < total && f < fv && sl < sv;
+      x[u] = src[ok ? f * fs + sl * ss : 0];
+      x[u] = ok ? x[u] : 0.0;
       f += df;
       sl += ds;
       if (f >= nf) {
@@ -640,7 +715,8 @@ __device__ __forceinline__ double rsqrt_pos(double d) {
 // a block the few entries needed come from single lanes, and the rows below
 // receive the block's four updates at once, the entries of row i read from
 // lane i into scalar registers (v_readlane), so no step waits on memory
-// (rowbuf is not used).  Only pivots of the first
+// (rowbuf is not used; broadcasting the rows through it was slower).  Only
+// pivots of the first
 // n columns are tested against thr2.  Writes R (zeros below the diagonal,
 // leading dimension 32) and R^-1 (leading dimension 33); R may alias W.
 // NEWTON = 1 leaves the pivots' square roots good to about 1e-10 relative,
@@ -935,6 +1011,59 @@ __device__ __forceinline__ void householder_qr(const Qr& q, double* A, int lda) 
   __syncthreads();
 }
 
+// The 32 x 32 stripe M(r0 .. r0 + 31, 0 .. 31) of an m x n matrix (zero
+// outside it) into this wave's LDS tile, element (r, c) at tile[32 r + (c ^ r)]
+// (the XOR keeps both the row and the column walks on distinct banks).  The
+// lanes walk M's contiguous index (rows when mrs <= mcs, columns otherwise),
+// so each load instruction reads whole cache lines; all 16 loads of a lane are
+// issued before the first is used.  One CU reads only some tens of GB/s, so
+// loads that touch 16 lines for 32 bytes each cost several microseconds per
+// tall matrix.
+__device__ __forceinline__ void load_tile(const double* M, int mrs, int mcs, int r0, int m, int n, double* tile) {
+  const int lane = tix() & 63, a = lane & 31, h = lane >> 5;
+  const bool rows = mrs <= mcs;  // lanes walk rows (a = row) or columns (a = column)
+  double x[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int r = rows ? a : 2 * k + h, c = rows ? 2 * k + h : a;
+    const bool ok = r0 + r < m && c < n;
+    x[k] = M[ok ? (unsigned)((r0 + r) * mrs + c * mcs) : 0u];
+  }
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    const int r = rows ? a : 2 * k + h, c = rows ? 2 * k + h : a;
+    const bool ok = r0 + r < m && c < n;
+    tile[32 * r + (c ^ r)] = ok ? x[k] : 0.0;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Row fragments f[s][cb] = X(4 s + l / 16, 16 cb + l % 16) and column fragments
+// g[t][kc] = X(16 t + l % 16, 4 kc + l / 16) of a wave's tile (see load_tile).
+__device__ __forceinline__ void tile_rows(const double* tile, double (&f)[8][2]) {
+  const int lane = tix() & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < 8; ++s)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) {
+      const int r = 4 * s + lk, c = 16 * cb + li;
+      f[s][cb] = tile[32 * r + (c ^ r)];
+    }
+  __builtin_amdgcn_wave_barrier();
+}
+__device__ __forceinline__ void tile_cols(const double* tile, double (&g)[2][8]) {
+  const int lane = tix() & 63, li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int t = 0; t < 2; ++t)
+#pragma unroll
+    for (int kc = 0; kc < 8; ++kc) {
+      const int r = 16 * t + li, c = 4 * kc + lk;
+      g[t][kc] = tile[32 * r + (c ^ r)];
+    }
+  __builtin_amdgcn_wave_barrier();
+}
+
 // Partial Gram blocks of a wave's 32-row stripe held in row fragments
 // f[s][cb] = X(r0 + 4s + l/16, 16 cb + l%16): blocks (0,0), (1,0), (1,1) of
 // X^T X go to part[(3 w + blk) * 256 + 64 v + l] (zero for a stripe wholly
@@ -992,16 +1121,20 @@ __device__ __forceinline__ bool cholqr2_reg(const Qr& q) {
   double* red = s_lds + kLdsRed;
   int* flag = reinterpret_cast<int*>(s_lds + kLdsFlag);
   constexpr int ldq = 513;
+  // 32-bit offsets (chain_fits32): one address register per load and no
+  // 64-bit multiplications
+  const int mrs = (int)q.mrs, mcs = (int)q.mcs;
 
-  // pass 1: W = M^T M from row fragments
+  // pass 1: W = M^T M from row fragments, read through the wave's LDS tile
+  double* tile = part + 1024 * w;
   double f[8][2];
+  if (live) {
+    load_tile(q.M, mrs, mcs, r0, m, n, tile);
+    tile_rows(tile, f);
+  } else {
 #pragma unroll
-  for (int s = 0; s < 8; ++s)
-#pragma unroll
-    for (int cb = 0; cb < 2; ++cb) {
-      const int row = r0 + 4 * s + lk, col = 16 * cb + li;
-      f[s][cb] = (row < m && col < n) ? q.M[row * q.mrs + col * q.mcs] : 0.0;
-    }
+    for (int s = 0; s < 8; ++s) f[s][0] = f[s][1] = 0.0;
+  }
   __syncthreads();
   stripe_gram(f, live, (m + 31) >> 5, part, W);
   {
@@ -1023,13 +1156,10 @@ __device__ __forceinline__ bool cholqr2_reg(const Qr& q) {
   // row-fragment order: block (t, cb) element v is Q1(r0 + 16t + 4v + l/16, 16cb + l%16)
   {
     double g[2][8];
-#pragma unroll
-    for (int t = 0; t < 2; ++t)
-#pragma unroll
-      for (int kc = 0; kc < 8; ++kc) {
-        const int row = r0 + 16 * t + li, col = 4 * kc + lk;
-        g[t][kc] = (row < m && col < n) ? q.M[row * q.mrs + col * q.mcs] : 0.0;
-      }
+    if (live) {
+      load_tile(q.M, mrs, mcs, r0, m, n, tile);
+      tile_cols(tile, g);
+    }
     v4d acc[2][2];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
@@ -1130,8 +1260,13 @@ __device__ __forceinline__ bool cholqr2_reg(const Qr& q) {
     }
   }
   if (q.R) {
-    const View R2v{kLdsW, 1, 32}, R1v{kLdsR1, 1, 32};
-    gemm_lds(n, n, 8, R2v, R1v, [&](int ii, int jj, double v) { q.R[ii + n * jj] = v; });
+    // R = R2 R1, both upper triangular: one element per thread, k in order
+    const int ii = tid & 31, jj = tid >> 5;
+    if (ii < n && jj < n) {
+      double v = 0.0;
+      for (int k = ii; k <= jj; ++k) v = fma(W[ii + 32 * k], R1[k + 32 * jj], v);
+      q.R[ii + n * jj] = v;
+    }
   }
   __syncthreads();
   return true;
@@ -1366,24 +1501,28 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
   int* flag = reinterpret_cast<int*>(s_lds + kLdsFlag);
   double* Q1 = q.aux;  // m x n column-major
 
-  auto load_rows = [&](const double* A, int64_t ars, int64_t acs, int st, double (&f)[8][2]) {
+  auto load_rows = [&](const double* A, int ars, int acs, int st, double (&f)[8][2]) {
     const int r0 = kQrRows * st + 32 * w;
 #pragma unroll
     for (int s = 0; s < 8; ++s)
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb) {
         const int row = r0 + 4 * s + lk, col = 16 * cb + li;
-        f[s][cb] = (row < m && col < n) ? A[row * ars + col * acs] : 0.0;
+        const bool ok = row < m && col < n;  // unconditional loads (see stage())
+        f[s][cb] = A[ok ? (unsigned)(row * ars + col * acs) : 0u];
+        f[s][cb] = ok ? f[s][cb] : 0.0;
       }
   };
-  auto load_cols = [&](const double* A, int64_t ars, int64_t acs, int st, double (&g)[2][8]) {
+  auto load_cols = [&](const double* A, int ars, int acs, int st, double (&g)[2][8]) {
     const int r0 = kQrRows * st + 32 * w;
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int kc = 0; kc < 8; ++kc) {
         const int row = r0 + 16 * t + li, col = 4 * kc + lk;
-        g[t][kc] = (row < m && col < n) ? A[row * ars + col * acs] : 0.0;
+        const bool ok = row < m && col < n;
+        g[t][kc] = A[ok ? (unsigned)(row * ars + col * acs) : 0u];
+        g[t][kc] = ok ? g[t][kc] : 0.0;
       }
   };
   auto pad_identity = [&]() {
@@ -1397,7 +1536,7 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
     double fa[8][2];
 #pragma unroll 1
     for (int st = 0; st < nst; ++st) {
-      load_rows(q.M, q.mrs, q.mcs, st, fa);
+      load_rows(q.M, (int)q.mrs, (int)q.mcs, st, fa);
       gram_acc(fa, g00, g10, g11);
     }
     __syncthreads();
@@ -1426,7 +1565,7 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
     };
 #pragma unroll 1
     for (int st = 0; st < nst; ++st) {
-      load_cols(q.M, q.mrs, q.mcs, st, ga);
+      load_cols(q.M, (int)q.mrs, (int)q.mcs, st, ga);
       finish(ga, st);
     }
     __syncthreads();  // Ri is read above and rewritten below; Q1 complete
@@ -1474,8 +1613,13 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
     }
   }
   if (q.R) {
-    const View R2v{kLdsW, 1, 32}, R1v{kLdsR1, 1, 32};
-    gemm_lds(n, n, 8, R2v, R1v, [&](int ii, int jj, double v) { q.R[ii + n * jj] = v; });
+    // R = R2 R1, both upper triangular: one element per thread, k in order
+    const int ii = tid & 31, jj = tid >> 5;
+    if (ii < n && jj < n) {
+      double v = 0.0;
+      for (int k = ii; k <= jj; ++k) v = fma(W[ii + 32 * k], R1[k + 32 * jj], v);
+      q.R[ii + n * jj] = v;
+    }
   }
   __syncthreads();
   return true;
@@ -1552,27 +1696,6 @@ __device__ __forceinline__ void rank1_qr(const Qr& q) {
   __syncthreads();
 }
 
-// Workgroup sums of K values per thread (fixed order: reproducible); every
-// thread gets the K totals in out[].  Uses red[0 .. 16 K).
-template <int K>
-__device__ __forceinline__ void block_sums(double (&v)[K], double* red, double (&out)[K]) {
-  const int lane = tix() & 63, wid = tix() >> 6;
-#pragma unroll
-  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
-  __syncthreads();
-  if (lane == 0)
-#pragma unroll
-    for (int k = 0; k < K; ++k) red[wid * K + k] = v[k];
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < K; ++k) {
-    double t = 0.0;
-#pragma unroll
-    for (int w = 0; w < kCW; ++w) t += red[w * K + k];
-    out[k] = t;
-  }
-}
-
 // Thin QR with the proper reflectors capped at 2 <= rho <= 4 (a local
 // solution of rank at most rho), R not wanted: Householder builds its rho
 // proper reflectors from the first rho columns alone (when none of them
@@ -1580,131 +1703,185 @@ __device__ __forceinline__ void block_sums(double (&v)[K], double* red, double (
 // reflectors, so Q = H_1 .. H_rho [I; 0] = E - V T V_top^T (compact WY form:
 // V the m x rho reflectors, unit diagonal, T upper triangular, V_top the
 // first n rows of V), column j negated where R(j, j) = beta_j < 0.  The
-// m x rho panel is factored in LDS; Q is written in one pass.  Returns false,
-// with nothing written, when one of the first rho columns would take an
-// identity reflector (the general path then decides).  m rho <= kMsDoubles.
+// m x rho panel goes to LDS (the whole matrix is read once, for ||M||_F), one
+// wave factors it and forms T with wave reductions only (lane l owns rows
+// l, l + 64, ...: no lane reads what another wrote), and Q is written in one
+// pass, wave w taking columns w, w + 16, ... and each lane its rows.  Returns
+// false, with nothing written, when one of the first rho columns would take
+// an identity reflector (the general path then decides).  m rho <= kMsDoubles.
 constexpr int kMsDoubles = 16448;
 constexpr int kSmallRho = 4;
+constexpr int kPanelRows = 8;  // rows per lane of the register panel (m <= 512)
 __device__ __forceinline__ bool small_capped_qr(const Qr& q) {
-  const int tid = tix();
+  const int tid = tix(), lane = tid & 63, w = tid >> 6;
   const int m = q.m, n = q.n, rho = q.rho;
   double* Pn = s_lds + kLdsMs;        // the panel, column-major, leading dimension m
-  double* red = s_lds + kLdsRow;      // block sums (up to 16 values)
-  double* U = s_lds + kLdsW;          // U = T V_top^T, rho x n (leading dimension kSmallRho)
-  double* sc = s_lds + kLdsTau;       // tau[4], beta[4], T (4 x 4, column-major)
+  double* red = s_lds + kLdsRow;      // block sums
+  double* U = s_lds + kLdsW;          // U = T V_top^T, kSmallRho x n (leading dimension kSmallRho)
+  double* sc = s_lds + kLdsTau;       // beta[4], T (4 x 4, column-major) at 8, status at 24
   // panel into LDS and ||M||_F^2
   double p = 0.0;
-  for_each_ij(m, n, [&](int i, int j) {
-    const double x = q.M[i * q.mrs + j * q.mcs];
-    p = fma(x, x, p);
-    if (j < rho) Pn[i + m * j] = x;
-  });
-  double fro2;
-  {
-    double a[1] = {p}, o[1];
-    block_sums<1>(a, red, o);
-    fro2 = o[0];
-  }
-  const double thr = q.tol * sqrt(fro2);
-  for (int j = 0; j < rho; ++j) {
-    double* cj = Pn + m * j;
-    double a[1] = {0.0}, o[1];
-    for (int i = j + tid; i < m; i += kCT) a[0] = fma(cj[i], cj[i], a[0]);
-    block_sums<1>(a, red, o);
-    const double nrm = sqrt(o[0]);
-    if (!(nrm > thr)) return false;  // uniform: every thread saw the same sum
-    const double alpha = cj[j];
-    const double beta = alpha >= 0.0 ? -nrm : nrm;
-    const double scal = 1.0 / (alpha - beta);
-    const double t = (beta - alpha) / beta;
-    __syncthreads();                  // cj[j] read by every thread before it is replaced
-    for (int i = j + 1 + tid; i < m; i += kCT) cj[i] *= scal;
-    if (tid == 0) {
-      cj[j] = 1.0;                    // the reflector's unit leading entry
-      sc[j] = t;
-      sc[kSmallRho + j] = beta;
-    }
-    __syncthreads();
-    // H_j on the panel's later columns: c -= t v (v^T c), rows j..m-1
-    if (j + 1 < rho) {
-      double w[kSmallRho - 1], wo[kSmallRho - 1];
+  for_each_ij_ld<8>(
+      m, n, [&](int i, int j) { return q.M[i * q.mrs + j * q.mcs]; },
+      [&](int i, int j, double x) {
+        p = fma(x, x, p);
+        if (j < rho) Pn[i + m * j] = x;
+      });
+  const double thr = q.tol * sqrt(block_sum(p, red));
+  if (w == 0) {
+    double tau[kSmallRho] = {0.0, 0.0, 0.0, 0.0};
+    bool ok = true;
+    if (m <= 64 * kPanelRows) {
+      // the panel in registers: lane l holds rows l + 64 k, k < kPanelRows
+      double P[kPanelRows][kSmallRho];
 #pragma unroll
-      for (int c = 0; c < kSmallRho - 1; ++c) w[c] = 0.0;
-      for (int i = j + tid; i < m; i += kCT) {
-        const double vi = cj[i];
+      for (int k = 0; k < kPanelRows; ++k)
 #pragma unroll
-        for (int c = 0; c < kSmallRho - 1; ++c)
-          if (j + 1 + c < rho) w[c] = fma(vi, Pn[i + m * (j + 1 + c)], w[c]);
+        for (int j = 0; j < kSmallRho; ++j) {
+          const int i = lane + 64 * k;
+          P[k][j] = (i < m && j < rho) ? Pn[i + m * j] : 0.0;
+        }
+#pragma unroll
+      for (int j = 0; j < kSmallRho; ++j) {
+        if (j >= rho || !ok) break;
+        double s2 = 0.0;
+#pragma unroll
+        for (int k = 0; k < kPanelRows; ++k)
+          if (lane + 64 * k >= j) s2 = fma(P[k][j], P[k][j], s2);
+        const double nrm = sqrt(wave_sum(s2));
+        ok = nrm > thr;  // uniform: every lane has the same sum
+        if (!ok) break;
+        const double alpha = read_lane(P[0][j], j);  // row j < 64 lives in lane j
+        const double beta = alpha >= 0.0 ? -nrm : nrm;
+        const double scal = 1.0 / (alpha - beta);
+        tau[j] = (beta - alpha) / beta;
+#pragma unroll
+        for (int k = 0; k < kPanelRows; ++k) {
+          const int i = lane + 64 * k;
+          if (i == j) P[k][j] = 1.0;
+          else if (i > j) P[k][j] *= scal;
+        }
+        if (lane == 0) sc[j] = beta;
+#pragma unroll
+        for (int c2 = j + 1; c2 < kSmallRho; ++c2) {
+          if (c2 >= rho) break;
+          double d = 0.0;
+#pragma unroll
+          for (int k = 0; k < kPanelRows; ++k)
+            if (lane + 64 * k >= j) d = fma(P[k][j], P[k][c2], d);
+          const double f = tau[j] * wave_sum(d);
+#pragma unroll
+          for (int k = 0; k < kPanelRows; ++k)
+            if (lane + 64 * k >= j) P[k][c2] = fma(-f, P[k][j], P[k][c2]);
+        }
       }
-      block_sums<kSmallRho - 1>(w, red, wo);
-      for (int i = j + tid; i < m; i += kCT) {
-        const double vi = cj[i];
+      // the reflectors back to LDS for the other waves
 #pragma unroll
-        for (int c = 0; c < kSmallRho - 1; ++c)
-          if (j + 1 + c < rho) Pn[i + m * (j + 1 + c)] = fma(-t * wo[c], vi, Pn[i + m * (j + 1 + c)]);
+      for (int k = 0; k < kPanelRows; ++k)
+#pragma unroll
+        for (int j = 0; j < kSmallRho; ++j) {
+          const int i = lane + 64 * k;
+          if (i < m && j < rho) Pn[i + m * j] = P[k][j];
+        }
+      __builtin_amdgcn_wave_barrier();
+    } else {
+      for (int j = 0; j < rho && ok; ++j) {
+        double* cj = Pn + m * j;
+        double s2 = 0.0;
+        for (int i = lane; i < m; i += 64)
+          if (i >= j) s2 = fma(cj[i], cj[i], s2);
+        const double nrm = sqrt(wave_sum(s2));
+        ok = nrm > thr;  // uniform: every lane has the same sum
+        if (!ok) break;
+        const double alpha = cj[j];
+        __builtin_amdgcn_wave_barrier();  // every lane has read cj[j] before its owner rewrites it
+        const double beta = alpha >= 0.0 ? -nrm : nrm;
+        const double scal = 1.0 / (alpha - beta);
+        tau[j] = (beta - alpha) / beta;
+        for (int i = lane; i < m; i += 64)
+          if (i >= j) cj[i] = (i == j) ? 1.0 : cj[i] * scal;
+        if (lane == 0) sc[j] = beta;
+        // H_j on the panel's later columns: c -= tau_j v (v^T c)
+        for (int c2 = j + 1; c2 < rho; ++c2) {
+          double* cc = Pn + m * c2;
+          double d = 0.0;
+          for (int i = lane; i < m; i += 64)
+            if (i >= j) d = fma(cj[i], cc[i], d);
+          const double f = tau[j] * wave_sum(d);
+          for (int i = lane; i < m; i += 64)
+            if (i >= j) cc[i] = fma(-f, cj[i], cc[i]);
+        }
       }
-      __syncthreads();
     }
-  }
-  // T of the compact WY form: T_jj = tau_j, T(0:j, j) = -tau_j T(0:j, 0:j) V(:, 0:j)^T v_j;
-  // the pair products V(:, a)^T V(:, b), a < b, in the order (0,1), (0,2), (1,2), (0,3), ...
-  {
-    constexpr int NP = kSmallRho * (kSmallRho - 1) / 2;
-    double g[NP], go[NP];
-#pragma unroll
-    for (int k = 0; k < NP; ++k) g[k] = 0.0;
-    for (int i = tid; i < m; i += kCT) {
-      int k = 0;
+    if (ok) {
+      // T: T_bb = tau_b, T(0:b, b) = -tau_b T(0:b, 0:b) V(:, 0:b)^T v_b, from the
+      // pair products V(:, a)^T V(:, b), a < b (V(i, a) = 0 above row a)
+      double g[kSmallRho][kSmallRho];
 #pragma unroll
       for (int b = 1; b < kSmallRho; ++b)
 #pragma unroll
-        for (int a = 0; a < b; ++a) {
-          if (b < rho) {
-            const double va = i < a ? 0.0 : Pn[i + m * a];
-            const double vb = i < b ? 0.0 : Pn[i + m * b];
-            g[k] = fma(va, vb, g[k]);
-          }
-          ++k;
+        for (int a2 = 0; a2 < b; ++a2) {
+          double d = 0.0;
+          if (b < rho)
+            for (int i = lane; i < m; i += 64)
+              if (i >= b) d = fma(Pn[i + m * a2], Pn[i + m * b], d);
+          g[a2][b] = wave_sum(d);
         }
-    }
-    block_sums<NP>(g, red, go);
-    if (tid == 0) {
-      double* T = sc + 2 * kSmallRho;
-      for (int e = 0; e < kSmallRho * kSmallRho; ++e) T[e] = 0.0;
-      int k = 0;
-      for (int b = 0; b < rho; ++b) {
-        T[b + kSmallRho * b] = sc[b];
-        for (int a = 0; a < b; ++a) {
+      double T[kSmallRho][kSmallRho];
+#pragma unroll
+      for (int b = 0; b < kSmallRho; ++b)
+#pragma unroll
+        for (int a2 = 0; a2 < kSmallRho; ++a2) T[a2][b] = 0.0;
+#pragma unroll
+      for (int b = 0; b < kSmallRho; ++b) {
+        if (b >= rho) break;
+        T[b][b] = tau[b];
+#pragma unroll
+        for (int a2 = 0; a2 < b; ++a2) {
           double acc = 0.0;
-          for (int c = a; c < b; ++c) acc += T[a + kSmallRho * c] * go[k + c];
-          T[a + kSmallRho * b] = -sc[b] * acc;
+#pragma unroll
+          for (int c = a2; c < b; ++c) acc += T[a2][c] * g[c][b];
+          T[a2][b] = -tau[b] * acc;
         }
-        k += b;
+      }
+      if (lane < kSmallRho * kSmallRho) {
+        const int a2 = lane & 3, b = lane >> 2;
+        double v = 0.0;
+#pragma unroll
+        for (int e = 0; e < kSmallRho * kSmallRho; ++e)
+          if (e == lane) v = T[e & 3][e >> 2];
+        sc[8 + a2 + kSmallRho * b] = v;
       }
     }
-    __syncthreads();
-  }
-  // U = T V_top^T (rho x n); V_top(c, b) = 0 for c < b, 1 for c == b
-  for (int e = tid; e < rho * n; e += kCT) {
-    const int a = e % rho, c = e / rho;
-    const double* T = sc + 2 * kSmallRho;
-    double acc = 0.0;
-    for (int b = a; b < rho; ++b) {
-      const double vcb = c < b ? 0.0 : (c == b ? 1.0 : Pn[c + m * b]);
-      acc = fma(T[a + kSmallRho * b], vcb, acc);
-    }
-    U[a + kSmallRho * c] = acc;
+    if (lane == 0) sc[24] = ok ? 1.0 : 0.0;
   }
   __syncthreads();
-  for_each_ij(m, n, [&](int i, int c) {
-    double val = (i == c) ? 1.0 : 0.0;
-    for (int a = 0; a < rho; ++a) {
-      const double via = i < a ? 0.0 : (i == a ? 1.0 : Pn[i + m * a]);
-      val = fma(-via, U[a + kSmallRho * c], val);
+  if (sc[24] == 0.0) return false;  // uniform
+  const double* T = sc + 8;
+  // U = T V_top^T (kSmallRho x n, rows >= rho zero); V_top(c, b) = 0 for c < b, 1 for c == b
+  for (int e = tid; e < kSmallRho * n; e += kCT) {
+    const int a2 = e & 3, c = e >> 2;
+    double acc = 0.0;
+    for (int b = a2; b < rho; ++b) {
+      const double vcb = c < b ? 0.0 : (c == b ? 1.0 : Pn[c + m * b]);
+      acc = fma(T[a2 + kSmallRho * b], vcb, acc);
     }
-    if (c < rho && sc[kSmallRho + c] < 0.0) val = -val;
-    q.Q[i * q.qrs + c * q.qcs] = val;
-  });
+    U[e] = acc;
+  }
+  __syncthreads();
+  for (int i = lane; i < m; i += 64) {
+    double pv[kSmallRho];
+#pragma unroll
+    for (int a2 = 0; a2 < kSmallRho; ++a2)
+      pv[a2] = a2 >= rho ? 0.0 : (i < a2 ? 0.0 : (i == a2 ? 1.0 : Pn[i + m * a2]));
+    for (int c = w; c < n; c += kCW) {
+      double val = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+      for (int a2 = 0; a2 < kSmallRho; ++a2) val = fma(-pv[a2], U[a2 + kSmallRho * c], val);
+      if (c < rho && sc[c] < 0.0) val = -val;
+      q.Q[i * q.qrs + c * q.qcs] = val;
+    }
+  }
   __syncthreads();
   return true;
 }
