@@ -722,9 +722,9 @@ __device__ __forceinline__ double rsqrt_pos(double d) {
 // NEWTON = 1 leaves the pivots' square roots good to about 1e-10 relative,
 // which suffices when a second CholeskyQR pass corrects the factor: R and
 // R^-1 are exact inverses of each other either way.
-template <int NEWTON>
-__device__ __forceinline__ bool chol_inv32(const double* W, double* R, double* Ri, double* rowbuf, double thr2,
-                                           int n) {
+template <int NB, int NEWTON>
+__device__ __forceinline__ bool chol_inv(const double* W, double* R, double* Ri, double* rowbuf, double thr2,
+                                         int n) {
   const int lane = tix() & 63;
   int c = lane & 31;
   // opaque to the optimiser: keeps the identity set-up below from being
@@ -739,7 +739,7 @@ __device__ __forceinline__ bool chol_inv32(const double* W, double* R, double* R
   }
   bool ok = true;
 #pragma unroll
-  for (int jb = 0; jb < 32; jb += 4) {
+  for (int jb = 0; jb < NB; jb += 4) {
 #pragma unroll
     for (int j = jb; j < jb + 4; ++j) {
       const double d = read_lane(v[j], j);
@@ -751,7 +751,7 @@ __device__ __forceinline__ bool chol_inv32(const double* W, double* R, double* R
     // rows below the block: R(jb..jb+3, i) lives in lane i; it reaches every
     // lane through scalar registers (no memory round trip on the chain)
 #pragma unroll
-    for (int i = jb + 4; i < 32; ++i) {
+    for (int i = jb + 4; i < NB; ++i) {
       const double r0 = read_lane(v[jb], i), r1 = read_lane(v[jb + 1], i);
       const double r2 = read_lane(v[jb + 2], i), r3 = read_lane(v[jb + 3], i);
       v[i] = fma(-r0, v[jb], v[i]);
@@ -766,6 +766,15 @@ __device__ __forceinline__ bool chol_inv32(const double* W, double* R, double* R
     *dst = (xh || i <= c) ? v[i] : 0.0;
   }
   return ok;
+}
+
+// The factorisation stops after the leading NB columns when n <= NB: beyond
+// n, W is the identity, whose columns no elimination step changes.
+template <int NEWTON>
+__device__ __forceinline__ bool chol_inv32(const double* W, double* R, double* Ri, double* rowbuf, double thr2,
+                                           int n) {
+  if (n <= 8) return chol_inv<8, NEWTON>(W, R, Ri, rowbuf, thr2, n);
+  return chol_inv<32, NEWTON>(W, R, Ri, rowbuf, thr2, n);
 }
 
 // ------------------------------------------------------------------ QR
@@ -1128,9 +1137,11 @@ __device__ __forceinline__ bool cholqr2_reg(const Qr& q) {
   // pass 1: W = M^T M from row fragments, read through the wave's LDS tile
   double* tile = part + 1024 * w;
   double f[8][2];
+  double g[2][8];  // the column fragments for Q1 = M R1^-1, kept from the same read
   if (live) {
     load_tile(q.M, mrs, mcs, r0, m, n, tile);
     tile_rows(tile, f);
+    tile_cols(tile, g);
   } else {
 #pragma unroll
     for (int s = 0; s < 8; ++s) f[s][0] = f[s][1] = 0.0;
@@ -1152,14 +1163,9 @@ __device__ __forceinline__ bool cholqr2_reg(const Qr& q) {
   __syncthreads();
   if (!flag[0]) return false;
 
-  // Q1 = M R1^-1: column fragments of M (second read, cached), result in
+  // Q1 = M R1^-1: column fragments of M (from the first read), result in
   // row-fragment order: block (t, cb) element v is Q1(r0 + 16t + 4v + l/16, 16cb + l%16)
   {
-    double g[2][8];
-    if (live) {
-      load_tile(q.M, mrs, mcs, r0, m, n, tile);
-      tile_cols(tile, g);
-    }
     v4d acc[2][2];
 #pragma unroll
     for (int t = 0; t < 2; ++t)
