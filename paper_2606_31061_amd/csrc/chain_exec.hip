@@ -631,6 +631,53 @@ __device__ __forceinline__ void small_gemm(const Gemm& g, int M, int N, int K) {
   __syncthreads();
 }
 
+// Products with n <= 32 and depth <= 32 that small_gemm does not take: B goes
+// to LDS (zero beyond n, up to whole 8-column groups), and thread t computes
+// row i = t % M of one group of 8 output columns, adding the depth in k order
+// (A read once per row and k; B read from LDS, the same address across the
+// wave).  Consecutive threads take consecutive rows, so column-major A and C
+// are read and written along their contiguous index.
+constexpr int kRowCols = 8;
+__device__ __forceinline__ void rowblock_gemm(const Gemm& g, int M, int N, int K) {
+  const int tid = tix();
+  double* Bs = s_lds + kLdsPart;  // K x 32, column-major, leading dimension 32
+  const int ng = (N + kRowCols - 1) / kRowCols;
+  const int ncols = ng * kRowCols;
+  for (int e = tid; e < 32 * ncols; e += kCT) {
+    const int k = e & 31, j = e >> 5;
+    const bool ok = k < K && j < N;
+    const double v = g.B[ok ? k * g.brs + j * g.bcs : 0];
+    Bs[e] = ok ? v : 0.0;
+  }
+  __syncthreads();
+  const int ars = g.ars, acs = g.acs;
+  for (int t = tid; t < M * ng; t += kCT) {
+    int i;
+    const int grp = small_div(t, M, i);
+    const int j0 = grp * kRowCols;
+    const double* a = g.A + i * ars;
+    const double* b = Bs + 32 * j0;
+    double acc[kRowCols];
+#pragma unroll
+    for (int c = 0; c < kRowCols; ++c) acc[c] = 0.0;
+#pragma unroll 4
+    for (int k = 0; k < K; ++k) {
+      const double x = a[k * acs];
+#pragma unroll
+      for (int c = 0; c < kRowCols; ++c) acc[c] = fma(x, b[k + 32 * c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < kRowCols; ++c) {
+      if (j0 + c < N) {
+        const int o = i * g.crs + (j0 + c) * g.ccs;
+        if (g.C) g.C[o] = acc[c];
+        if (g.C32) g.C32[o] = (float)acc[c];
+      }
+    }
+  }
+  __syncthreads();
+}
+
 // C = A B from global operands.  The output is cut into tiles of at most
 // 64 blocks; for each tile the needed rows of A and columns of B go through
 // LDS one k-chunk at a time.
@@ -642,6 +689,14 @@ __device__ __forceinline__ void wg_gemm(const Gemm& g) {
   }
   if ((int64_t)M * N * K <= kSmallFma && small_gemm_fits(M * N, K)) {
     small_gemm(g, M, N, K);
+    return;
+  }
+  if (N <= 32 && K <= 32) {
+    rowblock_gemm(g, M, N, K);
+    return;
+  }
+  if (M <= 32 && K <= 32) {  // the same on C^T = B^T A^T
+    rowblock_gemm(Gemm{g.N, g.M, g.K, g.B, g.bcs, g.brs, g.A, g.acs, g.ars, g.C, g.ccs, g.crs, g.C32}, N, M, K);
     return;
   }
   const int w = tix() >> 6;
