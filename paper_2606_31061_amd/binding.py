@@ -386,7 +386,7 @@ class TTStream:
         """Names of the contraction kernels of the two slice passes."""
         a, b = c_int32(), c_int32()
         _check(self._lib.tt_stream_pass_kernels(self._h, byref(a), byref(b)), "tt_stream_pass_kernels")
-        return ("k_pass1", "k_pass1b")[a.value], ("k_pass2", "k_pass2b", "k_pass2s")[b.value]
+        return ("k_pass1", "k_pass1b")[a.value], ("k_pass2", "k_pass2b", "k_pass2s", "k_pass2g")[b.value]
 
     def time_passes(self, xs, reps: int = 50):
         """Average device us per launch of the slice-pass kernels, launched

@@ -506,6 +506,133 @@ __global__ void __launch_bounds__(kPass2Waves * 64) k_pass2(const T* __restrict_
   if (bad) atomicOr(flag, 1);
 }
 
+
+// Pass 2 for FP32 slices with P % 4 == 0, P <= kPass2gMaxRows and r <= 32
+// (the grouped kernel).  Grid ceil(J/32) blocks of kPass2gWaves waves; block
+// b owns columns [32 b, 32 b + 32).  The ceil(P/8) eight-row MFMA k-steps are
+// split over the waves in contiguous runs (wave w takes steps
+// [K w / NW, K (w+1) / NW)), so the four waves of a SIMD hold about the same
+// number.  A wave issues every load of its rows at once, the interface's
+// before the slice's, in 16-row groups: two 16-byte loads per lane cover a
+// group's 32 columns (lane -> column 16h + lane/4, rows 4 (lane%4) .. +3, so
+// each column is read as one 64-byte run).  Group c is then written to two
+// 32 x 16 wave-private LDS tiles (slice and interface) and read back as MFMA
+// fragments as soon as its loads have landed, so a wave's MFMAs start on
+// its first group while the rest of its rows are still in flight; no block
+// barrier is needed before the final reduction.  Rows past P, columns past J
+// and ranks past r are zeroed at the LDS write; groups past the wave's run
+// are loaded (clamped) but not multiplied.
+constexpr int kPass2gWaves = 16;
+constexpr int kPass2gGroups = 5;  // 16-row groups per wave: up to 10 k-steps
+constexpr int kPass2gLdp = 20;    // LDS row pitch of a 32 x 16 tile (floats)
+constexpr int64_t kPass2gMaxRows = 8LL * 2 * kPass2gGroups * kPass2gWaves;
+constexpr size_t kPass2gLds =
+    (size_t)kPass2gWaves * 64 * kPass2gLdp * sizeof(float) > (size_t)kPass2gWaves * 1024 * sizeof(float)
+        ? (size_t)kPass2gWaves * 64 * kPass2gLdp * sizeof(float)
+        : (size_t)kPass2gWaves * 1024 * sizeof(float);
+
+__global__ void __launch_bounds__(kPass2gWaves * 64) k_pass2g(const float* __restrict__ X, int64_t P, int64_t J, int r,
+                                                              const float* __restrict__ A, double* __restrict__ Y,
+                                                              int* __restrict__ flag,
+                                                              const PassDesc* __restrict__ batch) {
+  if (batch) {
+    const PassDesc& pp = batch[blockIdx.y];
+    X = static_cast<const float*>(pp.x);
+    A = pp.w;
+    Y = pp.out;
+    flag = pp.flag;
+    P = pp.P;
+    J = pp.J;
+    r = pp.r;
+  }
+  if ((int64_t)blockIdx.x * 32 >= J) return;  // past this member's columns
+  constexpr int NW = kPass2gWaves, G = kPass2gGroups, LDP = kPass2gLdp;
+  extern __shared__ float lds[];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int g = lane >> 5, jl = lane & 31;
+  const int64_t j0 = (int64_t)blockIdx.x * 32;
+  const int np = (int)P;  // P <= kPass2gMaxRows
+  const int K = (np + 7) >> 3;
+  const int kb = K * w / NW, nk = K * (w + 1) / NW - kb;
+  const int rb = 8 * kb;
+  const int lc = lane >> 2, lr = 4 * (lane & 3);
+  f4 ar[2 * G], xr[2 * G];
+#pragma unroll
+  for (int c = 0; c < G; ++c)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      int p = rb + 16 * c + lr;
+      p = p < np - 4 ? p : np - 4;
+      int a = 16 * h + lc;
+      a = a < r ? a : r - 1;
+      ar[2 * c + h] = *gptr(reinterpret_cast<const f4*>(A + p + P * (int64_t)a));
+    }
+#pragma unroll
+  for (int c = 0; c < G; ++c)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      int p = rb + 16 * c + lr;
+      p = p < np - 4 ? p : np - 4;
+      int64_t jj = j0 + 16 * h + lc;
+      jj = jj < J ? jj : J - 1;
+      xr[2 * c + h] = *gptr(reinterpret_cast<const f4*>(X + p + P * jj));
+    }
+  // keep every load ahead of the first LDS write
+  __builtin_amdgcn_sched_barrier(0);
+  float* Xs = lds + w * 64 * LDP;
+  float* As = Xs + 32 * LDP;
+  floatx16 acc = floatx16{0};
+#pragma unroll
+  for (int c = 0; c < G; ++c) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int col = 16 * h + lc;
+      const bool xok = j0 + col < J, aok = col < r;
+      f4 v, u;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const bool rok = rb + 16 * c + lr + s < np;
+        v[s] = (xok && rok) ? xr[2 * c + h][s] : 0.f;
+        u[s] = (aok && rok) ? ar[2 * c + h][s] : 0.f;
+      }
+      // the wave's own tiles: its LDS operations complete in order, so the
+      // next group's writes cannot overtake this group's reads
+      *reinterpret_cast<f4*>(&Xs[col * LDP + lr]) = v;
+      *reinterpret_cast<f4*>(&As[col * LDP + lr]) = u;
+    }
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk) {
+      if (2 * c + kk < nk) {
+        const f4 xv = *reinterpret_cast<const f4*>(&Xs[jl * LDP + 8 * kk + 4 * g]);
+        const f4 av = *reinterpret_cast<const f4*>(&As[jl * LDP + 8 * kk + 4 * g]);
+        acc = mfma32(xv.x, av.x, acc);
+        acc = mfma32(xv.y, av.y, acc);
+        acc = mfma32(xv.z, av.z, acc);
+        acc = mfma32(xv.w, av.w, acc);
+      }
+    }
+  }
+  // cross-wave reduction in LDS (reuses the tiles), wave order
+  __syncthreads();
+#pragma unroll
+  for (int v = 0; v < 16; ++v) lds[(w * 16 + v) * 64 + lane] = acc[v];
+  __syncthreads();
+  int bad = 0;
+  for (int e = threadIdx.x; e < 1024; e += NW * 64) {
+    float s = 0.f;
+#pragma unroll
+    for (int ww = 0; ww < NW; ++ww) s += lds[ww * 1024 + e];
+    const int v = e / 64, ln = e % 64;
+    const int64_t jj = j0 + mfma_row(ln, v);
+    const int a = ln & 31;
+    if (jj < J && a < r) {
+      Y[a + (int64_t)r * jj] = (double)s;
+      if (!isfinite(s)) bad = 1;
+    }
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
 // ------------------------------------------------------------------ launch
 template <typename T, int VEC, int NW, int NTN>
 hipError_t launch_p1(hipStream_t st, const T* X, int64_t P, int64_t J, int r, const float* B, double* Z, float* ws,
@@ -636,6 +763,9 @@ void pass1_grids(const Pass1Plan& pl, int64_t P, unsigned* gx, unsigned* grx) {
 }
 
 unsigned pass2_grid(int64_t J) { return (unsigned)((J + 31) / 32); }
+bool pass2_grouped(int64_t P, int r, tt_dtype xdt) {
+  return xdt == TT_F32 && P % 4 == 0 && P >= 4 && P <= kPass2gMaxRows && r <= 32;
+}
 int pass2_vec(int64_t P) { return P % 4 == 0 ? 4 : (P % 2 == 0 ? 2 : 1); }
 
 hipError_t pass1(hipStream_t st, const void* X, tt_dtype xdt, const Pass1Plan& pl, int64_t P, int64_t J, int r,
@@ -652,6 +782,17 @@ hipError_t pass1(hipStream_t st, const void* X, tt_dtype xdt, const Pass1Plan& p
 hipError_t pass2(hipStream_t st, const void* X, tt_dtype xdt, int64_t P, int64_t J, int r, const float* A, double* Y,
                  int* flag, const PassLaunch* bl) {
   if (r < 1 || r > 64 || (bl && (bl->n < 1 || bl->n > 65535))) return hipErrorInvalidValue;
+  if (pass2_grouped(P, r, xdt)) {
+    const dim3 grid(bl ? bl->gx : pass2_grid(J), bl ? (unsigned)bl->n : 1u);
+    if (pass_launch_mask() & 1)
+      hipLaunchKernelGGL(k_pass2g, grid, dim3(kPass2gWaves * 64), kPass2gLds, st, static_cast<const float*>(X), P, J,
+                         r, A, Y, flag, bl ? bl->desc : nullptr);
+    if (hipEvent_t m = pass_mid_event()) {
+      const hipError_t e = hipEventRecord(m, st);
+      if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+  }
   switch (xdt) {
     case TT_F32: return pass2_t(st, static_cast<const float*>(X), P, J, r, A, Y, flag, bl);
     case TT_F64: return pass2_t(st, static_cast<const double*>(X), P, J, r, A, Y, flag, bl);
@@ -674,6 +815,8 @@ hipError_t pass_setup() {
   TT_A2(double)
   TT_A2(__hip_bfloat16)
 #undef TT_A2
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_pass2g, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPass2gLds);
   return e;
 }
 

@@ -174,6 +174,9 @@ hipError_t pass2(hipStream_t st, const void* X, tt_dtype xdt, int64_t P, int64_t
 unsigned pass2_grid(int64_t J);
 // Template shape of pass 2 for these sizes (members of one launch share it).
 int pass2_vec(int64_t P);
+// Whether pass 2 runs the grouped FP32 kernel k_pass2g for these sizes (FP32
+// slices, P % 4 == 0, P <= 1280, r <= 32); part of the template shape too.
+bool pass2_grouped(int64_t P, int r, tt_dtype xdt);
 
 // ---------------------------------------------------------------- passes (BF16)
 // The same two contractions with the slice and the interface rounded to BF16

@@ -16,8 +16,12 @@ def _rng(s):
     return np.random.Generator(np.random.PCG64(s))
 
 
+# The FP32 pass 2 runs k_pass2g where P % 4 == 0, P <= 1280 and r <= 32 (its
+# edges: P % 8 == 4, P = 1280 with ten k-steps per wave, P = 4, ranks and
+# columns that leave part of a tile empty) and k_pass2 elsewhere (1284, ...).
 CASES = [(32, 32, 4), (240, 960, 16), (1080, 5760, 32), (100, 77, 5), (33, 1, 8), (200, 300, 48),
-         (8, 777, 8), (4, 3, 1), (90, 70, 16), (6, 50, 3), (1090, 400, 40)]
+         (8, 777, 8), (4, 3, 1), (90, 70, 16), (6, 50, 3), (1090, 400, 40), (1084, 100, 32), (1280, 64, 32),
+         (1284, 40, 7), (12, 33, 31)]
 
 
 def _ref_round(X, dt):
