@@ -341,11 +341,12 @@ def write_traffic(fetch_db, write_db, workload, compute):
         out[key.replace("_bytes", "_scale")] = scale
         with open(os.path.join(ROOT, KERNEL_SOURCES[compute]), "rb") as f:
             digest = hashlib.sha256(f.read()).hexdigest()
-        passes = ([["k_pass1b"], ["k_pass2b", "k_pass2s"]] if compute == "bf16" else [["k_pass1"], ["k_pass2"]])
+        passes = ([["k_pass1b"], ["k_pass2b", "k_pass2s"]] if compute == "bf16"
+                  else [["k_pass1"], ["k_pass2g", "k_pass2"]])
         for kerns in passes:
             found = False
             for kern in kerns:
-                vals = [v for _, k, v in rows if re.search(r"\b" + kern + "<", k)][-10:]
+                vals = [v for _, k, v in rows if re.search(r"\b" + kern + r"[<(]", k)][-10:]
                 if not vals:
                     continue
                 found = True
@@ -534,8 +535,12 @@ def single_stream_section(torch, spec, pool, compute, tune, args, quiet=False):
         s.synchronize()
         lat_all.append((time.perf_counter() - ts) * 1e3)
     s.close()
-    log(f"[{compute}] latency push to commit p50 {np.percentile(lat, 50):.3f} ms p99 {np.percentile(lat, 99):.3f} ms; "
-        f"push to all work done p50 {np.percentile(lat_all, 50):.3f} ms")
+    def pct(v, q):  # None when the latency runs were skipped (--latency-steps 0)
+        return float(np.percentile(v, q)) if v else None
+
+    if lat:
+        log(f"[{compute}] latency push to commit p50 {pct(lat, 50):.3f} ms p99 {pct(lat, 99):.3f} ms; "
+            f"push to all work done p50 {pct(lat_all, 50):.3f} ms")
 
     # the passes inside the update, and optionally the chain's operations
     sp = TTStream(spec.modes, spec.ranks, init=(cores, g), profile_ops=True, compute=compute, autotune=tune)
@@ -572,10 +577,10 @@ def single_stream_section(torch, spec, pool, compute, tune, args, quiet=False):
         "split": (k, P, J, r),
         "value": args.steps / elapsed,
         "ms_per_step": ms_step,
-        "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99),
                        "device_last": dev_ms, "measured": "push to committed result, slices arriving with gaps",
-                       "push_to_all_work_p50": float(np.percentile(lat_all, 50)),
-                       "push_to_all_work_p99": float(np.percentile(lat_all, 99))},
+                       "push_to_all_work_p50": pct(lat_all, 50),
+                       "push_to_all_work_p99": pct(lat_all, 99)},
         "roofline": {"bound": "hbm", "kernel": kname, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_source": (f"{os.path.relpath(TRAFFIC_FILE, ROOT)}: rocprofv3 FETCH_SIZE and WRITE_SIZE "
