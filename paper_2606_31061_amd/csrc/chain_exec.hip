@@ -1704,9 +1704,22 @@ __device__ __forceinline__ void rank1_qr(const Qr& q) {
   double* v = s_lds + kLdsMs;    // the reflector (m values)
   double* sc = s_lds + kLdsRed;  // [0] t, [1] sign of column j0, [2] j0 (as double)
   for (int j = wid; j < n; j += kCW) {
+    const double* col = q.M + (int64_t)j * q.mcs;
     double pf = 0.0, pr = 0.0;
-    for (int i = lane; i < m; i += 64) {
-      const double x = q.M[i * q.mrs + (int64_t)j * q.mcs];
+    int i = lane;
+    // eight rows per lane in flight, added in row order as in the remainder
+    for (; i + 7 * 64 < m; i += 8 * 64) {
+      double x[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) x[u] = col[(int64_t)(i + 64 * u) * q.mrs];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        pf = fma(x[u], x[u], pf);
+        if (i + 64 * u >= j) pr = fma(x[u], x[u], pr);
+      }
+    }
+    for (; i < m; i += 64) {
+      const double x = col[(int64_t)i * q.mrs];
       pf = fma(x, x, pf);
       if (i >= j) pr = fma(x, x, pr);
     }
@@ -1742,9 +1755,11 @@ __device__ __forceinline__ void rank1_qr(const Qr& q) {
   __syncthreads();
   const double t = sc[0], flip = sc[1], scal = sc[3];
   const int j0 = (int)sc[2];
-  if (j0 < n)
+  if (j0 < n) {
+#pragma unroll 4
     for (int i = tid; i < m; i += kCT)
       v[i] = (i < j0) ? 0.0 : (i == j0 ? 1.0 : q.M[i * q.mrs + (int64_t)j0 * q.mcs] * scal);
+  }
   __syncthreads();
   for_each_ij(m, n, [&](int i, int j) {
     double val = (i == j) ? 1.0 : 0.0;
@@ -1947,23 +1962,45 @@ __device__ __forceinline__ bool small_capped_qr(const Qr& q) {
   return true;
 }
 
-// The completion of a tall QR capped at rho < n (see wg_qr): W = Q_rho(rho..n-1, :)
-// through LDS, then C = E - Q_rho W^T into Q's columns rho..n-1.
+// The completion of a tall QR capped at rho < n (see wg_qr): C = E - Q_rho W^T
+// into Q's columns rho..n-1, W = Q_rho(rho..n-1, :).  Laid out like
+// rowblock_gemm: -W^T goes to LDS (zero beyond rho and nc), thread t takes
+// row i = t % m of one group of 8 completion columns and walks the depth in
+// k order from the identity entry (the same FMA sequence for every layout),
+// several rows of Q_rho in flight.  The columns read (k < rho) and written
+// (rho and beyond) are disjoint.
 __device__ __forceinline__ void capped_completion(const Qr& q) {
+  const int tid = tix();
   const int m = q.m, n = q.n, rho = q.rho;
   const int nc = n - rho;
-  double* W = s_lds + kLdsW;  // nc x rho, leading dimension 32
-  for (int e = tix(); e < nc * rho; e += kCT) {
-    const int jc = e % nc, k = e / nc;
-    W[jc + 32 * k] = q.Q[(rho + jc) * q.qrs + k * q.qcs];
+  double* Bs = s_lds + kLdsPart;  // Bs[k + 32 jc] = -W(jc, k)
+  for (int e = tid; e < 32 * 32; e += kCT) {
+    const int k = e & 31, jc = e >> 5;
+    const bool ok = k < rho && jc < nc;
+    const double v = q.Q[ok ? (rho + jc) * q.qrs + k * q.qcs : 0];
+    Bs[e] = ok ? -v : 0.0;
   }
   __syncthreads();
   double* C = q.Q + (int64_t)rho * q.qcs;
-  for_each_ij(m, nc, [&](int i, int jc) {
-    double v = (i == rho + jc) ? 1.0 : 0.0;
-    for (int k = 0; k < rho; ++k) v = fma(-q.Q[i * q.qrs + k * q.qcs], W[jc + 32 * k], v);
-    C[i * q.qrs + jc * q.qcs] = v;
-  });
+  const int ng = (nc + kRowCols - 1) / kRowCols;
+  for (int t = tid; t < m * ng; t += kCT) {
+    int i;
+    const int j0 = small_div(t, m, i) * kRowCols;
+    const double* a = q.Q + i * q.qrs;
+    const double* b = Bs + 32 * j0;
+    double acc[kRowCols];
+#pragma unroll
+    for (int c = 0; c < kRowCols; ++c) acc[c] = (i == rho + j0 + c) ? 1.0 : 0.0;
+#pragma unroll 8
+    for (int k = 0; k < rho; ++k) {
+      const double x = a[k * q.qcs];
+#pragma unroll
+      for (int c = 0; c < kRowCols; ++c) acc[c] = fma(x, b[k + 32 * c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < kRowCols; ++c)
+      if (j0 + c < nc) C[i * q.qrs + (j0 + c) * q.qcs] = acc[c];
+  }
   __syncthreads();
 }
 
@@ -2054,9 +2091,11 @@ __device__ __forceinline__ void exec_op(const ChainOp& op) {
       if (nu > 0.0) {
         const double inv = 1.0 / nu;
         for (int i = tid; i < op.m; i += kCT) op.c[i] = op.a[i] * inv;
+#pragma unroll 8
         for (int64_t e = tid; e < op.k; e += kCT) op.r[e] = op.b[e] * nu;
       } else {
         for (int i = tid; i < op.m; i += kCT) op.c[i] = (i == 0) ? 1.0 : 0.0;
+#pragma unroll 8
         for (int64_t e = tid; e < op.k; e += kCT) op.r[e] = op.b[e];
       }
       __syncthreads();
@@ -2088,6 +2127,7 @@ __device__ __forceinline__ void exec_op(const ChainOp& op) {
       break;
     }
     case kOpCopy:
+#pragma unroll 8
       for (int64_t e = tid; e < op.m; e += kCT) {
         const double x = op.a[e];
         if (op.c) op.c[e] = x;

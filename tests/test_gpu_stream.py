@@ -198,6 +198,41 @@ def test_one_step_from_injected_oracle_state():
     s.close()
 
 
+def test_capped_tall_tail_core_from_oracle_state():
+    """A tail core of 640 x 32 whose local solution has rank <= 6 (modes
+    (40, 20, 6), ranks 32, split point 1): its Q is CholeskyQR2 of the first 6
+    columns plus an orthonormal completion of the other 26 (four groups of 8
+    columns).  The GPU starts from the oracle's state after the first slice:
+    the first update from the random initial state amplifies the FP32 rounding
+    of the slice contractions by the conditioning of the random interfaces
+    (1.4e-5 of max |X| element-wise on this shape, on that slice alone, with
+    every QR path), which is not what this case checks."""
+    torch = torch_cuda()
+    from paper_2606_31061_amd import TTStream
+    modes, ranks = (40, 20, 6), (32, 32, 32)
+    st = exact_tt_stream(modes, ranks, ranks, 12, 5, 6, sigma=1e-2)
+    init = st.init()
+    slices = list(st.frames(1, st.T))
+    say("capped tall tail core from the oracle state")
+    first = ttals.run_stream(slices[:1], init[0], init[1])
+    ref = ttals.run_stream(slices[1:], first.cores, first.g, keep_M=True)
+    s = TTStream(modes, ranks, init=init)
+    assert s.info()["split_point"] == 1
+    s.set_state(first.cores, first.g, t=1)
+    Ms = []
+    for X in slices[1:]:
+        s.push(to_device_slice(torch, X))
+        Ms.append(s.reconstruct())
+    s.synchronize()
+    worst = max(rel(M, i.M, np.linalg.norm(X)) for M, i, X in zip(Ms, ref.infos, slices[1:]))
+    elem = max(float(np.max(np.abs(M - i.M)) / np.max(np.abs(X))) for M, i, X in zip(Ms, ref.infos, slices[1:]))
+    assert worst <= M_TOL, worst
+    assert elem <= ELEM_TOL, elem
+    cores, _, _ = s.get_state()
+    assert max(_orth_errors(cores)) <= 1e-12
+    s.close()
+
+
 def test_nonfinite_slice_leaves_state_unchanged():
     torch = torch_cuda()
     from paper_2606_31061_amd import TTStream, binding
