@@ -65,7 +65,8 @@ std::array<int, 5> pass_key(const tt_stream* s, int pass) {
     return {1, 2, pass2b_vx(s->Pk[ks]) ? 1 : 0, s->p2b.staged ? -1 : s->p2b.waves, ntn};
   }
   if (pass == 1) return {0, 1, s->p1.vec, s->p1.waves, s->p1.ntn};
-  return {0, 2, pass2_vec(s->Pk[ks]), pass2_grouped(s->Pk[ks], (int)s->r[ks], TT_F32) ? 1 : 0, ntn};
+  return {0, 2, pass2_vec(s->Pk[ks]), pass2_grouped(s->Pk[ks], s->Jk[ks], (int)s->r[ks], TT_F32) ? pass2g_nwt(s->Pk[ks]) : 0,
+          ntn};
 }
 
 void pass_grids(const tt_stream* s, int pass, int64_t* gx, unsigned* grx) {

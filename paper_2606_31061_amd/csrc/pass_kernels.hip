@@ -507,30 +507,39 @@ __global__ void __launch_bounds__(kPass2Waves * 64) k_pass2(const T* __restrict_
 }
 
 
-// Pass 2 for FP32 slices with P % 4 == 0, P <= kPass2gMaxRows and r <= 32
-// (the grouped kernel).  Grid ceil(J/32) blocks of kPass2gWaves waves; block
-// b owns columns [32 b, 32 b + 32).  The ceil(P/8) eight-row MFMA k-steps are
-// split over the waves in contiguous runs (wave w takes steps
-// [K w / NW, K (w+1) / NW)), so the four waves of a SIMD hold about the same
-// number.  A wave issues every load of its rows at once, the interface's
-// before the slice's, in 16-row groups: two 16-byte loads per lane cover a
-// group's 32 columns (lane -> column 16h + lane/4, rows 4 (lane%4) .. +3, so
-// each column is read as one 64-byte run).  Group c is then written to two
+// Pass 2 for FP32 slices with 4 <= P <= 1280 (768 when P % 4 != 0) and
+// r <= 32 (the grouped kernel).  A block of kPass2gWaves waves owns TPB = NW / NWT
+// consecutive 32-column tiles, NWT waves per tile (NWT, a power of two, the
+// fewest waves that keep every wave within 2G eight-row k-steps: P <= 16 G NWT,
+// so small slices do not spread a few rows over many waves).  The ceil(P/8)
+// MFMA k-steps of a tile are split over its waves in contiguous runs (wave i
+// of the tile takes steps [K i / NWT, K (i+1) / NWT)), so the waves of a SIMD
+// hold about the same number.  A wave issues every load of its rows at once,
+// the interface's before the slice's, in 16-row groups: two loads per lane
+// cover a group's 32 columns (lane -> column 16h + lane/4, rows 4 (lane%4)
+// .. +3, each column read as one 64-byte run; one 16-byte load when
+// P % 4 == 0 (V4), else four 4-byte loads).  Group c is then written to two
 // 32 x 16 wave-private LDS tiles (slice and interface) and read back as MFMA
-// fragments as soon as its loads have landed, so a wave's MFMAs start on
-// its first group while the rest of its rows are still in flight; no block
-// barrier is needed before the final reduction.  Rows past P, columns past J
-// and ranks past r are zeroed at the LDS write; groups past the wave's run
-// are loaded (clamped) but not multiplied.
+// fragments as soon as its loads have landed, so a wave's MFMAs start on its
+// first group while the rest of its rows are still in flight; no block
+// barrier is needed before the final reduction, which adds each tile's waves
+// in order.  Rows past P, columns past J and ranks past r are zeroed at the
+// LDS write; groups past the wave's run are loaded (clamped) but not
+// multiplied.
 constexpr int kPass2gWaves = 16;
-constexpr int kPass2gGroups = 5;  // 16-row groups per wave: up to 10 k-steps
-constexpr int kPass2gLdp = 20;    // LDS row pitch of a 32 x 16 tile (floats)
+// 16-row groups per wave: up to 10 k-steps with 16-byte loads, 6 with 4-byte
+// loads (whose addresses take more registers)
+constexpr int kPass2gGroups = 5;
+constexpr int kPass2gGroups1 = 3;
+constexpr int kPass2gLdp = 20;  // LDS row pitch of a 32 x 16 tile (floats)
 constexpr int64_t kPass2gMaxRows = 8LL * 2 * kPass2gGroups * kPass2gWaves;
+constexpr int64_t kPass2gMaxRows1 = 8LL * 2 * kPass2gGroups1 * kPass2gWaves;
 constexpr size_t kPass2gLds =
     (size_t)kPass2gWaves * 64 * kPass2gLdp * sizeof(float) > (size_t)kPass2gWaves * 1024 * sizeof(float)
         ? (size_t)kPass2gWaves * 64 * kPass2gLdp * sizeof(float)
         : (size_t)kPass2gWaves * 1024 * sizeof(float);
 
+template <int NWT, bool V4>
 __global__ void __launch_bounds__(kPass2gWaves * 64) k_pass2g(const float* __restrict__ X, int64_t P, int64_t J, int r,
                                                               const float* __restrict__ A, double* __restrict__ Y,
                                                               int* __restrict__ flag,
@@ -545,37 +554,50 @@ __global__ void __launch_bounds__(kPass2gWaves * 64) k_pass2g(const float* __res
     J = pp.J;
     r = pp.r;
   }
-  if ((int64_t)blockIdx.x * 32 >= J) return;  // past this member's columns
-  constexpr int NW = kPass2gWaves, G = kPass2gGroups, LDP = kPass2gLdp;
+  constexpr int NW = kPass2gWaves, TPB = NW / NWT, G = V4 ? kPass2gGroups : kPass2gGroups1, LDP = kPass2gLdp;
+  if ((int64_t)blockIdx.x * TPB * 32 >= J) return;  // past this member's columns
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int g = lane >> 5, jl = lane & 31;
-  const int64_t j0 = (int64_t)blockIdx.x * 32;
+  const int64_t jb = (int64_t)blockIdx.x * TPB * 32;  // the block's first column
+  const int64_t j0 = jb + 32 * (w / NWT);               // this wave's tile
+  const int wi = w % NWT;
   const int np = (int)P;  // P <= kPass2gMaxRows
   const int K = (np + 7) >> 3;
-  const int kb = K * w / NW, nk = K * (w + 1) / NW - kb;
+  const int kb = K * wi / NWT;
+  const int nk = j0 < J ? K * (wi + 1) / NWT - kb : 0;  // a tile past J multiplies nothing
   const int rb = 8 * kb;
   const int lc = lane >> 2, lr = 4 * (lane & 3);
+  // four consecutive rows from row p of the column whose first element is
+  // base[col] (clamped into the matrix); the 4-byte loads take 32-bit
+  // element offsets from the uniform base (P J < 2^30 for this variant)
+  auto ld4 = [&](const float* base, int64_t col, int p) -> f4 {
+    if constexpr (V4) {
+      return *gptr(reinterpret_cast<const f4*>(base + col + (p < np - 4 ? p : np - 4)));
+    } else {
+      f4 v;
+      const unsigned co = (unsigned)col;
+#pragma unroll
+      for (int s = 0; s < 4; ++s) v[s] = *gptr(base + (co + (unsigned)(p + s < np - 1 ? p + s : np - 1)));
+      return v;
+    }
+  };
   f4 ar[2 * G], xr[2 * G];
 #pragma unroll
   for (int c = 0; c < G; ++c)
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      int p = rb + 16 * c + lr;
-      p = p < np - 4 ? p : np - 4;
       int a = 16 * h + lc;
       a = a < r ? a : r - 1;
-      ar[2 * c + h] = *gptr(reinterpret_cast<const f4*>(A + p + P * (int64_t)a));
+      ar[2 * c + h] = ld4(A, P * (int64_t)a, rb + 16 * c + lr);
     }
 #pragma unroll
   for (int c = 0; c < G; ++c)
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      int p = rb + 16 * c + lr;
-      p = p < np - 4 ? p : np - 4;
       int64_t jj = j0 + 16 * h + lc;
       jj = jj < J ? jj : J - 1;
-      xr[2 * c + h] = *gptr(reinterpret_cast<const f4*>(X + p + P * jj));
+      xr[2 * c + h] = ld4(X, P * jj, rb + 16 * c + lr);
     }
   // keep every load ahead of the first LDS write
   __builtin_amdgcn_sched_barrier(0);
@@ -612,18 +634,19 @@ __global__ void __launch_bounds__(kPass2gWaves * 64) k_pass2g(const float* __res
       }
     }
   }
-  // cross-wave reduction in LDS (reuses the tiles), wave order
+  // reduction in LDS (reuses the tiles): each tile adds its waves in order
   __syncthreads();
 #pragma unroll
   for (int v = 0; v < 16; ++v) lds[(w * 16 + v) * 64 + lane] = acc[v];
   __syncthreads();
   int bad = 0;
-  for (int e = threadIdx.x; e < 1024; e += NW * 64) {
+  for (int e = threadIdx.x; e < TPB * 1024; e += NW * 64) {
+    const int t = e >> 10, el = e & 1023;
     float s = 0.f;
 #pragma unroll
-    for (int ww = 0; ww < NW; ++ww) s += lds[ww * 1024 + e];
-    const int v = e / 64, ln = e % 64;
-    const int64_t jj = j0 + mfma_row(ln, v);
+    for (int q = 0; q < NWT; ++q) s += lds[(t * NWT + q) * 1024 + el];
+    const int v = el / 64, ln = el % 64;
+    const int64_t jj = jb + 32 * t + mfma_row(ln, v);
     const int a = ln & 31;
     if (jj < J && a < r) {
       Y[a + (int64_t)r * jj] = (double)s;
@@ -631,6 +654,31 @@ __global__ void __launch_bounds__(kPass2gWaves * 64) k_pass2g(const float* __res
     }
   }
   if (bad) atomicOr(flag, 1);
+}
+
+template <int NWT>
+hipError_t launch_p2g(hipStream_t st, const float* X, int64_t P, int64_t J, int r, const float* A, double* Y, int* flag,
+                      const PassLaunch* bl) {
+  constexpr int TPB = kPass2gWaves / NWT;
+  const unsigned tiles = pass2_grid(J);
+  const dim3 grid(bl ? bl->gx : (tiles + TPB - 1) / TPB, bl ? (unsigned)bl->n : 1u);
+  const PassDesc* d = bl ? bl->desc : nullptr;
+  if (P % 4 == 0)
+    hipLaunchKernelGGL((k_pass2g<NWT, true>), grid, dim3(kPass2gWaves * 64), kPass2gLds, st, X, P, J, r, A, Y, flag, d);
+  else
+    hipLaunchKernelGGL((k_pass2g<NWT, false>), grid, dim3(kPass2gWaves * 64), kPass2gLds, st, X, P, J, r, A, Y, flag,
+                       d);
+  return hipSuccess;
+}
+
+template <int NWT>
+hipError_t attr2g() {
+  hipError_t e = hipFuncSetAttribute((const void*)k_pass2g<NWT, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                     (int)kPass2gLds);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)k_pass2g<NWT, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kPass2gLds);
+  return e;
 }
 
 // ------------------------------------------------------------------ launch
@@ -763,8 +811,15 @@ void pass1_grids(const Pass1Plan& pl, int64_t P, unsigned* gx, unsigned* grx) {
 }
 
 unsigned pass2_grid(int64_t J) { return (unsigned)((J + 31) / 32); }
-bool pass2_grouped(int64_t P, int r, tt_dtype xdt) {
-  return xdt == TT_F32 && P % 4 == 0 && P >= 4 && P <= kPass2gMaxRows && r <= 32;
+bool pass2_grouped(int64_t P, int64_t J, int r, tt_dtype xdt) {
+  if (xdt != TT_F32 || P < 4 || r > 32) return false;
+  return P % 4 == 0 ? P <= kPass2gMaxRows : (P <= kPass2gMaxRows1 && P * J < (1LL << 30));
+}
+int pass2g_nwt(int64_t P) {
+  const int64_t K = (P + 7) / 8, G = P % 4 == 0 ? kPass2gGroups : kPass2gGroups1;
+  int nwt = 1;
+  while (nwt < kPass2gWaves && K > 2 * G * nwt) nwt *= 2;
+  return nwt;
 }
 int pass2_vec(int64_t P) { return P % 4 == 0 ? 4 : (P % 2 == 0 ? 2 : 1); }
 
@@ -782,11 +837,17 @@ hipError_t pass1(hipStream_t st, const void* X, tt_dtype xdt, const Pass1Plan& p
 hipError_t pass2(hipStream_t st, const void* X, tt_dtype xdt, int64_t P, int64_t J, int r, const float* A, double* Y,
                  int* flag, const PassLaunch* bl) {
   if (r < 1 || r > 64 || (bl && (bl->n < 1 || bl->n > 65535))) return hipErrorInvalidValue;
-  if (pass2_grouped(P, r, xdt)) {
-    const dim3 grid(bl ? bl->gx : pass2_grid(J), bl ? (unsigned)bl->n : 1u);
-    if (pass_launch_mask() & 1)
-      hipLaunchKernelGGL(k_pass2g, grid, dim3(kPass2gWaves * 64), kPass2gLds, st, static_cast<const float*>(X), P, J,
-                         r, A, Y, flag, bl ? bl->desc : nullptr);
+  if (pass2_grouped(P, J, r, xdt)) {
+    if (pass_launch_mask() & 1) {
+      const float* Xf = static_cast<const float*>(X);
+      switch (pass2g_nwt(P)) {
+        case 1: launch_p2g<1>(st, Xf, P, J, r, A, Y, flag, bl); break;
+        case 2: launch_p2g<2>(st, Xf, P, J, r, A, Y, flag, bl); break;
+        case 4: launch_p2g<4>(st, Xf, P, J, r, A, Y, flag, bl); break;
+        case 8: launch_p2g<8>(st, Xf, P, J, r, A, Y, flag, bl); break;
+        default: launch_p2g<16>(st, Xf, P, J, r, A, Y, flag, bl); break;
+      }
+    }
     if (hipEvent_t m = pass_mid_event()) {
       const hipError_t e = hipEventRecord(m, st);
       if (e != hipSuccess) return e;
@@ -815,8 +876,11 @@ hipError_t pass_setup() {
   TT_A2(double)
   TT_A2(__hip_bfloat16)
 #undef TT_A2
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)k_pass2g, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kPass2gLds);
+  if (e == hipSuccess) e = attr2g<1>();
+  if (e == hipSuccess) e = attr2g<2>();
+  if (e == hipSuccess) e = attr2g<4>();
+  if (e == hipSuccess) e = attr2g<8>();
+  if (e == hipSuccess) e = attr2g<16>();
   return e;
 }
 

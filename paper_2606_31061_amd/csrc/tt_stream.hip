@@ -1170,7 +1170,7 @@ tt_status tt_stream_pass_kernels(const tt_stream* s, int32_t* pass1, int32_t* pa
   const bool bf16 = s->compute == TT_BF16;
   *pass1 = bf16 ? 1 : 0;
   const int ks = s->kstar;
-  *pass2 = bf16 ? (s->p2b.staged ? 2 : 1) : (ttk::pass2_grouped(s->Pk[ks], (int)s->r[ks], TT_F32) ? 3 : 0);
+  *pass2 = bf16 ? (s->p2b.staged ? 2 : 1) : (ttk::pass2_grouped(s->Pk[ks], s->Jk[ks], (int)s->r[ks], TT_F32) ? 3 : 0);
   return TT_OK;
 }
 
