@@ -117,7 +117,10 @@ def batched_section(torch, n_streams, rounds, warmup, compute, tune):
             bytes_round += b1 + b2
 
         def run(batch_graph, solo):
-            streams = [TTStream(sp.modes, sp.ranks, init=sp.init(), compute=compute, autotune=tune) for sp in specs]
+            # batch members are planned for waves (TT_FLAG_WAVE_PLAN); the
+            # one-after-another baseline keeps the plan that is fastest alone
+            streams = [TTStream(sp.modes, sp.ranks, init=sp.init(), compute=compute, autotune=tune,
+                                wave_plan=not solo) for sp in specs]
             b = None if solo else TTBatch(streams, graph=batch_graph)
 
             def one(i):
@@ -168,6 +171,7 @@ def batched_section(torch, n_streams, rounds, warmup, compute, tune):
                     "uniform in [16, 256] at order 5) has slices of up to 4.3e9 entries (17 GB in FP32), which "
                     "64 resident streams cannot hold",
         "streams": n_streams,
+        "plan": "members with TT_FLAG_WAVE_PLAN; the one-after-another baseline with the default plan",
         "frames_per_stream": nfr,
         "frame_set_bytes": frame_bytes,
         "rounds": rounds,

@@ -120,6 +120,14 @@ typedef struct {
  * modelled side traffic (P_k + J_k) r_k is within 4x of the smallest are timed
  * with their tuned passes, and the fastest is used. */
 #define TT_FLAG_AUTOTUNE 0x8u
+/* TT_FLAG_WAVE_PLAN: plan the update for batched waves (tt_batch.h,
+ * tt_server.h): FP64 products of up to 4e5 multiply-adds run inside the
+ * one-workgroup chain segments rather than as whole-GPU launches of their own
+ * (2e5 without the flag).  In a wave every such launch is another step that
+ * all members wait for, so the wave is faster; a stream alone is slower.  The
+ * update is the same computation either way, and a stream gives the same bits
+ * alone or in a batch for a given flag. */
+#define TT_FLAG_WAVE_PLAN 0x10u
 
 /* Create a stream.  The initial cores are the paper's random initialisation
  * (Algorithm 1, first line): taken from init_cores, else i.i.d. N(0,1) from a

@@ -32,6 +32,7 @@ TT_FLAG_SYNC_PUSH = 0x1
 TT_FLAG_NO_ORTHO = 0x2
 TT_FLAG_PROFILE_OPS = 0x4
 TT_FLAG_AUTOTUNE = 0x8
+TT_FLAG_WAVE_PLAN = 0x10
 
 
 class TTError(RuntimeError):
@@ -239,12 +240,15 @@ class TTStream:
     stream: torch.cuda.Stream (default: the current stream).
     allocator: optional tt_allocator (make_allocator) for the handle's device
     memory; it must outlive the handle.
+    sync_push, profile_ops, autotune, no_ortho, wave_plan: the TT_FLAG_*
+    creation flags of tt_stream.h (wave_plan: plan the update for batched
+    waves).
     """
 
     def __init__(self, modes, ranks, init=None, *, seed: int = 0, stream=None, keep_history: bool = False,
                  history_capacity: int = 0, split_point: int = 0, sync_push: bool = False,
                  profile_ops: bool = False, compute: str = "f32", autotune: bool = False,
-                 no_ortho: bool = False, allocator: Optional[tt_allocator] = None):
+                 no_ortho: bool = False, wave_plan: bool = False, allocator: Optional[tt_allocator] = None):
         self.modes = tuple(int(v) for v in modes)
         self.ranks = tuple(int(v) for v in ranks)
         self.n = int(np.prod(self.modes))
@@ -264,7 +268,8 @@ class TTStream:
                                    flags=(TT_FLAG_SYNC_PUSH if sync_push else 0)
                                    | (TT_FLAG_PROFILE_OPS if profile_ops else 0)
                                    | (TT_FLAG_AUTOTUNE if autotune else 0)
-                                   | (TT_FLAG_NO_ORTHO if no_ortho else 0),
+                                   | (TT_FLAG_NO_ORTHO if no_ortho else 0)
+                                   | (TT_FLAG_WAVE_PLAN if wave_plan else 0),
                                    allocator=allocator)
         self._lib = load_library()
 

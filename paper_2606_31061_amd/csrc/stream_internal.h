@@ -28,6 +28,7 @@ struct Step {
 struct UpdatePlan {
   std::vector<ttk::ChainOp> ops;
   std::vector<Step> steps;
+  double wide_fma = 2.0e5;         // products from this size run as whole-GPU launches
   ttk::ChainOp* dev = nullptr;     // the ops on the device
   ttk::ChainSeg* segs = nullptr;   // segs[i]: step i's operations (device; chain steps)
   ttk::ChainOp** opptr = nullptr;  // opptr[i] = dev + i (device)

@@ -55,6 +55,7 @@ constexpr double kQrTol = 64.0 * 2.220446049250313e-16;
 // the chain workgroup takes 20-35 us for products of 0.5-0.7 M multiply-adds
 // (staging and writing them through one CU), hence these thresholds.
 constexpr double kWideFma = 2.0e5;
+constexpr double kWideFmaWave = 4.0e5;  // with TT_FLAG_WAVE_PLAN
 constexpr int64_t kWideDepth = 256;
 constexpr double kWideDeepFma = 3.0e4;
 
@@ -292,6 +293,8 @@ bool independent(const ttk::ChainOp& x, const ttk::ChainOp& y) {
 // C = A B (see ttk::ChainOp); large products become launches of their own,
 // and a large product independent of the large products planned right
 // before it joins their launch.
+double wide_fma_of(const tt_stream* s) { return (s->flags & TT_FLAG_WAVE_PLAN) ? kWideFmaWave : kWideFma; }
+
 void plan_gemm(UpdatePlan& p, int64_t M, int64_t N, int64_t K, const double* A, int64_t ars, int64_t acs,
                const double* B, int64_t brs, int64_t bcs, double* C, int64_t crs, int64_t ccs, float* C32) {
   ttk::ChainOp op;
@@ -310,7 +313,7 @@ void plan_gemm(UpdatePlan& p, int64_t M, int64_t N, int64_t K, const double* A, 
   op.ccs = ccs;
   op.c32 = C32;
   const double fma = (double)M * (double)N * (double)K;
-  if (fma >= kWideFma || (K >= kWideDepth && fma >= kWideDeepFma)) {
+  if (fma >= p.wide_fma || (K >= kWideDepth && fma >= kWideDeepFma)) {
     p.ops.push_back(op);
     const int idx = (int)p.ops.size() - 1;
     bool join = !p.steps.empty() && p.steps.back().kind == kStepWide &&
@@ -382,6 +385,7 @@ void plan_spd_inv(UpdatePlan& p, const tt_stream* s, int64_t m, const double* S,
 void build_plan_noortho(tt_stream* s, int par) {
   UpdatePlan& P = s->plan[par];
   P.ops.clear();
+  P.wide_fma = wide_fma_of(s);
   P.steps.clear();
   double* master = s->state[par];
   double* fresh = s->state[par ^ 1];
@@ -556,6 +560,7 @@ void plan_sweep(tt_stream* s, UpdatePlan& P, double* master) {
 void build_plan(tt_stream* s, int par) {
   UpdatePlan& P = s->plan[par];
   P.ops.clear();
+  P.wide_fma = wide_fma_of(s);
   P.steps.clear();
   double* master = s->state[par];
   double* fresh = s->state[par ^ 1];
@@ -642,6 +647,7 @@ void build_plan(tt_stream* s, int par) {
 void build_sweep_plan(tt_stream* s, int par) {
   UpdatePlan& P = s->sweep0[par];
   P.ops.clear();
+  P.wide_fma = wide_fma_of(s);
   P.steps.clear();
   plan_sweep(s, P, s->state[par]);
 }
@@ -746,7 +752,7 @@ tt_status tt_stream_create(const tt_stream_config* cfg, tt_stream** out) {
         return fail(TT_ERR_RANK, "infeasible TT-ranks: need r_k <= r_{k-1} I_k and r_{k-1} <= I_k r_k");
   }
   if (cfg->compute != TT_F32 && cfg->compute != TT_BF16) return fail(TT_ERR_INVALID_ARG, "compute must be F32/BF16");
-  if (cfg->flags & ~(TT_FLAG_SYNC_PUSH | TT_FLAG_PROFILE_OPS | TT_FLAG_AUTOTUNE | TT_FLAG_NO_ORTHO))
+  if (cfg->flags & ~(TT_FLAG_SYNC_PUSH | TT_FLAG_PROFILE_OPS | TT_FLAG_AUTOTUNE | TT_FLAG_NO_ORTHO | TT_FLAG_WAVE_PLAN))
     return fail(TT_ERR_UNSUPPORTED, "unsupported flags");
   if (cfg->split_point < 0 || cfg->split_point > m) return fail(TT_ERR_INVALID_ARG, "split_point out of range");
 

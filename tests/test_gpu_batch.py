@@ -205,3 +205,40 @@ def test_graph_replay_matches_eager_batch():
             _ = (dev[0][t] * 2.0).sum().item()
         be.close()
         bg.close()
+
+
+def test_wave_plan_streams_are_bitwise_equal_alone_and_batched():
+    """TT_FLAG_WAVE_PLAN moves products of 2e5..4e5 multiply-adds from
+    whole-GPU launches into the chain segments (config 3 has such a product,
+    so the chain runs more operations); a stream with the flag gives the
+    same bits alone and in a batch, and follows the oracle."""
+    torch = torch_cuda()
+    from paper_2606_31061_amd import TTBatch, TTStream
+    st = config_c3(T=3)
+    init = st.init()
+    frames = list(st.frames(1, 3))
+    xs = [to_device_slice(torch, X) for X in frames]
+    say("batch: config-3 streams with the wave plan")
+    counts = []
+    for wave in (False, True):
+        p = TTStream(st.modes, st.ranks, init=init, profile_ops=True, wave_plan=wave)
+        p.push(xs[0])
+        p.synchronize()
+        counts.append(len(p.op_profile()))
+        p.close()
+    assert counts[1] > counts[0], counts
+    a = TTStream(st.modes, st.ranks, init=init, wave_plan=True)
+    b1 = TTStream(st.modes, st.ranks, init=init, wave_plan=True)
+    b2 = TTStream(st.modes, st.ranks, init=init, wave_plan=True)
+    batch = TTBatch([b1, b2])
+    for t in range(3):
+        a.push(xs[t])
+        batch.push([xs[t], xs[(t + 1) % 3]])
+    assert batch.synchronize() == [0, 0]
+    a.synchronize()
+    assert _states_equal(a, b1)
+    ref = ttals.run_stream(frames, init[0], init[1], keep_M=True)
+    assert rel(a.reconstruct(), ref.infos[-1].M, np.linalg.norm(frames[-1])) <= M_TOL
+    batch.close()
+    for s in (a, b1, b2):
+        s.close()
