@@ -5,7 +5,9 @@
 // the two slice passes into three phases; inside a phase a member alternates
 // chain segments and whole-GPU products, and slot w of every member's phase
 // runs in one launch (chain segment w on one workgroup per member, then
-// product w of the members that have one).  Each pass runs as one launch per
+// product w of the members that have one).  A member with fewer products than
+// the longest may start its phase a few slots late (align_members), so that
+// the members' long chain segments share launches.  Each pass runs as one launch per
 // kernel template shape over the members of that shape.  Per wave, the
 // members' operation-list pointers, slices and pass sizes go to the device in
 // one descriptor upload.  Every member computes exactly what it computes
@@ -106,6 +108,99 @@ PassDesc pass_desc(const tt_stream* s, int pass, const void* x) {
   return d;
 }
 
+// A rough device time (us) of one chain operation on its workgroup, from its
+// shape: only the ordering of the heavy operations (tall QRs) matters to the
+// alignment below.
+double op_cost_us(const ChainOp& o) {
+  const double m = (double)o.m, n = (double)o.n, k = (double)o.k;
+  switch (o.type) {
+    case kOpQr: {
+      if (o.rho == 1) return 3.0 + 0.012 * m;
+      if (m <= 512) return 15.0 + 0.032 * m;
+      const bool capped = o.rho >= 2 && o.rho < o.n && !o.r;
+      return (capped ? 2.0 : 1.0) * (10.0 + 0.042 * m * (n > 16 ? 1.0 : 0.75));
+    }
+    case kOpGemm: {
+      double c = m * n * k / 3e4;
+      if (m * n <= 1024) c = std::max(c, 0.035 * k);
+      c = std::max(c, 0.0065 * m);
+      return 1.5 + c;
+    }
+    case kOpNormG: return 2.0 + 0.00027 * k;
+    case kOpCopy: return 1.0 + 0.0001 * m;
+    case kOpCommit: return 1.0 + 0.0001 * k;
+    default: return 5.0;
+  }
+}
+
+// Members of a wave whose phase has fewer whole-GPU products than the
+// longest start it later (empty chain segments first), by an offset chosen
+// so that the members' heavy chain segments share launches: each launch
+// lasts as long as its slowest segment, so the sum over launches of the
+// slowest estimated segment is reduced by coordinate descent from the
+// left-aligned start.  The members' own operations and their order are
+// unchanged.
+void align_members(Wave& w) {
+  const int n = (int)w.members.size();
+  for (int ph = 0; ph < 3; ++ph) {
+    size_t W = 0;
+    for (int i = 0; i < n; ++i) W = std::max(W, w.phases[i][ph].wides.size());
+    if (W == 0) continue;
+    const int S = (int)W + 1;
+    std::vector<std::vector<double>> c(n);
+    std::vector<int> range(n), d(n, 0);
+    for (int i = 0; i < n; ++i) {
+      const auto& mp = w.phases[i][ph];
+      const auto& ops = w.members[i]->plan[0].ops;
+      for (const auto& sg : mp.segs) {
+        double t = 0.0;
+        for (int q = sg.first; q < sg.first + sg.second; ++q) t += op_cost_us(ops[q]);
+        c[i].push_back(t);
+      }
+      range[i] = (int)(W - mp.wides.size());
+    }
+    auto total = [&]() {
+      double sum = 0.0;
+      for (int sl = 0; sl < S; ++sl) {
+        double mx = 0.0;
+        for (int i = 0; i < n; ++i) {
+          const int j = sl - d[i];
+          if (j >= 0 && j < (int)c[i].size()) mx = std::max(mx, c[i][j]);
+        }
+        sum += mx;
+      }
+      return sum;
+    };
+    double best = total();
+    for (int pass = 0; pass < 4; ++pass) {
+      bool moved = false;
+      for (int i = 0; i < n; ++i) {
+        if (range[i] == 0) continue;
+        const int d0 = d[i];
+        int bd = d0;
+        for (int dd = 0; dd <= range[i]; ++dd) {
+          if (dd == d0) continue;
+          d[i] = dd;
+          const double t = total();
+          if (t < best - 1e-9) {
+            best = t;
+            bd = dd;
+          }
+        }
+        d[i] = bd;
+        moved = moved || bd != d0;
+      }
+      if (!moved) break;
+    }
+    for (int i = 0; i < n; ++i) {
+      if (d[i] == 0) continue;
+      auto& mp = w.phases[i][ph];
+      mp.segs.insert(mp.segs.begin(), d[i], std::pair<int, int>{0, 0});
+      mp.wides.insert(mp.wides.begin(), d[i], -1);
+    }
+  }
+}
+
 // The launch sequence of a wave (its shape depends only on the members).
 void wave_build(Wave& w) {
   const int n = (int)w.members.size();
@@ -132,6 +227,7 @@ void wave_build(Wave& w) {
       }
     }
   }
+  align_members(w);
   w.launches.clear();
   size_t off = 0;
   auto add = [&](WaveLaunch&& L, size_t bytes) {
@@ -163,7 +259,7 @@ void wave_build(Wave& w) {
         L.slot = (int)sl;
         for (int i = 0; i < n; ++i) {
           const auto& mp = w.phases[i][ph];
-          if (sl < mp.wides.size()) {
+          if (sl < mp.wides.size() && mp.wides[sl] >= 0) {
             L.members.push_back(i);
             const ChainOp& o = w.members[i]->plan[0].ops[mp.wides[sl]];
             L.gx = std::max(L.gx, gemm64_blocks(o.m, o.n, o.k));
