@@ -117,8 +117,8 @@ double op_cost_us(const ChainOp& o) {
     case kOpQr: {
       if (o.rho == 1) return 3.0 + 0.012 * m;
       if (m <= 512) return 15.0 + 0.032 * m;
-      const bool capped = o.rho >= 2 && o.rho < o.n && !o.r;
-      return (capped ? 2.0 : 1.0) * (10.0 + 0.042 * m * (n > 16 ? 1.0 : 0.75));
+      const bool capped = o.rho >= 2 && o.rho < o.n && !o.r;  // plus a one-pass completion
+      return (capped ? 1.15 : 1.0) * (10.0 + 0.042 * m * (n > 16 ? 1.0 : 0.75));
     }
     case kOpGemm: {
       double c = m * n * k / 3e4;

@@ -2004,6 +2004,79 @@ __device__ __forceinline__ void capped_completion(const Qr& q) {
   __syncthreads();
 }
 
+// The completion of a tall QR capped at rho < n in one pass, when it is well
+// conditioned: with W = Q_rho(rho..n-1, :) (nc x rho) the completion
+// C = E - Q_rho W^T has the Gram matrix C^T C = I - W W^T exactly (Q_rho
+// orthonormal), so its Cholesky factor R (nc x nc, one wave, every pivot
+// above 1/4, i.e. no column of C shorter than 1/2) orthonormalises it without
+// reading C: Q_c = C R^-1 = E R^-1 - Q_rho (W^T R^-1).  Row i of E R^-1 is row
+// i - rho of R^-1 for rho <= i < n and zero elsewhere, so the row-blocked loop
+// of capped_completion starts from it and adds Q_rho times B = -W^T R^-1.
+// Returns false, with nothing written, when a pivot is 1/4 or less.
+__device__ __forceinline__ bool capped_completion_closed(const Qr& q) {
+  const int tid = tix();
+  const int m = q.m, n = q.n, rho = q.rho;
+  const int nc = n - rho;
+  double* Wm = s_lds + kLdsMs;    // Wm[jc + 32 k] = W(jc, k)
+  double* G = s_lds + kLdsW;      // I - W W^T, identity beyond nc
+  double* R = s_lds + kLdsR1;
+  double* Ri = s_lds + kLdsRi;    // R^-1, leading dimension 33
+  double* Bs = s_lds + kLdsPart;  // Bs[k + 32 jc] = B(k, jc)
+  int* flag = reinterpret_cast<int*>(s_lds + kLdsFlag);
+  {
+    const int jc = tid & 31, k = tid >> 5;
+    const bool ok = jc < nc && k < rho;
+    const double v = q.Q[ok ? (rho + jc) * q.qrs + k * q.qcs : 0];
+    Wm[jc + 32 * k] = ok ? v : 0.0;
+  }
+  __syncthreads();
+  {
+    const int i = tid & 31, j = tid >> 5;
+    double v = (i == j) ? 1.0 : 0.0;
+    if (i < nc && j < nc)
+      for (int k = 0; k < rho; ++k) v = fma(-Wm[i + 32 * k], Wm[j + 32 * k], v);
+    G[i + 32 * j] = v;
+  }
+  __syncthreads();
+  if (tid < 64) {
+    const bool ok = chol_inv32<2>(G, R, Ri, s_lds + kLdsRow, 0.25, nc);
+    if (tid == 0) flag[0] = ok ? 1 : 0;
+  }
+  __syncthreads();
+  if (!flag[0]) return false;
+  {
+    const int k = tid & 31, jc = tid >> 5;
+    double v = 0.0;
+    if (k < rho && jc < nc)
+      for (int l = 0; l <= jc; ++l) v = fma(-Wm[l + 32 * k], Ri[l + 33 * jc], v);
+    Bs[k + 32 * jc] = v;
+  }
+  __syncthreads();
+  double* C = q.Q + (int64_t)rho * q.qcs;
+  const int ng = (nc + kRowCols - 1) / kRowCols;
+  for (int t = tid; t < m * ng; t += kCT) {
+    int i;
+    const int j0 = small_div(t, m, i) * kRowCols;
+    const double* a = q.Q + i * q.qrs;
+    const double* b = Bs + 32 * j0;
+    const int e = i - rho;  // row of R^-1 that E contributes, if any
+    double acc[kRowCols];
+#pragma unroll
+    for (int c = 0; c < kRowCols; ++c) acc[c] = (e >= 0 && e < nc && j0 + c < nc) ? Ri[e + 33 * (j0 + c)] : 0.0;
+#pragma unroll 8
+    for (int k = 0; k < rho; ++k) {
+      const double x = a[k * q.qcs];
+#pragma unroll
+      for (int c = 0; c < kRowCols; ++c) acc[c] = fma(x, b[k + 32 * c], acc[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < kRowCols; ++c)
+      if (j0 + c < nc) C[i * q.qrs + (j0 + c) * q.qcs] = acc[c];
+  }
+  __syncthreads();
+  return true;
+}
+
 __device__ __forceinline__ void wg_qr(const Qr& q) {
   const int m = q.m, n = q.n;
   if (q.rho == 1 && !q.R && m <= kRank1Rows) {
@@ -2035,6 +2108,7 @@ __device__ __forceinline__ void wg_qr(const Qr& q) {
           a.n = q.rho;
           a.R = nullptr;
         } else if (capped) {
+          if (capped_completion_closed(q)) break;
           capped_completion(q);
           a.n = n - q.rho;
           a.rho = a.n;
