@@ -243,8 +243,8 @@ tt_status tt_stream_pass_profile(tt_stream* s, float* ms);
  * 1 for k_pass2b (BF16 MFMA, slice read straight into registers), 2 for
  * k_pass2s (BF16 MFMA, slice staged through LDS) or 3 for k_pass2g (FP32
  * MFMA, whole-slab loads in 16-row groups; FP32 slices with 4 <= P <= 1280
- * (768 when P % 4 != 0) and r <= 32 at the split point, where slices of the
- * other dtypes use k_pass2).  Errors: INVALID_ARG (null). */
+ * and r <= 32 at the split point (P J < 2^30 when P % 4 != 0), where slices
+ * of the other dtypes use k_pass2).  Errors: INVALID_ARG (null). */
 tt_status tt_stream_pass_kernels(const tt_stream* s, int32_t* pass1, int32_t* pass2);
 
 /* Average device time per launch, in microseconds, of the handle's slice-pass

@@ -507,11 +507,11 @@ __global__ void __launch_bounds__(kPass2Waves * 64) k_pass2(const T* __restrict_
 }
 
 
-// Pass 2 for FP32 slices with 4 <= P <= 1280 (768 when P % 4 != 0) and
-// r <= 32 (the grouped kernel).  A block of kPass2gWaves waves owns TPB = NW / NWT
+// Pass 2 for FP32 slices with 4 <= P <= 1280 and r <= 32 (the grouped
+// kernel).  A block of kPass2gWaves waves owns TPB = NW / NWT
 // consecutive 32-column tiles, NWT waves per tile (NWT, a power of two, the
-// fewest waves that keep every wave within 2G eight-row k-steps: P <= 16 G NWT,
-// so small slices do not spread a few rows over many waves).  The ceil(P/8)
+// fewest waves that keep every wave within 2G = 10 eight-row k-steps:
+// P <= 80 NWT, so small slices do not spread a few rows over many waves).  The ceil(P/8)
 // MFMA k-steps of a tile are split over its waves in contiguous runs (wave i
 // of the tile takes steps [K i / NWT, K (i+1) / NWT)), so the waves of a SIMD
 // hold about the same number.  A wave issues every load of its rows at once,
@@ -527,13 +527,9 @@ __global__ void __launch_bounds__(kPass2Waves * 64) k_pass2(const T* __restrict_
 // LDS write; groups past the wave's run are loaded (clamped) but not
 // multiplied.
 constexpr int kPass2gWaves = 16;
-// 16-row groups per wave: up to 10 k-steps with 16-byte loads, 6 with 4-byte
-// loads (whose addresses take more registers)
-constexpr int kPass2gGroups = 5;
-constexpr int kPass2gGroups1 = 3;
-constexpr int kPass2gLdp = 20;  // LDS row pitch of a 32 x 16 tile (floats)
+constexpr int kPass2gGroups = 5;  // 16-row groups per wave: up to 10 k-steps
+constexpr int kPass2gLdp = 20;    // LDS row pitch of a 32 x 16 tile (floats)
 constexpr int64_t kPass2gMaxRows = 8LL * 2 * kPass2gGroups * kPass2gWaves;
-constexpr int64_t kPass2gMaxRows1 = 8LL * 2 * kPass2gGroups1 * kPass2gWaves;
 constexpr size_t kPass2gLds =
     (size_t)kPass2gWaves * 64 * kPass2gLdp * sizeof(float) > (size_t)kPass2gWaves * 1024 * sizeof(float)
         ? (size_t)kPass2gWaves * 64 * kPass2gLdp * sizeof(float)
@@ -554,7 +550,7 @@ __global__ void __launch_bounds__(kPass2gWaves * 64) k_pass2g(const float* __res
     J = pp.J;
     r = pp.r;
   }
-  constexpr int NW = kPass2gWaves, TPB = NW / NWT, G = V4 ? kPass2gGroups : kPass2gGroups1, LDP = kPass2gLdp;
+  constexpr int NW = kPass2gWaves, TPB = NW / NWT, G = kPass2gGroups, LDP = kPass2gLdp;
   if ((int64_t)blockIdx.x * TPB * 32 >= J) return;  // past this member's columns
   extern __shared__ float lds[];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -813,12 +809,12 @@ void pass1_grids(const Pass1Plan& pl, int64_t P, unsigned* gx, unsigned* grx) {
 unsigned pass2_grid(int64_t J) { return (unsigned)((J + 31) / 32); }
 bool pass2_grouped(int64_t P, int64_t J, int r, tt_dtype xdt) {
   if (xdt != TT_F32 || P < 4 || r > 32) return false;
-  return P % 4 == 0 ? P <= kPass2gMaxRows : (P <= kPass2gMaxRows1 && P * J < (1LL << 30));
+  return P <= kPass2gMaxRows && (P % 4 == 0 || P * J < (1LL << 30));
 }
 int pass2g_nwt(int64_t P) {
-  const int64_t K = (P + 7) / 8, G = P % 4 == 0 ? kPass2gGroups : kPass2gGroups1;
+  const int64_t K = (P + 7) / 8;
   int nwt = 1;
-  while (nwt < kPass2gWaves && K > 2 * G * nwt) nwt *= 2;
+  while (nwt < kPass2gWaves && K > 2LL * kPass2gGroups * nwt) nwt *= 2;
   return nwt;
 }
 int pass2_vec(int64_t P) { return P % 4 == 0 ? 4 : (P % 2 == 0 ? 2 : 1); }

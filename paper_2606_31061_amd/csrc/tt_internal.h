@@ -175,8 +175,8 @@ unsigned pass2_grid(int64_t J);
 // Template shape of pass 2 for these sizes (members of one launch share it).
 int pass2_vec(int64_t P);
 // Whether pass 2 runs the grouped FP32 kernel k_pass2g for these sizes (FP32
-// slices, 4 <= P <= 1280, r <= 32; when P % 4 != 0 also P <= 768 and
-// P J < 2^30), and its waves per column tile (1, 2, 4, 8 or 16, from P); both are part of the template shape too.  Its batched grid
+// slices, 4 <= P <= 1280, r <= 32; when P % 4 != 0 also P J < 2^30), and
+// its waves per column tile (1, 2, 4, 8 or 16, from P); both are part of the template shape too.  Its batched grid
 // is pass2_grid(J) like k_pass2's (blocks past a member's tiles return).
 bool pass2_grouped(int64_t P, int64_t J, int r, tt_dtype xdt);
 int pass2g_nwt(int64_t P);

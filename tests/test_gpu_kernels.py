@@ -16,17 +16,16 @@ def _rng(s):
     return np.random.Generator(np.random.PCG64(s))
 
 
-# The FP32 pass 2 runs k_pass2g where 4 <= P <= 1280 (768 when P % 4 != 0)
-# and r <= 32, with 1, 2, 4, 8 or 16 waves per column tile as P grows past
-# 80, 160, 320 and 640 rows (48, 96, 192, 384 with the 4-byte loads used when
-# P % 4 != 0; 16-byte loads otherwise).  Its edges here: P % 8 == 4, P = 1280
-# with ten k-steps per wave, P = 4, odd P, ranks and columns that leave part
-# of a tile or of a block's tiles empty.  k_pass2 runs elsewhere (P > 1280,
-# 801 odd, r > 32, P < 4).
+# The FP32 pass 2 runs k_pass2g where 4 <= P <= 1280 and r <= 32, with 1, 2,
+# 4, 8 or 16 waves per column tile as P grows past 80, 160, 320 and 640 rows,
+# 16-byte loads where P % 4 == 0 and 4-byte loads otherwise.  Its edges here:
+# P % 8 == 4, P = 1280 with ten k-steps per wave, P = 4, odd P up to 1279,
+# ranks and columns that leave part of a tile or of a block's tiles empty.
+# k_pass2 runs elsewhere (P > 1280, r > 32, P < 4).
 CASES = [(32, 32, 4), (240, 960, 16), (1080, 5760, 32), (100, 77, 5), (33, 1, 8), (200, 300, 48),
          (8, 777, 8), (4, 3, 1), (90, 70, 16), (6, 50, 3), (1090, 400, 40), (1084, 100, 32), (1280, 64, 32),
          (1284, 40, 7), (12, 33, 31), (600, 200, 20), (601, 300, 32), (161, 1000, 32), (2, 10, 3),
-         (801, 50, 16), (97, 2000, 32)]
+         (801, 50, 16), (97, 2000, 32), (1279, 70, 32), (1282, 40, 8)]
 
 
 def _ref_round(X, dt):

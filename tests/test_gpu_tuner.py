@@ -120,8 +120,8 @@ def test_tuner_picks_the_split_point_per_shape():
 @pytest.mark.parametrize("autotune", [False, True])
 def test_pass_kernel_names_follow_the_plan(compute, autotune):
     """The library names the contraction kernels its passes launch: FP32
-    streams k_pass1 and k_pass2g (FP32 slices, 4 <= P <= 1280 (768 for
-    P % 4 != 0), r <= 32) or k_pass2; BF16 streams k_pass1b and, for pass 2, the
+    streams k_pass1 and k_pass2g (FP32 slices, 4 <= P <= 1280, r <= 32) or
+    k_pass2; BF16 streams k_pass1b and, for pass 2, the
     LDS-staged k_pass2s by default where P % 8 == 0 and P <= 2304 (the tuner
     may pick either BF16 kernel)."""
     torch_cuda()
@@ -135,8 +135,7 @@ def test_pass_kernel_names_follow_the_plan(compute, autotune):
     P = int(np.prod(modes[:sp]))
     if compute == "f32":
         # every rank here is 4: the grouped pass 2 applies where 4 <= P <= 1280
-        # (768 when P % 4 != 0)
-        assert (k1, k2) == ("k_pass1", "k_pass2g" if 4 <= P <= (1280 if P % 4 == 0 else 768) else "k_pass2")
+        assert (k1, k2) == ("k_pass1", "k_pass2g" if 4 <= P <= 1280 else "k_pass2")
     else:
         assert k1 == "k_pass1b"
         if autotune:
