@@ -123,8 +123,10 @@ typedef struct {
 /* TT_FLAG_WAVE_PLAN: plan the update for batched waves (tt_batch.h,
  * tt_server.h): FP64 products of up to 4e5 multiply-adds run inside the
  * one-workgroup chain segments rather than as whole-GPU launches of their own
- * (2e5 without the flag).  In a wave every such launch is another step that
- * all members wait for, so the wave is faster; a stream alone is slower.  The
+ * (2e5 without the flag), and whole-GPU products of at least 4e6 compute
+ * four outputs per thread.  In a wave every whole-GPU launch is another step
+ * that all members wait for, and the members' large products run at once,
+ * so the wave is faster; a stream alone is slower.  The
  * update is the same computation either way, and a stream gives the same bits
  * alone or in a batch for a given flag. */
 #define TT_FLAG_WAVE_PLAN 0x10u

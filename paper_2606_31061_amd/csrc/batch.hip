@@ -262,7 +262,7 @@ void wave_build(Wave& w) {
           if (sl < mp.wides.size() && mp.wides[sl] >= 0) {
             L.members.push_back(i);
             const ChainOp& o = w.members[i]->plan[0].ops[mp.wides[sl]];
-            L.gx = std::max(L.gx, gemm64_blocks(o.m, o.n, o.k));
+            L.gx = std::max(L.gx, gemm64_blocks(o.m, o.n, o.k, o.ars, o.acs, o.brs, o.bcs, o.rho == kWideJb4));
           }
         }
         const size_t k = L.members.size();

@@ -39,7 +39,8 @@ constexpr int kChainThreads = 1024;
 // kernel of chain_exec.hip.  Field use by type:
 //   kOpGemm   C(i,j) = sum_k A(i,k) B(k,j): m = rows, n = cols, k = depth;
 //             a/ars/acs, b/brs/bcs, c/crs/ccs element strides; c may be null
-//             when c32 (same strides) receives an FP32 copy.
+//             when c32 (same strides) receives an FP32 copy; rho = kWideJb4
+//             (below) marks a whole-GPU product for four outputs per thread.
 //   kOpQr     thin QR of the m x n matrix a (strides ars, acs) into Q = c
 //             (strides crs, ccs) and, if r != null, R (n x n column-major);
 //             aux holds m*n doubles; rho = cap on proper reflectors; tol = rank
@@ -104,7 +105,12 @@ hipError_t gemm64(hipStream_t st, int64_t M, int64_t N, int64_t K,
 // differ) over the whole GPU, grid (gx, nops); gx must cover the largest
 // (gemm64_blocks).  Each product's split of the depth depends on its own shape
 // only, so a product computes the same bits in any batch.
-int64_t gemm64_blocks(int64_t M, int64_t N, int64_t K);
+// A whole-GPU product whose ChainOp has rho == kWideJb4 computes four
+// consecutive output columns per thread where its layout allows (plans for
+// batched waves mark their large products so); the result is the same bits.
+constexpr int32_t kWideJb4 = 4;
+int64_t gemm64_blocks(int64_t M, int64_t N, int64_t K, int64_t ars, int64_t acs, int64_t brs, int64_t bcs,
+                      bool jb4);
 hipError_t gemm64_ops(hipStream_t st, const ChainOp* const* ops_dev, int nops, int64_t gx);
 
 // Element conversion FP64 -> out dtype (F64/F32).

@@ -56,6 +56,7 @@ constexpr double kQrTol = 64.0 * 2.220446049250313e-16;
 // (staging and writing them through one CU), hence these thresholds.
 constexpr double kWideFma = 2.0e5;
 constexpr double kWideFmaWave = 4.0e5;  // with TT_FLAG_WAVE_PLAN
+constexpr double kWideJb4Fma = 4.0e6;   // with TT_FLAG_WAVE_PLAN: blocked whole-GPU products from this size
 constexpr int64_t kWideDepth = 256;
 constexpr double kWideDeepFma = 3.0e4;
 
@@ -314,6 +315,8 @@ void plan_gemm(UpdatePlan& p, int64_t M, int64_t N, int64_t K, const double* A, 
   op.c32 = C32;
   const double fma = (double)M * (double)N * (double)K;
   if (fma >= p.wide_fma || (K >= kWideDepth && fma >= kWideDeepFma)) {
+    // plans for batched waves: large products take four outputs per thread
+    if (p.wide_fma > kWideFma && fma >= kWideJb4Fma) op.rho = ttk::kWideJb4;
     p.ops.push_back(op);
     const int idx = (int)p.ops.size() - 1;
     bool join = !p.steps.empty() && p.steps.back().kind == kStepWide &&
@@ -668,7 +671,7 @@ tt_status run_steps(hipStream_t st, const tt_stream* s, const UpdatePlan& P, con
         int64_t gx = 0;
         for (int q = step.first; q < step.first + step.count; ++q) {
           const ttk::ChainOp& o = P.ops[q];
-          gx = std::max(gx, ttk::gemm64_blocks(o.m, o.n, o.k));
+          gx = std::max(gx, ttk::gemm64_blocks(o.m, o.n, o.k, o.ars, o.acs, o.brs, o.bcs, o.rho == ttk::kWideJb4));
         }
         TT_HIP(ttk::gemm64_ops(st, P.opptr + step.first, step.count, gx));
         break;
