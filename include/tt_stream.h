@@ -127,8 +127,8 @@ typedef struct {
  * four outputs per thread.  In a wave every whole-GPU launch is another step
  * that all members wait for, and the members' large products run at once,
  * so the wave is faster; a stream alone is slower.  The
- * update is the same computation either way, and a stream gives the same bits
- * alone or in a batch for a given flag. */
+ * update is the same up to rounding either way, and a stream gives the same
+ * bits alone or in a batch for a given flag. */
 #define TT_FLAG_WAVE_PLAN 0x10u
 
 /* Create a stream.  The initial cores are the paper's random initialisation
