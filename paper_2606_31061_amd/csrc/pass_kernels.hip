@@ -653,8 +653,8 @@ __global__ void __launch_bounds__(kPass2gWaves * 64) k_pass2g(const float* __res
 }
 
 template <int NWT>
-hipError_t launch_p2g(hipStream_t st, const float* X, int64_t P, int64_t J, int r, const float* A, double* Y, int* flag,
-                      const PassLaunch* bl) {
+void launch_p2g(hipStream_t st, const float* X, int64_t P, int64_t J, int r, const float* A, double* Y, int* flag,
+                const PassLaunch* bl) {
   constexpr int TPB = kPass2gWaves / NWT;
   const unsigned tiles = pass2_grid(J);
   const dim3 grid(bl ? bl->gx : (tiles + TPB - 1) / TPB, bl ? (unsigned)bl->n : 1u);
@@ -664,7 +664,6 @@ hipError_t launch_p2g(hipStream_t st, const float* X, int64_t P, int64_t J, int 
   else
     hipLaunchKernelGGL((k_pass2g<NWT, false>), grid, dim3(kPass2gWaves * 64), kPass2gLds, st, X, P, J, r, A, Y, flag,
                        d);
-  return hipSuccess;
 }
 
 template <int NWT>
