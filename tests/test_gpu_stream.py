@@ -29,8 +29,10 @@ def _compare_stream(modes, ranks, init, slices, **kw):
     Ms, s = run_gpu_stream(torch, modes, ranks, init, slices, **kw)
     ref = ttals.run_stream(slices, init[0], init[1], keep_M=True)
     E_gpu = np.array([np.linalg.norm(np.asarray(X, np.float64) - M) for X, M in zip(slices, Ms)])
-    worst = max(rel(M, i.M, np.linalg.norm(X)) for M, i, X in zip(Ms, ref.infos, slices))
-    elem = max(float(np.max(np.abs(M - i.M)) / np.max(np.abs(X))) for M, i, X in zip(Ms, ref.infos, slices))
+    # an all-zero slice is measured in absolute terms (its projection must vanish on both sides)
+    worst = max(rel(M, i.M, np.linalg.norm(X) or 1.0) for M, i, X in zip(Ms, ref.infos, slices))
+    elem = max(float(np.max(np.abs(M - i.M)) / (np.max(np.abs(X)) or 1.0))
+               for M, i, X in zip(Ms, ref.infos, slices))
     assert elem <= ELEM_TOL, elem
     re_gpu = float(np.sqrt(np.sum(E_gpu ** 2) / np.sum(ref.Xnorm ** 2)))
     return s, ref, worst, re_gpu, E_gpu
