@@ -762,74 +762,125 @@ __device__ __forceinline__ double rsqrt_pos(double d) {
 }
 
 // Cholesky factor of the 32 x 32 symmetric matrix W (LDS, column-major) and
-// its inverse, by one wave.  Lanes 0..31 hold column c of W and turn it into
-// column c of R (W = R^T R, R upper triangular); lanes 32..63 hold column c of
-// X, which starts as the identity and receives the same elimination steps, so
-// that it ends as R^-T.  Step j scales row j by 1/sqrt(pivot) and removes
-// R(j,:)^T R(j,:) from the rows below.  The steps go in blocks of four: inside
-// a block the few entries needed come from single lanes, and the rows below
-// receive the block's four updates at once, the entries of row i read from
-// lane i into scalar registers (v_readlane), so no step waits on memory
-// (rowbuf is not used; broadcasting the rows through it was slower).  Only
-// pivots of the first
-// n columns are tested against thr2.  Writes R (zeros below the diagonal,
-// leading dimension 32) and R^-1 (leading dimension 33); R may alias W.
-// NEWTON = 1 leaves the pivots' square roots good to about 1e-10 relative,
-// which suffices when a second CholeskyQR pass corrects the factor: R and
-// R^-1 are exact inverses of each other either way.
+// its inverse, by four waves (one per SIMD); every thread of the workgroup
+// calls it, passes the same barriers and receives the same status.  Wave w
+// (w < 4) owns rows 8w .. 8w+7: lane c < 32 holds their entries in column c
+// of W, turned into column c of R (W = R^T R, R upper triangular); lane
+// 32 + c holds them in column c of X, which starts as the identity and
+// receives the same elimination steps, so that it ends as R^-T.  Step j
+// scales row j by 1/sqrt(pivot) and removes R(j,:)^T R(j,:) from the rows
+// below.  The steps go in blocks of four rows inside one wave: the few
+// entries a step needs come from single lanes (v_readlane), and that wave
+// also updates its own rows below the block.  It then publishes the block's
+// rows through LDS, by lane and transposed (the multipliers of row i,
+// R(jb..jb+3, i), in one place), and after a barrier the waves that own rows
+// further down apply the block's four updates to them.  The published rows
+// alternate between two buffers (the Householder scratch, idle here), so
+// one barrier per block suffices.  Every entry receives the same fused
+// multiply-adds in the same order as in a one-wave elimination.  Only
+// pivots of the first n columns are tested against thr2.  Writes R (zeros
+// below the diagonal, leading dimension 32) and R^-1 (leading dimension 33);
+// R may alias W.  NB = 8 factors the leading 8 columns only (beyond n <= 8,
+// W is the identity, whose columns no step changes): that stays in wave 0
+// and needs no barrier before the last.  NEWTON = 1 leaves the pivots'
+// square roots good to about 1e-10 relative, which suffices when a second
+// CholeskyQR pass corrects the factor: R and R^-1 are exact inverses of each
+// other either way.
 template <int NB, int NEWTON>
-__device__ __forceinline__ bool chol_inv(const double* W, double* R, double* Ri, double* rowbuf, double thr2,
-                                         int n) {
-  const int lane = tix() & 63;
+__device__ __forceinline__ bool chol_inv(const double* W, double* R, double* Ri, double thr2, int n) {
+  constexpr int RW = 8;  // rows per wave
+  const int tid = tix(), lane = tid & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
   int c = lane & 31;
   // opaque to the optimiser: keeps the identity set-up below from being
-  // hoisted out of the operation loop (32 live values would spill)
+  // hoisted out of the operation loop
   asm volatile("" : "+v"(c));
   const bool xh = lane >= 32;
-  double v[32];
-#pragma unroll
-  for (int i = 0; i < 32; ++i) {
-    const double w = W[i + 32 * c];
-    v[i] = xh ? (i == c ? 1.0 : 0.0) : w;
-  }
+  int* okw = reinterpret_cast<int*>(s_lds + kLdsFlag) + 4;  // one status per wave
+  double v[RW];
   bool ok = true;
+  if (w < 4) {
+#pragma unroll
+    for (int r = 0; r < RW; ++r) {
+      const int i = RW * w + r;
+      double x = W[i + 32 * c];
+      asm volatile("" : "+v"(x));  // loaded by every lane: no branch around the load
+      v[r] = xh ? (i == c ? 1.0 : 0.0) : x;
+    }
+  }
 #pragma unroll
   for (int jb = 0; jb < NB; jb += 4) {
+    const int q = jb / RW, o = jb % RW;     // owning wave, its first row of the block
+    const bool others = NB > RW * (q + 1);  // rows below in later waves
+    const bool odd = (jb / 4) & 1;
+    double* bl = s_lds + (odd ? kLdsTau : kLdsRow);        // bl[64 k + lane] = row jb + k
+    double* bt = s_lds + kLdsSgn + (odd ? 128 : 0);        // bt[4 i + k] = R(jb + k, i)
+    if (w == q) {
 #pragma unroll
-    for (int j = jb; j < jb + 4; ++j) {
-      const double d = read_lane(v[j], j);
-      ok = ok && (j >= n || d > thr2);
-      v[j] *= rsqrt_pos<NEWTON>(d);
+      for (int j = 0; j < 4; ++j) {
+        const double d = read_lane(v[o + j], jb + j);
+        ok = ok && (jb + j >= n || d > thr2);
+        v[o + j] *= rsqrt_pos<NEWTON>(d);
 #pragma unroll
-      for (int i = j + 1; i < jb + 4; ++i) v[i] = fma(-read_lane(v[j], i), v[j], v[i]);
+        for (int i = j + 1; i < 4; ++i) v[o + i] = fma(-read_lane(v[o + j], jb + i), v[o + j], v[o + i]);
+      }
+      if (others) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) bl[64 * k + lane] = v[o + k];
+        if (!xh) {
+          double2* t = reinterpret_cast<double2*>(bt + 4 * lane);
+          t[0] = make_double2(v[o], v[o + 1]);
+          t[1] = make_double2(v[o + 2], v[o + 3]);
+        }
+      }
+      // this wave's own rows below the block
+#pragma unroll
+      for (int i = o + 4; i < RW; ++i) {
+        if (RW * q + i < NB) {
+          const double r0 = read_lane(v[o], RW * q + i), r1 = read_lane(v[o + 1], RW * q + i);
+          const double r2 = read_lane(v[o + 2], RW * q + i), r3 = read_lane(v[o + 3], RW * q + i);
+          v[i] = fma(-r0, v[o], v[i]);
+          v[i] = fma(-r1, v[o + 1], v[i]);
+          v[i] = fma(-r2, v[o + 2], v[i]);
+          v[i] = fma(-r3, v[o + 3], v[i]);
+        }
+      }
     }
-    // rows below the block: R(jb..jb+3, i) lives in lane i; it reaches every
-    // lane through scalar registers (no memory round trip on the chain)
+    if (others) {
+      __syncthreads();
+      if (w > q && w < NB / RW) {
+        const double l0 = bl[lane], l1 = bl[64 + lane], l2 = bl[128 + lane], l3 = bl[192 + lane];
 #pragma unroll
-    for (int i = jb + 4; i < NB; ++i) {
-      const double r0 = read_lane(v[jb], i), r1 = read_lane(v[jb + 1], i);
-      const double r2 = read_lane(v[jb + 2], i), r3 = read_lane(v[jb + 3], i);
-      v[i] = fma(-r0, v[jb], v[i]);
-      v[i] = fma(-r1, v[jb + 1], v[i]);
-      v[i] = fma(-r2, v[jb + 2], v[i]);
-      v[i] = fma(-r3, v[jb + 3], v[i]);
+        for (int r = 0; r < RW; ++r) {
+          const double2* t = reinterpret_cast<const double2*>(bt + 4 * (RW * w + r));
+          const double2 a01 = t[0], a23 = t[1];
+          v[r] = fma(-a01.x, l0, v[r]);
+          v[r] = fma(-a01.y, l1, v[r]);
+          v[r] = fma(-a23.x, l2, v[r]);
+          v[r] = fma(-a23.y, l3, v[r]);
+        }
+      }
     }
   }
+  if (w < 4) {
 #pragma unroll
-  for (int i = 0; i < 32; ++i) {
-    double* dst = xh ? Ri + c + 33 * i : R + i + 32 * c;
-    *dst = (xh || i <= c) ? v[i] : 0.0;
+    for (int r = 0; r < RW; ++r) {
+      const int i = RW * w + r;
+      double* dst = xh ? Ri + c + 33 * i : R + i + 32 * c;
+      *dst = (xh || i <= c) ? v[r] : 0.0;
+    }
+    if (lane == 0) okw[w] = ok ? 1 : 0;
   }
-  return ok;
+  __syncthreads();
+  return (okw[0] & okw[1] & okw[2] & okw[3]) != 0;
 }
 
 // The factorisation stops after the leading NB columns when n <= NB: beyond
 // n, W is the identity, whose columns no elimination step changes.
 template <int NEWTON>
-__device__ __forceinline__ bool chol_inv32(const double* W, double* R, double* Ri, double* rowbuf, double thr2,
-                                           int n) {
-  if (n <= 8) return chol_inv<8, NEWTON>(W, R, Ri, rowbuf, thr2, n);
-  return chol_inv<32, NEWTON>(W, R, Ri, rowbuf, thr2, n);
+__device__ __forceinline__ bool chol_inv32(const double* W, double* R, double* Ri, double thr2, int n) {
+  if (n <= 8) return chol_inv<8, NEWTON>(W, R, Ri, thr2, n);
+  return chol_inv<32, NEWTON>(W, R, Ri, thr2, n);
 }
 
 // ------------------------------------------------------------------ QR
@@ -1181,7 +1232,6 @@ __device__ __forceinline__ bool cholqr2_reg(const Qr& q) {
   double* W = s_lds + kLdsW;
   double* R1 = s_lds + kLdsR1;
   double* Ri = s_lds + kLdsRi;
-  double* rowbuf = s_lds + kLdsRow;
   double* red = s_lds + kLdsRed;
   int* flag = reinterpret_cast<int*>(s_lds + kLdsFlag);
   constexpr int ldq = 513;
@@ -1208,15 +1258,12 @@ __device__ __forceinline__ bool cholqr2_reg(const Qr& q) {
     if (i >= n || j >= n) W[i + 32 * j] = (i == j) ? 1.0 : 0.0;
   }
   __syncthreads();
-  if (tid < 64) {  // one wave: the trace of W (= ||M||_F^2) and the factor
+  {  // the trace of W (= ||M||_F^2) and the factor
     double fro2 = 0.0;
 #pragma unroll 4
     for (int i = 0; i < n; ++i) fro2 += W[i * 33];
-    const bool ok = chol_inv32<1>(W, R1, Ri, rowbuf, kCholRel * kCholRel * fro2, n);
-    if (tid == 0) flag[0] = ok ? 1 : 0;
+    if (!chol_inv32<1>(W, R1, Ri, kCholRel * kCholRel * fro2, n)) return false;
   }
-  __syncthreads();
-  if (!flag[0]) return false;
 
   // Q1 = M R1^-1: column fragments of M (from the first read), result in
   // row-fragment order: block (t, cb) element v is Q1(r0 + 16t + 4v + l/16, 16cb + l%16)
@@ -1263,12 +1310,7 @@ __device__ __forceinline__ bool cholqr2_reg(const Qr& q) {
   } else {
     if (i >= n || j >= n) W[i + 32 * j] = (i == j) ? 1.0 : 0.0;
     __syncthreads();
-    if (tid < 64) {
-      const bool ok = chol_inv32<2>(W, W, Ri, rowbuf, 0.25, n);
-      if (tid == 0) flag[0] = ok ? 1 : 0;
-    }
-    __syncthreads();
-    if (!flag[0]) return false;
+    if (!chol_inv32<2>(W, W, Ri, 0.25, n)) return false;
   }
   // Q = Q1 R2^-1: Q1 goes through LDS to become column fragments
 #pragma unroll
@@ -1557,7 +1599,6 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
   double* W = s_lds + kLdsW;
   double* R1 = s_lds + kLdsR1;
   double* Ri = s_lds + kLdsRi;
-  double* rowbuf = s_lds + kLdsRow;
   double* red = s_lds + kLdsRed;
   int* flag = reinterpret_cast<int*>(s_lds + kLdsFlag);
   double* Q1 = q.aux;  // m x n column-major
@@ -1605,15 +1646,12 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
   }
   pad_identity();
   __syncthreads();
-  if (tid < 64) {  // one wave: the trace of W (= ||M||_F^2) and the factor
+  {  // the trace of W (= ||M||_F^2) and the factor
     double fro2 = 0.0;
 #pragma unroll 4
     for (int i = 0; i < n; ++i) fro2 += W[i * 33];
-    const bool ok = chol_inv32<1>(W, R1, Ri, rowbuf, kCholRel * kCholRel * fro2, n);
-    if (tid == 0) flag[0] = ok ? 1 : 0;
+    if (!chol_inv32<1>(W, R1, Ri, kCholRel * kCholRel * fro2, n)) return false;
   }
-  __syncthreads();
-  if (!flag[0]) return false;
 
   // pass B
   {
@@ -1644,12 +1682,7 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
     } else {
       pad_identity();
       __syncthreads();
-      if (tid < 64) {
-        const bool ok = chol_inv32<2>(W, W, Ri, rowbuf, 0.25, n);
-        if (tid == 0) flag[0] = ok ? 1 : 0;
-      }
-      __syncthreads();
-      if (!flag[0]) return false;
+      if (!chol_inv32<2>(W, W, Ri, 0.25, n)) return false;
     }
   }
 
@@ -2038,12 +2071,7 @@ __device__ __forceinline__ bool capped_completion_closed(const Qr& q) {
     G[i + 32 * j] = v;
   }
   __syncthreads();
-  if (tid < 64) {
-    const bool ok = chol_inv32<2>(G, R, Ri, s_lds + kLdsRow, 0.25, nc);
-    if (tid == 0) flag[0] = ok ? 1 : 0;
-  }
-  __syncthreads();
-  if (!flag[0]) return false;
+  if (!chol_inv32<2>(G, R, Ri, 0.25, nc)) return false;
   {
     const int k = tid & 31, jc = tid >> 5;
     double v = 0.0;
@@ -2189,12 +2217,8 @@ __device__ __forceinline__ void exec_op(const ChainOp& op) {
                                          : (i == j ? 1.0 : 0.0);
       }
       __syncthreads();
-      if (tid < 64) {
-        const bool ok = chol_inv32<2>(s_lds + kLdsW, s_lds + kLdsR1, s_lds + kLdsRi, s_lds + kLdsRow, 0.0, n);
-        if (tid == 0) flag[0] = ok ? 1 : 0;
-      }
-      __syncthreads();
-      if (!flag[0] && tid == 0) *op.flag = 1;
+      const bool ok = chol_inv32<2>(s_lds + kLdsW, s_lds + kLdsR1, s_lds + kLdsRi, 0.0, n);
+      if (!ok && tid == 0) *op.flag = 1;
       const View Riv{kLdsRi, 1, 33}, RiTv{kLdsRi, 33, 1};
       gemm_lds(n, n, 8, Riv, RiTv, [&](int ii, int jj, double v) { op.c[ii + n * jj] = v; });
       __syncthreads();
