@@ -883,6 +883,32 @@ __device__ __forceinline__ bool chol_inv32(const double* W, double* R, double* R
   return chol_inv<32, NEWTON>(W, R, Ri, thr2, n);
 }
 
+// R = R2 R1 for the upper triangular 32 x 32 factors of CholeskyQR2 in LDS
+// (R2 in W, then R1; column-major, leading dimension 32, zeros below the
+// diagonal, the identity beyond n), written to the n x n matrix R (leading
+// dimension n).  The blocks (0,0), (0,1) and (1,1) go to the matrix cores,
+// one wave each, over the k range in which neither triangle vanishes; wave
+// 3 writes the zero block (1,0).  Every thread calls it; the caller's
+// barrier publishes R.
+__device__ __forceinline__ void upper_product(const double* W, const double* R1, int n, double* R) {
+  const int tid = tix(), lane = tid & 63, li = lane & 15, lk = lane >> 4;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  if (wv >= 4) return;
+  const int bi = wv >= 2 ? 1 : 0, bj = (wv == 1 || wv == 2) ? 1 : 0;
+  const int k0 = wv == 2 ? 4 : 0, k1 = wv == 0 ? 4 : (wv == 3 ? 0 : 8);
+  v4d acc = {0.0, 0.0, 0.0, 0.0};
+  for (int kc = k0; kc < k1; ++kc) {
+    const double a = W[(16 * bi + li) + 32 * (4 * kc + lk)];
+    const double b = R1[(4 * kc + lk) + 32 * (16 * bj + li)];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = 16 * bi + 4 * v + lk, col = 16 * bj + li;
+    if (row < n && col < n) R[row + n * col] = acc[v];
+  }
+}
+
 // ------------------------------------------------------------------ QR
 
 struct Qr {
@@ -1362,15 +1388,7 @@ __device__ __forceinline__ bool cholqr2_reg(const Qr& q) {
       }
     }
   }
-  if (q.R) {
-    // R = R2 R1, both upper triangular: one element per thread, k in order
-    const int ii = tid & 31, jj = tid >> 5;
-    if (ii < n && jj < n) {
-      double v = 0.0;
-      for (int k = ii; k <= jj; ++k) v = fma(W[ii + 32 * k], R1[k + 32 * jj], v);
-      q.R[ii + n * jj] = v;
-    }
-  }
+  if (q.R) upper_product(W, R1, n, q.R);
   __syncthreads();
   return true;
 }
@@ -1706,15 +1724,7 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
       finish(ga, st);
     }
   }
-  if (q.R) {
-    // R = R2 R1, both upper triangular: one element per thread, k in order
-    const int ii = tid & 31, jj = tid >> 5;
-    if (ii < n && jj < n) {
-      double v = 0.0;
-      for (int k = ii; k <= jj; ++k) v = fma(W[ii + 32 * k], R1[k + 32 * jj], v);
-      q.R[ii + n * jj] = v;
-    }
-  }
+  if (q.R) upper_product(W, R1, n, q.R);
   __syncthreads();
   return true;
 }
