@@ -1621,28 +1621,48 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
   int* flag = reinterpret_cast<int*>(s_lds + kLdsFlag);
   double* Q1 = q.aux;  // m x n column-major
 
-  auto load_rows = [&](const double* A, int ars, int acs, int st, double (&f)[8][2]) {
+  // A stripe's loads (unconditional, see stage(): entries outside the
+  // matrix read the nearest one inside) and, apart from them, the zeroing of
+  // those entries, so that the next stripe's loads go out before this one's
+  // arithmetic waits on its own
+  auto fetch_rows = [&](const double* A, int ars, int acs, int st, double (&f)[8][2]) {
+    const int r0 = kQrRows * st + 32 * w;
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb) {
+        const int row = min(r0 + 4 * s + lk, m - 1), col = min(16 * cb + li, n - 1);
+        f[s][cb] = A[(unsigned)(row * ars + col * acs)];
+      }
+  };
+  auto mask_rows = [&](int st, double (&f)[8][2]) {
     const int r0 = kQrRows * st + 32 * w;
 #pragma unroll
     for (int s = 0; s < 8; ++s)
 #pragma unroll
       for (int cb = 0; cb < 2; ++cb) {
         const int row = r0 + 4 * s + lk, col = 16 * cb + li;
-        const bool ok = row < m && col < n;  // unconditional loads (see stage())
-        f[s][cb] = A[ok ? (unsigned)(row * ars + col * acs) : 0u];
-        f[s][cb] = ok ? f[s][cb] : 0.0;
+        f[s][cb] = (row < m && col < n) ? f[s][cb] : 0.0;
       }
   };
-  auto load_cols = [&](const double* A, int ars, int acs, int st, double (&g)[2][8]) {
+  auto fetch_cols = [&](const double* A, int ars, int acs, int st, double (&g)[2][8]) {
+    const int r0 = kQrRows * st + 32 * w;
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+      for (int kc = 0; kc < 8; ++kc) {
+        const int row = min(r0 + 16 * t + li, m - 1), col = min(4 * kc + lk, n - 1);
+        g[t][kc] = A[(unsigned)(row * ars + col * acs)];
+      }
+  };
+  auto mask_cols = [&](int st, double (&g)[2][8]) {
     const int r0 = kQrRows * st + 32 * w;
 #pragma unroll
     for (int t = 0; t < 2; ++t)
 #pragma unroll
       for (int kc = 0; kc < 8; ++kc) {
         const int row = r0 + 16 * t + li, col = 4 * kc + lk;
-        const bool ok = row < m && col < n;
-        g[t][kc] = A[ok ? (unsigned)(row * ars + col * acs) : 0u];
-        g[t][kc] = ok ? g[t][kc] : 0.0;
+        g[t][kc] = (row < m && col < n) ? g[t][kc] : 0.0;
       }
   };
   auto pad_identity = [&]() {
@@ -1653,11 +1673,19 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
   // pass A
   {
     v4d g00 = {0.0, 0.0, 0.0, 0.0}, g10 = g00, g11 = g00;
-    double fa[8][2];
+    double fa[8][2], fb[8][2];
+    const int mrs = (int)q.mrs, mcs = (int)q.mcs;
+    fetch_rows(q.M, mrs, mcs, 0, fa);
 #pragma unroll 1
-    for (int st = 0; st < nst; ++st) {
-      load_rows(q.M, (int)q.mrs, (int)q.mcs, st, fa);
+    for (int st = 0; st < nst; st += 2) {  // two stripes in turn, the next one's loads in flight
+      if (st + 1 < nst) fetch_rows(q.M, mrs, mcs, st + 1, fb);
+      mask_rows(st, fa);
       gram_acc(fa, g00, g10, g11);
+      if (st + 2 < nst) fetch_rows(q.M, mrs, mcs, st + 2, fa);
+      if (st + 1 < nst) {
+        mask_rows(st + 1, fb);
+        gram_acc(fb, g00, g10, g11);
+      }
     }
     __syncthreads();
     gram_reduce(g00, g10, g11, part, W);
@@ -1680,9 +1708,11 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
       gram_acc(f, h00, h10, h11);
       store_stripe(f, part + 1024 * w, kQrRows * st + 32 * w, m, n, Q1, 1, m);
     };
+    const int mrs = (int)q.mrs, mcs = (int)q.mcs;
 #pragma unroll 1
     for (int st = 0; st < nst; ++st) {
-      load_cols(q.M, (int)q.mrs, (int)q.mcs, st, ga);
+      fetch_cols(q.M, mrs, mcs, st, ga);
+      mask_cols(st, ga);
       finish(ga, st);
     }
     __syncthreads();  // Ri is read above and rewritten below; Q1 complete
@@ -1718,10 +1748,18 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
           if (row < m && col < n) q.Q[row * q.qrs + col * q.qcs] = f[s][cb];
         }
     };
+    double gb[2][8];
+    fetch_cols(Q1, 1, m, 0, ga);
 #pragma unroll 1
-    for (int st = 0; st < nst; ++st) {
-      load_cols(Q1, 1, m, st, ga);
+    for (int st = 0; st < nst; st += 2) {
+      if (st + 1 < nst) fetch_cols(Q1, 1, m, st + 1, gb);
+      mask_cols(st, ga);
       finish(ga, st);
+      if (st + 2 < nst) fetch_cols(Q1, 1, m, st + 2, ga);
+      if (st + 1 < nst) {
+        mask_cols(st + 1, gb);
+        finish(gb, st + 1);
+      }
     }
   }
   if (q.R) upper_product(W, R1, n, q.R);
