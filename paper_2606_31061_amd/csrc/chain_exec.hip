@@ -1259,7 +1259,6 @@ __device__ __forceinline__ bool cholqr2_reg(const Qr& q) {
   double* R1 = s_lds + kLdsR1;
   double* Ri = s_lds + kLdsRi;
   double* red = s_lds + kLdsRed;
-  int* flag = reinterpret_cast<int*>(s_lds + kLdsFlag);
   constexpr int ldq = 513;
   // 32-bit offsets (chain_fits32): one address register per load and no
   // 64-bit multiplications
@@ -1618,7 +1617,6 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
   double* R1 = s_lds + kLdsR1;
   double* Ri = s_lds + kLdsRi;
   double* red = s_lds + kLdsRed;
-  int* flag = reinterpret_cast<int*>(s_lds + kLdsFlag);
   double* Q1 = q.aux;  // m x n column-major
 
   // A stripe's loads (unconditional, see stage(): entries outside the
@@ -2103,7 +2101,6 @@ __device__ __forceinline__ bool capped_completion_closed(const Qr& q) {
   double* R = s_lds + kLdsR1;
   double* Ri = s_lds + kLdsRi;    // R^-1, leading dimension 33
   double* Bs = s_lds + kLdsPart;  // Bs[k + 32 jc] = B(k, jc)
-  int* flag = reinterpret_cast<int*>(s_lds + kLdsFlag);
   {
     const int jc = tid & 31, k = tid >> 5;
     const bool ok = jc < nc && k < rho;
@@ -2255,7 +2252,6 @@ __device__ __forceinline__ void exec_op(const ChainOp& op) {
       // W = S + shift I (identity beyond m), R^-1 by chol_inv32, S^-1 = R^-1 R^-T
       const int n = (int)op.m;
       double* W = s_lds + kLdsW;
-      int* flag = reinterpret_cast<int*>(s_lds + kLdsFlag);
       double tr = 0.0;
       for (int i = 0; i < n; ++i) tr += op.a[i * op.ars + i * op.acs];
       const double shift = op.tol * tr / n;
