@@ -111,7 +111,10 @@ QR_CASES = [(8, 8, None), (72, 32, None), (480, 32, None), (512, 32, None), (96,
             (513, 32, None), (7328, 32, None), (2049, 33, None), (4096, 32, 5), (1000, 1, None),
             (700, 48, None), (1500, 40, 7), (66, 40, None),
             # more than 64 columns: the reflector bit masks span several words
-            (600, 100, None), (300, 130, 20), (160, 70, 66)]
+            (600, 100, None), (300, 130, 20), (160, 70, 66),
+            # the first failing Cholesky pivot in the rows of the second, third and last of the
+            # factorisation's four waves (and in the streamed path): the fallback must still run
+            (72, 32, 12), (480, 32, 20), (512, 32, 28), (2000, 32, 17)]
 
 
 @pytest.mark.parametrize("m,n,rank", QR_CASES)
