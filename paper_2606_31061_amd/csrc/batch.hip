@@ -51,6 +51,13 @@ struct MemberPhase {
   std::vector<int> wides;
 };
 
+// A stream of the batch's own beside its HIP stream, and the events that fork
+// a run of launches onto it and join them back.
+struct SideStream {
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
 struct Wave {
   std::vector<tt_stream*> members;
   std::vector<std::array<MemberPhase, 3>> phases;
@@ -332,17 +339,42 @@ void wave_fill(const Wave& w, char* h, const void* const* slices) {
   }
 }
 
-// Enqueues the descriptor upload from host buffer h and every launch.
-tt_status wave_enqueue(const Wave& w, hipStream_t st, char* dev, const char* h, tt_dtype dtype) {
+// Enqueues the descriptor upload from host buffer h and every launch.  With
+// a side stream, a run of slice-pass launches (one per pass plan, different
+// members, so independent) forks when it holds launches of fewer than
+// kNarrowBlocks blocks, which leave most of the GPU idle: those go to the side
+// stream and run beside the wider ones, and the run joins before the next
+// chain launch.  Under graph capture the fork and join become edges of the
+// graph.  Which stream a launch takes changes no result.
+constexpr int64_t kNarrowBlocks = 256;
+tt_status wave_enqueue(const Wave& w, hipStream_t st, char* dev, const char* h, tt_dtype dtype, const SideStream* side) {
   const int n = (int)w.members.size();
   TT_HIP_RT(hipMemcpyAsync(dev, h, w.bytes, hipMemcpyHostToDevice, st));
-  for (const WaveLaunch& L : w.launches) {
+  const auto is_pass = [](const WaveLaunch& L) { return L.kind == kWlPass1 || L.kind == kWlPass2; };
+  const auto narrow = [](const WaveLaunch& L) { return L.gx * (int64_t)L.members.size() < kNarrowBlocks; };
+  const size_t nl = w.launches.size();
+  hipStream_t run_side = nullptr;  // the side stream while a forked run lasts
+  size_t run_end = 0;
+  for (size_t li = 0; li < nl; ++li) {
+    const WaveLaunch& L = w.launches[li];
+    if (side && is_pass(L) && li >= run_end) {
+      size_t e = li;
+      int nn = 0;
+      while (e < nl && w.launches[e].kind == L.kind) nn += narrow(w.launches[e++]) ? 1 : 0;
+      run_end = e;
+      if (nn > 0 && e - li >= 2) {
+        TT_HIP_RT(hipEventRecord(side->fork, st));
+        TT_HIP_RT(hipStreamWaitEvent(side->stream, side->fork, 0));
+        run_side = side->stream;
+      }
+    }
+    hipStream_t ls = (run_side && narrow(L)) ? run_side : st;
     char* p = dev + L.off;
     const int k = (int)L.members.size();
     if (L.kind == kWlChain) {
-      TT_HIP_RT(chain_run(st, reinterpret_cast<const ChainSeg*>(p), n));
+      TT_HIP_RT(chain_run(ls, reinterpret_cast<const ChainSeg*>(p), n));
     } else if (L.kind == kWlWide) {
-      TT_HIP_RT(gemm64_ops(st, reinterpret_cast<const ChainOp* const*>(p), k, L.gx));
+      TT_HIP_RT(gemm64_ops(ls, reinterpret_cast<const ChainOp* const*>(p), k, L.gx));
     } else {
       const tt_stream* s = w.members[L.rep];
       const int ks = s->kstar;
@@ -351,15 +383,20 @@ tt_status wave_enqueue(const Wave& w, hipStream_t st, char* dev, const char* h, 
       const int r = (int)s->r[ks];
       if (L.kind == kWlPass1) {
         if (s->compute == TT_BF16)
-          TT_HIP_RT(pass1_bf16(st, nullptr, dtype, s->p1b, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
+          TT_HIP_RT(pass1_bf16(ls, nullptr, dtype, s->p1b, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
         else
-          TT_HIP_RT(pass1(st, nullptr, dtype, s->p1, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
+          TT_HIP_RT(pass1(ls, nullptr, dtype, s->p1, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
       } else {
         if (s->compute == TT_BF16)
-          TT_HIP_RT(pass2_bf16(st, nullptr, dtype, s->p2b, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
+          TT_HIP_RT(pass2_bf16(ls, nullptr, dtype, s->p2b, P, J, r, nullptr, nullptr, nullptr, nullptr, &bl));
         else
-          TT_HIP_RT(pass2(st, nullptr, dtype, P, J, r, nullptr, nullptr, nullptr, &bl));
+          TT_HIP_RT(pass2(ls, nullptr, dtype, P, J, r, nullptr, nullptr, nullptr, &bl));
       }
+    }
+    if (run_side && li + 1 == run_end) {  // join the run
+      TT_HIP_RT(hipEventRecord(side->join, run_side));
+      TT_HIP_RT(hipStreamWaitEvent(st, side->join, 0));
+      run_side = nullptr;
     }
   }
   return TT_OK;
@@ -408,6 +445,7 @@ constexpr int kBatchSlots = 8;
 struct tt_batch {
   uint64_t magic = kBatchMagic;
   hipStream_t stream = nullptr;
+  ttk::SideStream side;  // narrow slice-pass launches run here, beside the rest
   ttk::Wave wave;
   int n_groups = 0;  // distinct update structures (informational)
   char* dev = nullptr;
@@ -436,6 +474,10 @@ void batch_drop_graphs(tt_batch* b) {
 
 void batch_release(tt_batch* b) {
   batch_drop_graphs(b);
+  if (b->side.stream) (void)hipStreamDestroy(b->side.stream);
+  if (b->side.fork) (void)hipEventDestroy(b->side.fork);
+  if (b->side.join) (void)hipEventDestroy(b->side.join);
+  b->side = ttk::SideStream{};
   if (b->dev) (void)hipFree(b->dev);
   b->dev = nullptr;
   for (int k = 0; k < kBatchSlots; ++k) {
@@ -488,6 +530,14 @@ tt_status tt_batch_create(tt_stream* const* streams, int32_t n, void* hip_stream
     return fail_msg(TT_ERR_OOM, "batch descriptor allocation failed");
   }
   b->dev = static_cast<char*>(d);
+  if (hipStreamCreateWithFlags(&b->side.stream, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->side.fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->side.join, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    batch_release(b);
+    delete b;
+    return fail_msg(TT_ERR_DEVICE, "batch side stream creation failed");
+  }
   for (int q = 0; q < kBatchSlots; ++q) {
     void* h = nullptr;
     if (hipHostMalloc(&h, b->wave.bytes, hipHostMallocDefault) != hipSuccess ||
@@ -523,7 +573,7 @@ tt_status tt_batch_push(tt_batch* b, const void* const* slices, tt_dtype dtype) 
   if (b->use_graph && !b->graph[q]) {
     hipGraph_t g = nullptr;
     TT_HIP_RT(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    const tt_status st = ttk::wave_enqueue(b->wave, b->stream, b->dev, h, dtype);
+    const tt_status st = ttk::wave_enqueue(b->wave, b->stream, b->dev, h, dtype, &b->side);
     const hipError_t e = hipStreamEndCapture(b->stream, &g);
     if (st != TT_OK) {
       if (g) (void)hipGraphDestroy(g);
@@ -538,7 +588,7 @@ tt_status tt_batch_push(tt_batch* b, const void* const* slices, tt_dtype dtype) 
   if (b->use_graph) {
     TT_HIP_RT(hipGraphLaunch(b->graph[q], b->stream));
   } else {
-    const tt_status st = ttk::wave_enqueue(b->wave, b->stream, b->dev, h, dtype);
+    const tt_status st = ttk::wave_enqueue(b->wave, b->stream, b->dev, h, dtype, &b->side);
     if (st != TT_OK) return st;
   }
   TT_HIP_RT(hipEventRecord(b->done[q], b->stream));
@@ -759,7 +809,7 @@ tt_status lane_launch(tt_server* sv, Lane& L) {
     L.rej_cap = cap;
   }
   ttk::wave_fill(L.wave, L.host, slices.data());
-  tt_status st = ttk::wave_enqueue(L.wave, L.stream, L.dev, L.host, dt);
+  tt_status st = ttk::wave_enqueue(L.wave, L.stream, L.dev, L.host, dt, nullptr);
   if (st != TT_OK) return st;
   for (size_t k = 0; k < pick.size(); ++k)
     TT_HIP_RT(hipMemcpyAsync(L.rej_host + k, L.wave.members[k]->rejected, sizeof(int), hipMemcpyDeviceToHost,
