@@ -1663,6 +1663,31 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
         g[t][kc] = (row < m && col < n) ? g[t][kc] : 0.0;
       }
   };
+  // A stripe read along M's contiguous index (lanes as in load_tile, the
+  // addresses of entries outside the matrix clamped), then, once its loads
+  // have landed, written to the wave's LDS tile with those entries zeroed:
+  // for the one of passes A and B whose fragments, read straight from M,
+  // would take 32 bytes of each of 16 cache lines per load
+  auto fetch_tile = [&](const double* A, int ars, int acs, int st, double (&x)[16]) {
+    const int a = lane & 31, h = lane >> 5, r0 = kQrRows * st + 32 * w;
+    const bool rows = ars <= acs;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int r = rows ? a : 2 * k + h, c = rows ? 2 * k + h : a;
+      const int row = min(r0 + r, m - 1), col = min(c, n - 1);
+      x[k] = A[(unsigned)(row * ars + col * acs)];
+    }
+  };
+  auto put_tile = [&](int st, int ars, int acs, const double (&x)[16], double* tile) {
+    const int a = lane & 31, h = lane >> 5, r0 = kQrRows * st + 32 * w;
+    const bool rows = ars <= acs;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) {
+      const int r = rows ? a : 2 * k + h, c = rows ? 2 * k + h : a;
+      tile[32 * r + (c ^ r)] = (r0 + r < m && c < n) ? x[k] : 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+  };
   auto pad_identity = [&]() {
     const int i = tid & 31, j = tid >> 5;
     if (i >= n || j >= n) W[i + 32 * j] = (i == j) ? 1.0 : 0.0;
@@ -1671,18 +1696,31 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
   // pass A
   {
     v4d g00 = {0.0, 0.0, 0.0, 0.0}, g10 = g00, g11 = g00;
-    double fa[8][2], fb[8][2];
     const int mrs = (int)q.mrs, mcs = (int)q.mcs;
-    fetch_rows(q.M, mrs, mcs, 0, fa);
+    if (mrs <= mcs) {  // row fragments straight from a column-major M would be scattered
+      double x[16], f[8][2];
+      double* tile = part + 1024 * w;
+      fetch_tile(q.M, mrs, mcs, 0, x);
 #pragma unroll 1
-    for (int st = 0; st < nst; st += 2) {  // two stripes in turn, the next one's loads in flight
-      if (st + 1 < nst) fetch_rows(q.M, mrs, mcs, st + 1, fb);
-      mask_rows(st, fa);
-      gram_acc(fa, g00, g10, g11);
-      if (st + 2 < nst) fetch_rows(q.M, mrs, mcs, st + 2, fa);
-      if (st + 1 < nst) {
-        mask_rows(st + 1, fb);
-        gram_acc(fb, g00, g10, g11);
+      for (int st = 0; st < nst; ++st) {
+        put_tile(st, mrs, mcs, x, tile);
+        if (st + 1 < nst) fetch_tile(q.M, mrs, mcs, st + 1, x);  // in flight during the Gram
+        tile_rows(tile, f);
+        gram_acc(f, g00, g10, g11);
+      }
+    } else {
+      double fa[8][2], fb[8][2];
+      fetch_rows(q.M, mrs, mcs, 0, fa);
+#pragma unroll 1
+      for (int st = 0; st < nst; st += 2) {  // two stripes in turn, the next one's loads in flight
+        if (st + 1 < nst) fetch_rows(q.M, mrs, mcs, st + 1, fb);
+        mask_rows(st, fa);
+        gram_acc(fa, g00, g10, g11);
+        if (st + 2 < nst) fetch_rows(q.M, mrs, mcs, st + 2, fa);
+        if (st + 1 < nst) {
+          mask_rows(st + 1, fb);
+          gram_acc(fb, g00, g10, g11);
+        }
       }
     }
     __syncthreads();
@@ -1707,11 +1745,23 @@ __device__ __forceinline__ bool cholqr2_tall(const Qr& q) {
       store_stripe(f, part + 1024 * w, kQrRows * st + 32 * w, m, n, Q1, 1, m);
     };
     const int mrs = (int)q.mrs, mcs = (int)q.mcs;
+    if (mrs > mcs) {  // column fragments straight from a row-major M would be scattered
+      double* tile = part + 1024 * w;
 #pragma unroll 1
-    for (int st = 0; st < nst; ++st) {
-      fetch_cols(q.M, mrs, mcs, st, ga);
-      mask_cols(st, ga);
-      finish(ga, st);
+      for (int st = 0; st < nst; ++st) {
+        double x[16];
+        fetch_tile(q.M, mrs, mcs, st, x);
+        put_tile(st, mrs, mcs, x, tile);
+        tile_cols(tile, ga);
+        finish(ga, st);  // its stores stage through the same tile, after the reads above
+      }
+    } else {
+#pragma unroll 1
+      for (int st = 0; st < nst; ++st) {
+        fetch_cols(q.M, mrs, mcs, st, ga);
+        mask_cols(st, ga);
+        finish(ga, st);
+      }
     }
     __syncthreads();  // Ri is read above and rewritten below; Q1 complete
     gram_reduce(h00, h10, h11, part, W);
