@@ -242,3 +242,26 @@ def test_wave_plan_streams_are_bitwise_equal_alone_and_batched():
     batch.close()
     for s in (a, b1, b2):
         s.close()
+
+
+def test_wave_plan_large_products_match_the_oracle():
+    """A stream planned for batched waves whose right interface and tail
+    contraction are 7,328 x 77 x 32 products (whole-GPU products with four
+    outputs per thread) agrees with the oracle slice by slice, as the default
+    plan does."""
+    torch = torch_cuda()
+    from paper_2606_31061_amd import TTStream
+    modes, ranks = (40, 229, 77), (32, 32, 32)
+    st = exact_tt_stream(modes, ranks, ranks, 6, 11, 12, sigma=1e-2)
+    init = st.init()
+    slices = list(st.frames(1, 6))
+    ref = ttals.run_stream(slices, init[0], init[1], keep_M=True)
+    for wave_plan in (False, True):
+        say(f"large products: wave_plan={wave_plan}")
+        s = TTStream(modes, ranks, init=init, split_point=1, wave_plan=wave_plan)
+        worst = 0.0
+        for X, info in zip(slices, ref.infos):
+            s.push(to_device_slice(torch, X))
+            worst = max(worst, rel(s.reconstruct(), info.M, np.linalg.norm(X)))
+        s.close()
+        assert worst <= M_TOL, (wave_plan, worst)
