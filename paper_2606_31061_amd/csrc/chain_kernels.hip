@@ -10,14 +10,20 @@
 namespace ttk {
 namespace {
 
-// Depth groups of a wide product: a power of two from 1 to 16 with about 16
-// or more multiply-adds per group (a function of K only, the same on host
-// and device).  A block of kWideThreads threads owns kWideThreads / groups
-// consecutive outputs.
+// Depth groups of a wide product: a power of two with about 16 or more
+// multiply-adds per group, up to 16, and up to 64 while the product's
+// outputs times groups stay within 1024 blocks (deep products with few
+// outputs, which would otherwise leave most of the GPU idle); a function of
+// the product's shape only, the same on host and device.  A block of
+// kWideThreads threads owns kWideThreads / groups consecutive outputs.
 constexpr int kWideThreads = 256;
-__host__ __device__ inline int depth_groups(int64_t K) {
+__host__ __device__ inline int depth_groups(int64_t K, int64_t nout) {
   int g = 1;
   while (g < 16 && (int64_t)g * 32 <= K) g <<= 1;
+  while (g == 16 || g == 32) {
+    if ((int64_t)(2 * g) * 32 > K || nout * 2 * g > (int64_t)1024 * kWideThreads) break;
+    g <<= 1;
+  }
   return g;
 }
 
@@ -57,7 +63,7 @@ __device__ __forceinline__ void wide_gemm_jb4(int64_t M, int64_t N, int64_t K, c
                                               int64_t crs, int64_t ccs, float* C32) {
   constexpr int JB = 4;
   __shared__ double red4[JB * kWideThreads];
-  const int G = depth_groups(K), lg = __builtin_ctz(G), OB = kWideThreads >> lg, lob = __builtin_ctz(OB);
+  const int G = depth_groups(K, M * N), lg = __builtin_ctz(G), OB = kWideThreads >> lg, lob = __builtin_ctz(OB);
   const int64_t NJ = (N + JB - 1) / JB;
   const int64_t nout = M * NJ;
   const int64_t base = (int64_t)blockIdx.x * OB;
@@ -134,7 +140,7 @@ __device__ __forceinline__ void wide_gemm(int64_t M, int64_t N, int64_t K, const
   }
   __shared__ double red[kWideThreads];
   // G and OB are powers of two: shifts and masks instead of divisions
-  const int G = depth_groups(K), lg = __builtin_ctz(G), OB = kWideThreads >> lg, lob = __builtin_ctz(OB);
+  const int G = depth_groups(K, M * N), lg = __builtin_ctz(G), OB = kWideThreads >> lg, lob = __builtin_ctz(OB);
   const int64_t nout = M * N;
   const int64_t base = (int64_t)blockIdx.x * OB;
   if (base >= nout) return;
@@ -227,7 +233,7 @@ inline unsigned grid_for(int64_t work, int threads, int64_t cap = 65536) {
 int64_t gemm64_blocks(int64_t M, int64_t N, int64_t K, int64_t ars, int64_t acs, int64_t brs, int64_t bcs,
                       bool jb4) {
   if (M <= 0 || N <= 0) return 0;
-  const int64_t ob = kWideThreads / depth_groups(K);
+  const int64_t ob = kWideThreads / depth_groups(K, M * N);
   const int jb = wide_jb(N, ars, acs, brs, bcs, jb4);
   return (M * ((N + jb - 1) / jb) + ob - 1) / ob;
 }
