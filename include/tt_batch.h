@@ -8,7 +8,10 @@
  * slot w of every member's phase in one launch (chain segment w with one
  * workgroup per member, then product w of the members that have one); each
  * pass runs as one launch per kernel template shape over the members of that
- * shape.  Members may differ in order, mode sizes, ranks, split point and
+ * shape; the pass launches of fewer than 256 blocks run on a HIP stream the
+ * batch creates for itself (default priority, non-blocking), forked from and
+ * joined back to hip_stream by events within each push, so that they run
+ * beside the wider ones.  Members may differ in order, mode sizes, ranks, split point and
  * contraction precision.  Every member is computed exactly as when pushed
  * alone (same kernels, launch shapes and arithmetic order), so its results
  * are bitwise the same.
@@ -28,9 +31,11 @@ extern "C" {
 
 typedef struct tt_batch tt_batch;
 
-/* Groups n >= 1 distinct streams.  Errors: INVALID_ARG (null, n < 1,
- * duplicates, a stream created on another HIP stream or device, a stream
- * created with TT_FLAG_PROFILE_OPS), OOM, DEVICE. */
+/* Groups n >= 1 distinct streams; creates the batch's own side stream and
+ * its two events (released by tt_batch_destroy).  Errors: INVALID_ARG (null,
+ * n < 1, duplicates, a stream created on another HIP stream or device, a
+ * stream created with TT_FLAG_PROFILE_OPS), OOM, DEVICE (also when the side
+ * stream or its events cannot be created). */
 tt_status tt_batch_create(tt_stream* const* streams, int32_t n, void* hip_stream, tt_batch** out);
 
 /* One update of every member: slices[i] is member i's next slice, a device
